@@ -1,0 +1,101 @@
+"""Dense tier: naive DFT matrices and the assembled saddle system.
+
+Used only on grids of at most a few hundred nodes, to check the FFT tier and
+to provide the direct solve x = A^{-1} b that Proposition 1 (well-posedness)
+guarantees is unique.  The DFT is written out as exp(-2 pi i j k / n), with no
+FFT library involved.
+"""
+
+import numpy as np
+
+from . import nodal
+from .grid import wavenumbers
+
+
+def dft_matrix(n):
+    """F[k, j] = exp(-2 pi i k j / n): the naive n-point DFT."""
+    j = np.arange(n)
+    return np.exp(-2j * np.pi * np.outer(j, j) / n)
+
+
+def grid_dft(g):
+    """DFT over the node index x + nx (y + ny z): kron(Fz, Fy, Fx)."""
+    return np.kron(dft_matrix(g.nz), np.kron(dft_matrix(g.ny), dft_matrix(g.nx)))
+
+
+def neg_laplacian_matrix(g):
+    """D = F^{-1} diag(|xi|^2) F, real symmetric (N_g x N_g)."""
+    F = grid_dft(g)
+    # |xi|^2 listed in the same (kz, ky, kx) C order as the rows of F
+    kz = 2 * np.pi * wavenumbers(g.nz) / g.lengths[0] if g.nz > 1 else np.zeros(1)
+    ky = 2 * np.pi * wavenumbers(g.ny) / g.lengths[1]
+    kx = 2 * np.pi * wavenumbers(g.nx) / g.lengths[2]
+    s = (kz[:, None, None] ** 2 + ky[None, :, None] ** 2 + kx[None, None, :] ** 2).ravel()
+    D = (np.conj(F).T @ (s[:, None] * F)) / g.ng
+    return D.real
+
+
+def block_indices(g):
+    n = g.ng
+    return [np.arange(c * n, (c + 1) * n) for c in range(4)]
+
+
+def saddle_parts(g, prm, m):
+    """Dense (calH, calS) of Sec. 3.1, eq. (HS), in the block order
+    (v1, v2, v3, r), each block N_g wide."""
+    n = g.ng
+    D = neg_laplacian_matrix(g)
+    Hb = prm.alpha * np.eye(n) + prm.h_coef * D
+    calH = np.zeros((4 * n, 4 * n))
+    for c in range(3):
+        calH[c * n:(c + 1) * n, c * n:(c + 1) * n] = Hb
+    calS = np.zeros((4 * n, 4 * n))
+    mf = m.reshape(3, n)
+    for i in range(n):
+        blk = nodal.s_tilde(mf[:, i])
+        rows = np.arange(4) * n + i
+        calS[np.ix_(rows, rows)] = blk
+    return calH, calS
+
+
+def saddle_matrix(g, prm, m):
+    calH, calS = saddle_parts(g, prm, m)
+    return calH + calS
+
+
+def hss_factors(g, prm, m):
+    """Dense M1 = calH + lambda I and M2 = calS + lambda I."""
+    calH, calS = saddle_parts(g, prm, m)
+    eye = np.eye(calH.shape[0])
+    return calH + prm.shift * eye, calS + prm.shift * eye
+
+
+def solve(g, prm, m, b):
+    """Direct solve of A x = b (b, x of shape (4, nz, ny, nx))."""
+    A = saddle_matrix(g, prm, m)
+    return np.linalg.solve(A, b.ravel()).reshape(b.shape)
+
+
+def midpoint_jacobian(g, prm, m_n, v, r):
+    """Dense Jacobian J of the midpoint residual with respect to (v, r),
+    assembled block by block from the dense -Delta_N and the nodal blocks
+    (theta = 1/2; see oracle.adjoint for the formula)."""
+    n = g.ng
+    k = prm.dt
+    D = neg_laplacian_matrix(g)
+    mn = m_n.reshape(3, n)
+    vv = v.reshape(3, n)
+    rr = np.asarray(r).reshape(n)
+    mh = mn + 0.5 * k * vv
+    mc = mh + 0.5 * k * vv
+    J = np.zeros((4 * n, 4 * n))
+    Hb = prm.alpha * np.eye(n) + 0.5 * k * prm.c_hat * D
+    for c in range(3):
+        J[c * n:(c + 1) * n, c * n:(c + 1) * n] = Hb + 0.5 * k * np.diag(rr)
+    for i in range(n):
+        L = nodal.lambda_matrix(mn[:, i])
+        rows = np.arange(3) * n + i
+        J[np.ix_(rows, rows)] += L
+        J[rows, 3 * n + i] = mh[:, i]
+        J[3 * n + i, rows] = -mc[:, i]
+    return J

@@ -1,0 +1,115 @@
+"""Pins of the oracle GMRES: the dense direct solve (Proposition 1 makes the
+solution unique), the uniform-state closed form derived from the tangent
+equation, the even-step residual bound of the Theorem "Full saddle two-step
+contraction", and the paper's iteration count for the smooth one-step system
+(Sec. 4.3, a soft pin)."""
+
+import json
+import os
+
+import numpy as np
+import pytest
+
+from oracle import dense, gmres, manufactured, nodal, operators, steppers, theory
+from oracle.grid import Grid
+from oracle.operators import Params
+
+GOLD = json.load(open(os.path.join(os.path.dirname(__file__), "golden", "paper_printed_values.json")))
+
+
+@pytest.mark.parametrize("shape,theta", [((1, 4, 4), 1.0), ((1, 8, 6), 0.5), ((4, 4, 4), 1.0)])
+def test_gmres_matches_dense_solve(shape, theta):
+    g = Grid(shape[2], shape[1], shape[0], h=1.0 / shape[2])
+    prm = Params(alpha=0.1, dt=5e-3, theta=theta, shift=0.5)
+    rng = np.random.default_rng(11)
+    m = rng.standard_normal((3,) + g.shape)
+    m /= np.sqrt(nodal.dot(m, m))
+    b = rng.standard_normal((4,) + g.shape)
+    xs = dense.solve(g, prm, m, b)
+    x, info = steppers.solve_saddle(g, prm, m, b, rtol=1e-14, restart=30)
+    assert info["converged"]
+    assert np.linalg.norm(x - xs) <= 1e-12 * np.linalg.norm(xs)
+
+
+@pytest.mark.parametrize("theta", [1.0, 0.5])
+def test_uniform_state_closed_form(theta):
+    """m = m0, h = h0 constant: v = alpha h_T - m0 x h_T, r = (1+alpha^2) m0.h0."""
+    g = Grid(8, 8, 4, h=1.0 / 8)
+    prm = Params(alpha=0.07, dt=1e-3, theta=theta, shift=0.5, h_uniform=(0.3, -0.2, 0.9))
+    m0 = np.array([0.48, -0.6, 0.64])
+    m0 = m0 / np.linalg.norm(m0)
+    m = np.broadcast_to(m0.reshape(3, 1, 1, 1), (3,) + g.shape).copy()
+    b = steppers.rhs(g, prm, m)
+    x, info = steppers.solve_saddle(g, prm, m, b, rtol=1e-14)
+    h0 = np.array(prm.h_uniform)
+    hT = h0 - (m0 @ h0) * m0
+    v_ref = prm.alpha * hT - np.cross(m0, hT)
+    r_ref = (1 + prm.alpha ** 2) * (m0 @ h0)
+    np.testing.assert_allclose(x[:3].reshape(3, -1), np.repeat(v_ref[:, None], g.ng, 1), atol=1e-13)
+    np.testing.assert_allclose(x[3], r_ref, atol=1e-13)
+
+
+def test_even_step_gmres_bound():
+    """||r_{2j}|| / ||r_0|| <= kappa vartheta_2^j for unrestarted GMRES
+    (unit magnetization, so kappa = 1)."""
+    g = Grid(8, 8, 1, lengths=(1.0, 2 * np.pi, 2 * np.pi))
+    prm = Params(alpha=0.2, dt=10.24 / 64, theta=1.0, shift=0.5)
+    rng = np.random.default_rng(5)
+    m = rng.standard_normal((3,) + g.shape)
+    m /= np.sqrt(nodal.dot(m, m))
+    b = np.zeros((4,) + g.shape)
+    b[:3] = rng.standard_normal((3,) + g.shape)
+    A = dense.saddle_matrix(g, prm, m)
+    M1, M2 = dense.hss_factors(g, prm, m)
+    P = np.linalg.solve(M2, np.linalg.solve(M1, A))
+    r0 = np.linalg.solve(M2, np.linalg.solve(M1, b.ravel()))
+    beta = theory.beta_n(prm.alpha, 1.0, prm.dt, prm.c_hat, g.max_symbol())
+    qh = theory.q_bar(0.5, prm.alpha, beta)
+    th2 = theory.vartheta2(qh, theory.gamma_m(0.5, 1.0))
+    # exact GMRES residuals: min over the Krylov space, via least squares
+    K = [r0 / np.linalg.norm(r0)]
+    for j in range(1, 2 * 8 + 1):
+        w = P @ K[-1]
+        for q in K:
+            w -= (q @ w) * q
+        for q in K:
+            w -= (q @ w) * q
+        K.append(w / np.linalg.norm(w))
+    Q = np.array(K).T
+    for jj in range(1, 9):
+        Qk = Q[:, :2 * jj]
+        PQ = P @ Qk
+        y, *_ = np.linalg.lstsq(PQ, r0, rcond=None)
+        res = np.linalg.norm(r0 - PQ @ y) / np.linalg.norm(r0)
+        assert res <= th2 ** jj * (1 + 1e-10)
+
+
+def test_smooth_rhs_iteration_count_soft():
+    """Sec. 4.3: one Euler system with the smooth manufactured right-hand side,
+    k = 1e-2, alpha = 0.2, lambda = 0.5, rtol 1e-8, GMRES(50): 11 iterations
+    in 2D.  Counts depend on the GMRES variant, so this is a +-2 pin."""
+    gold = GOLD["smooth_rhs_iterations"]
+    for n in (32, 64):
+        g = Grid(n, n, 1, lengths=(1.0, 2 * np.pi, 2 * np.pi))
+        prm = Params(alpha=0.2, dt=1e-2, theta=1.0, shift=0.5)
+        m, _ = manufactured.grid_fields(g, 0.0, prm.alpha)
+        _, F = manufactured.grid_fields(g, prm.dt, prm.alpha)
+        b = steppers.rhs(g, prm, m, forcing=F)
+        x, info = steppers.solve_saddle(g, prm, m, b, rtol=1e-8, restart=50)
+        assert info["converged"]
+        assert abs(info["iters"] - gold["split_2d"]) <= gold["soft_tolerance"], info["iters"]
+
+
+def test_fgmres_ir_matches_gmres():
+    g = Grid(16, 16, 1, h=1.0 / 16)
+    prm = Params(alpha=0.05, dt=10 / 256, theta=0.5, shift=0.5)
+    rng = np.random.default_rng(9)
+    m = rng.standard_normal((3,) + g.shape)
+    m /= np.sqrt(nodal.dot(m, m))
+    b = steppers.rhs(g, prm, m)
+    A = lambda x: operators.matvec(g, prm, m, x)
+    M = lambda x: operators.hss_apply(g, prm, m, x)
+    x1, i1 = gmres.gmres(A, M, b, rtol=1e-12)
+    x2, i2 = gmres.fgmres_ir(A, M, b, rtol=1e-12, inner_rtol=1e-4)
+    assert i1["converged"] and i2["converged"] and i2["outer_steps"] >= 2
+    assert np.linalg.norm(x2 - x1) <= 1e-10 * np.linalg.norm(x1)
