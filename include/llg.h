@@ -1,0 +1,204 @@
+/*
+ * llg.h -- C ABI of the MI355X library for periodic Landau-Lifshitz-Gilbert
+ * tangent-plane saddle-point systems with the matrix-free split FFT-HSS
+ * preconditioner (Qi, Ye, Guan, "Matrix-Free FFT-HSS Preconditioning for
+ * Periodic Landau-Lifshitz-Gilbert Saddle-Point Systems").
+ *
+ * Problem (Sec. 2.3-2.4): on a periodic grid of nx x ny x nz nodes with
+ * spacing h (cell lengths L = n h; nz = 1 is two-dimensional), a time step k
+ * solves the saddle-point system
+ *
+ *     A (v, r) = (f, 0),   A = [[H + S, B^T], [-B, 0]],
+ *     H = alpha I + theta k C_hat (-Delta_N),  S v = m x v,
+ *     B^T r = m r (node by node),  -B v = -m . v,  C_hat = (1 + alpha^2) cexc,
+ *
+ * for the velocity v and the Lagrange multiplier r (called "lam" below;
+ * the paper's lambda is the HSS shift, called "shift").  theta = 1 is the
+ * projected implicit Euler scheme, theta = 1/2 the midpoint scheme (Sec. 3.3).
+ *
+ * Data layout.  Every grid array is a contiguous, caller-owned DEVICE buffer
+ * of float64 (float32 for the *_f32 entry points) in structure-of-arrays
+ * form: plane c of a field starts at c * N_g, and node (x, y, z) of a plane
+ * is element x + nx (y + ny z), N_g = nx ny nz.
+ *   m      magnetization, 3 planes (m1, m2, m3)
+ *   x      saddle unknown, 4 planes (v1, v2, v3, lam)
+ * Pointers must be 16-byte aligned.  The library never frees or retains a
+ * caller buffer.
+ *
+ * Execution.  Calls run on the caller's HIP stream (stream == NULL means the
+ * null stream).  llg_matvec and fft_hss_apply are asynchronous.  gmres_solve
+ * and the steppers synchronize the stream for their convergence tests and
+ * return once the result is complete.  One context must not be used by two
+ * calls at the same time (it owns the spectral scratch buffer).
+ *
+ * Errors are returned as llg_status codes, never thrown; llg_last_error()
+ * returns a message for the last failing call on the calling thread.
+ * Argument checks happen before any GPU work is queued.
+ */
+#ifndef LLG_H
+#define LLG_H
+
+#include <stddef.h>
+
+#ifdef __cplusplus
+extern "C" {
+#endif
+
+typedef enum {
+  LLG_OK = 0,
+  LLG_EARG = 1,      /* invalid argument (null pointer, size, parameter range) */
+  LLG_EZERO_M = 2,   /* some |m_i| = 0: the constraint block loses rank (Prop. 1) */
+  LLG_ENOCONV = 3,   /* Krylov iteration limit reached; x holds the last iterate */
+  LLG_EPICARD = 4,   /* midpoint Picard iteration limit reached */
+  LLG_ENAN = 5,      /* a residual or norm became non-finite */
+  LLG_EHIP = 6,      /* HIP runtime failure */
+  LLG_ENOMEM = 7,    /* device allocation failed, or workspace too small */
+  LLG_EUNSUPPORTED = 8 /* grid size not supported by this build */
+} llg_status;
+
+typedef enum {
+  LLG_FP64 = 0,    /* plain float64 left-preconditioned GMRES */
+  LLG_FP32_IR = 1  /* float32 preconditioner and inner matvec inside float64
+                      flexible GMRES with iterative refinement */
+} llg_precision;
+
+typedef struct llg_ctx llg_ctx;
+
+/* Physical parameters of one saddle system (Sec. 2.4 and Sec. 4.1). */
+typedef struct {
+  double alpha;         /* damping, > 0 */
+  double cexc;          /* normalized exchange coefficient (1 in the paper) */
+  double dt;            /* time step k, >= 0 */
+  double theta;         /* 1 (Euler) or 1/2 (midpoint); in (0, 1] */
+  double shift;         /* HSS shift lambda > 0 (0.5 in the paper) */
+  double h_uniform[3];  /* uniform applied field */
+  const double* h_field;/* optional spatial applied field, 3 planes, or NULL */
+} llg_params;
+
+typedef struct {
+  int restart;       /* Krylov cycle length (30 by default) */
+  int maxiter;       /* total inner iteration limit */
+  int max_outer;     /* refinement steps of LLG_FP32_IR */
+  int use_x0;        /* 1: x holds the initial guess on entry, 0: start from 0 */
+  double rtol;       /* accept when ||b - A x||_2 <= rtol ||b||_2 */
+  double inner_rtol; /* relative tolerance of each inner FGMRES cycle (FP32_IR) */
+  int prec;          /* llg_precision */
+} llg_solver_opts;
+
+typedef struct {
+  int iters;           /* inner Krylov iterations (all cycles / refinement steps) */
+  int cycles;          /* Krylov cycles (restarts + 1) */
+  int outer_steps;     /* refinement steps (FP32_IR) */
+  int converged;       /* 1 if the true residual test passed */
+  double rel_res_true; /* ||b - A x||_2 / ||b||_2, recomputed in float64 */
+  double rel_res_prec; /* last preconditioned residual estimate / ||M^{-1} b|| */
+} llg_solver_stats;
+
+typedef struct {
+  int picard_iters;         /* Picard iterations of the midpoint step (1 for Euler) */
+  int lin_iters_total;      /* Krylov iterations over all solves of the step */
+  int converged;            /* Picard (and every linear solve) converged */
+  double picard_rel_change; /* last ||v^p - v^{p-1}|| / ||v^p|| */
+  double max_len_err;       /* max_i | |m_i^{n+1}| - 1 | */
+  double energy_before;     /* g_N(m^n) (exchange + Zeeman) */
+  double energy_after;      /* g_N(m^{n+1}) */
+  double dissipation_defect;/* g_N(m^{n+1}) - g_N(m^n) + alpha k/(1+alpha^2) ||v||_N^2 */
+  double inexact_correction;/* k/(1+alpha^2) [rho(v) - chi(lam)] (midpoint) */
+  double v_norm2;           /* ||v||_N^2 */
+} llg_step_stats;
+
+/* Create a context for an nx x ny x nz grid (nz = 1: 2-D) with spacing h on
+ * device `device`.  Each n must be a power of two in [4, 512].  Allocates the
+ * twiddle tables, the spectral scratch (about 48 N_g bytes) and reduction
+ * buffers.  Errors: LLG_EARG (null out, bad n or h), LLG_EUNSUPPORTED,
+ * LLG_ENOMEM, LLG_EHIP. */
+llg_status llg_ctx_create(llg_ctx** out, int nx, int ny, int nz, double h, int device);
+llg_status llg_ctx_destroy(llg_ctx* ctx);
+
+/* Bytes of caller workspace that gmres_solve and the steppers need with
+ * restart length `restart` and precision `prec` (0 on bad arguments). */
+size_t llg_workspace_bytes(const llg_ctx* ctx, int restart, int prec);
+
+/* y = A x (transpose = 0) or A^T x (transpose = 1): the matrix-free saddle
+ * operator of Sec. 2.4 eq. "saddle point system" (Sec. 3.1 eq. (HS)).
+ * m: 3 planes; x, y: 4 planes; y must not alias x.  Asynchronous. */
+llg_status llg_matvec(llg_ctx* ctx, const llg_params* prm, const double* m, const double* x, double* y,
+                      int transpose, void* stream);
+
+/* z = M^{-1} p = (calS + shift I)^{-1} (calH + shift I)^{-1} p (transpose = 0),
+ * or M^{-T} p = (calH + shift I)^{-1} (calS + shift I)^{-T} p (transpose = 1):
+ * the split FFT-HSS preconditioner of Sec. 3.2 (Algorithm 1 followed by the
+ * closed-form nodal inverse, eq. "inverse S").  m: 3 planes; p, z: 4 planes;
+ * z may alias p.  Asynchronous. */
+llg_status fft_hss_apply(llg_ctx* ctx, const llg_params* prm, const double* m, const double* p, double* z,
+                         int transpose, void* stream);
+
+/* The same two operators computed entirely in float32 (benchmarks and the
+ * inner operators of the precision form). */
+llg_status llg_matvec_f32(llg_ctx* ctx, const llg_params* prm, const float* m, const float* x, float* y,
+                          int transpose, void* stream);
+llg_status fft_hss_apply_f32(llg_ctx* ctx, const llg_params* prm, const float* m, const float* p, float* z,
+                             int transpose, void* stream);
+
+/* Solve A(m) x = b (Sec. 3.2: GMRES left-preconditioned by the split
+ * FFT-HSS operator; acceptance on the true relative residual).
+ * b, x: 4 planes; x is the initial guess when opts->use_x0 = 1 and receives
+ * the solution (the last iterate on LLG_ENOCONV).  work: device workspace of
+ * at least llg_workspace_bytes(ctx, opts->restart, opts->prec) bytes.
+ * stats may be NULL.  Synchronizes the stream.
+ * Errors: LLG_EARG, LLG_EZERO_M, LLG_ENOMEM (work too small), LLG_ENOCONV,
+ * LLG_ENAN, LLG_EHIP. */
+llg_status gmres_solve(llg_ctx* ctx, const llg_params* prm, const double* m, const double* b, double* x,
+                       const llg_solver_opts* opts, llg_solver_stats* stats, void* work, size_t work_bytes,
+                       void* stream);
+
+/* One projected implicit Euler step (Sec. 2.4; Sec. 3.2 last paragraph):
+ * solve A(m^n) (v, lam) = (C_hat Delta_N m^n + (1+alpha^2) h, 0) with
+ * theta = 1, then m^{n+1} = (m^n + k v) / |m^n + k v|.
+ * m: in m^n, out m^{n+1} (3 planes); v_out (3 planes) and lam_out (1 plane)
+ * may be NULL.  prm->theta is ignored.  Synchronizes the stream. */
+llg_status llg_step_euler(llg_ctx* ctx, const llg_params* prm, double* m, double* v_out, double* lam_out,
+                          const llg_solver_opts* opts, llg_step_stats* stats, void* work, size_t work_bytes,
+                          void* stream);
+
+/* One projection-free midpoint step (Sec. 3.3, eqs. "C-N" and "hatm"):
+ * Picard iteration on the frozen midpoint m^n + (k/2) v^{p-1}, each iterate
+ * a GMRES solve with theta = 1/2 warm-started from the previous iterate;
+ * stops when ||v^p - v^{p-1}||_2 <= picard_tol ||v^p||_2; then
+ * m^{n+1} = m^n + k v.
+ * m: in m^n, out m^{n+1}.  v_half: in v^{n-1/2} (the p = 0 midpoint; zeros on
+ * the first step), out v^{n+1/2}.  lam: in the previous multiplier (initial
+ * guess), out the new one; either may be NULL (zeros used, no output).
+ * prm->theta is ignored.  Synchronizes the stream.
+ * Errors: as gmres_solve, plus LLG_EPICARD. */
+llg_status llg_step_midpoint(llg_ctx* ctx, const llg_params* prm, double* m, double* v_half, double* lam,
+                             double picard_tol, int picard_max, const llg_solver_opts* opts,
+                             llg_step_stats* stats, void* work, size_t work_bytes, void* stream);
+
+/* Adjoint of one converged midpoint step m^{n+1} = m^n + k v(m^n, h).
+ * With J the Jacobian of the residual of eq. "C-N" with respect to (v, lam),
+ * solves J^T mu = (k gbar, 0) by GMRES preconditioned with the transposed
+ * split FFT-HSS operator built on the midpoint, then
+ *   gbar  <- gbar - [v x mu_v + C_hat (-Delta_N) mu_v + lam mu_v - v mu_lam]
+ *   hbar_field   += (1 + alpha^2) mu_v            (3 planes, may be NULL)
+ *   hbar_uniform += (1 + alpha^2) sum_i mu_v,i    (3 host doubles, may be NULL)
+ * m_n, v, lam: the forward step's input magnetization, velocity and
+ * multiplier.  gbar: in dL/dm^{n+1}, out dL/dm^n.  Synchronizes. */
+llg_status llg_step_midpoint_adjoint(llg_ctx* ctx, const llg_params* prm, const double* m_n, const double* v,
+                                     const double* lam, double* gbar, double* hbar_field, double* hbar_uniform,
+                                     const llg_solver_opts* opts, llg_solver_stats* stats, void* work,
+                                     size_t work_bytes, void* stream);
+
+/* Discrete energy g_N(m) = |Omega|/N_g sum_i [cexc/2 m_i.(-Delta_N m)_i - m_i.h_i]
+ * (exchange + Zeeman; Sec. 3.3, Proposition on the energy law).  Result to
+ * the host double *energy.  Synchronizes. */
+llg_status llg_energy(llg_ctx* ctx, const llg_params* prm, const double* m, double* energy, void* stream);
+
+/* Message describing the last error on this thread ("" if none). */
+const char* llg_last_error(void);
+
+#ifdef __cplusplus
+}
+#endif
+
+#endif /* LLG_H */

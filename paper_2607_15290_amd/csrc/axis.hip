@@ -1,0 +1,44 @@
+// Axis passes of the spectral pipeline (DFTs along y or z, see
+// pipeline_kernels.h).  Dispatches the runtime axis length to a kernel
+// instantiation.
+#include "llg_internal.h"
+#include "pipeline_kernels.h"
+
+namespace llg {
+
+template <typename T, int N>
+static hipError_t axis_n(const Ctx& c, int axis, int mode, const SymArgs& sym, cx<T>* spec, hipStream_t st) {
+  constexpr int W = axis_w(N), TPL = N / plan_p(N);
+  const unsigned gx = (unsigned)((c.geom.cs + W - 1) / W);
+  const unsigned gy = (unsigned)(axis == 1 ? c.nz : c.ny);
+  const cx<T>* tw;
+  if constexpr (std::is_same<T, double>::value) tw = c.tw_d[axis];
+  else tw = c.tw_f[axis];
+  switch (mode) {
+    case 0: hipLaunchKernelGGL((k_axis<T, N, 0>), dim3(gx, gy), dim3(W * TPL), 0, st, spec, c.geom, axis, sym, tw); break;
+    case 1: hipLaunchKernelGGL((k_axis<T, N, 1>), dim3(gx, gy), dim3(W * TPL), 0, st, spec, c.geom, axis, sym, tw); break;
+    default: hipLaunchKernelGGL((k_axis<T, N, 2>), dim3(gx, gy), dim3(W * TPL), 0, st, spec, c.geom, axis, sym, tw); break;
+  }
+  return hipGetLastError();
+}
+
+template <typename T>
+hipError_t launch_axis(const Ctx& c, int axis, int mode, const SymArgs& sym, cx<T>* spec, hipStream_t st) {
+  const int n = axis == 1 ? c.ny : c.nz;
+  switch (n) {
+    case 4: return axis_n<T, 4>(c, axis, mode, sym, spec, st);
+    case 8: return axis_n<T, 8>(c, axis, mode, sym, spec, st);
+    case 16: return axis_n<T, 16>(c, axis, mode, sym, spec, st);
+    case 32: return axis_n<T, 32>(c, axis, mode, sym, spec, st);
+    case 64: return axis_n<T, 64>(c, axis, mode, sym, spec, st);
+    case 128: return axis_n<T, 128>(c, axis, mode, sym, spec, st);
+    case 256: return axis_n<T, 256>(c, axis, mode, sym, spec, st);
+    case 512: return axis_n<T, 512>(c, axis, mode, sym, spec, st);
+    default: return hipErrorInvalidValue;
+  }
+}
+
+template hipError_t launch_axis<double>(const Ctx&, int, int, const SymArgs&, cx<double>*, hipStream_t);
+template hipError_t launch_axis<float>(const Ctx&, int, int, const SymArgs&, cx<float>*, hipStream_t);
+
+}  // namespace llg

@@ -1,0 +1,819 @@
+// C ABI of the library (include/llg.h): context, argument checks, the
+// operator entry points, the GMRES drivers and the time steppers.
+//
+// Host code only; every step of the numerical path runs in the HIP kernels of
+// the other translation units.  The host keeps the small Hessenberg least-
+// squares problem (Givens rotations, back substitution) of GMRES, which needs
+// j + 2 scalars per Arnoldi step read back from the device.
+#include <hip/hip_runtime.h>
+
+#include <cmath>
+#include <cstring>
+#include <functional>
+#include <string>
+#include <vector>
+
+#include "krylov.h"
+
+struct llg_ctx {
+  llg::Ctx c;
+};
+
+namespace llg {
+
+static thread_local std::string g_err;
+void set_error(const std::string& msg) { g_err = msg; }
+
+SymArgs sym_for(const Ctx& c, double a, double b, bool invert) {
+  SymArgs s{};
+  s.a = a;
+  s.b = b;
+  s.cx = 2.0 * M_PI / c.Lx;
+  s.cy = 2.0 * M_PI / c.Ly;
+  s.cz = c.dim == 3 ? 2.0 * M_PI / c.Lz : 0.0;
+  s.inv_ng = 1.0 / double(c.ng);
+  s.invert = invert ? 1 : 0;
+  return s;
+}
+
+namespace {
+
+bool pow2_in(int n, int lo, int hi) { return n >= lo && n <= hi && (n & (n - 1)) == 0; }
+bool is_fin(double v) { return std::isfinite(v); }
+
+llg_status fail(llg_status s, const std::string& msg) {
+  set_error(msg);
+  return s;
+}
+
+llg_status check_params(const llg_params* p) {
+  if (!p) return fail(LLG_EARG, "params is null");
+  if (!is_fin(p->alpha) || p->alpha <= 0) return fail(LLG_EARG, "alpha must be finite and > 0");
+  if (!is_fin(p->shift) || p->shift <= 0) return fail(LLG_EARG, "shift (HSS lambda) must be finite and > 0");
+  if (!is_fin(p->dt) || p->dt < 0) return fail(LLG_EARG, "dt must be finite and >= 0");
+  if (!is_fin(p->theta) || p->theta <= 0 || p->theta > 1) return fail(LLG_EARG, "theta must be in (0, 1]");
+  if (!is_fin(p->cexc) || p->cexc < 0) return fail(LLG_EARG, "cexc must be finite and >= 0");
+  for (int i = 0; i < 3; ++i)
+    if (!is_fin(p->h_uniform[i])) return fail(LLG_EARG, "h_uniform must be finite");
+  return LLG_OK;
+}
+
+llg_status check_opts(const llg_solver_opts* o) {
+  if (!o) return fail(LLG_EARG, "solver options are null");
+  if (o->restart < 1 || o->restart > kMaxDots - 2) return fail(LLG_EARG, "restart must be in [1, 62]");
+  if (o->maxiter < 1) return fail(LLG_EARG, "maxiter must be >= 1");
+  if (!is_fin(o->rtol) || o->rtol <= 0 || o->rtol >= 1) return fail(LLG_EARG, "rtol must be in (0, 1)");
+  if (o->prec != LLG_FP64 && o->prec != LLG_FP32_IR) return fail(LLG_EARG, "unknown precision");
+  if (o->prec == LLG_FP32_IR) {
+    if (o->max_outer < 1) return fail(LLG_EARG, "max_outer must be >= 1");
+    if (!is_fin(o->inner_rtol) || o->inner_rtol <= 0 || o->inner_rtol >= 1)
+      return fail(LLG_EARG, "inner_rtol must be in (0, 1)");
+  }
+  return LLG_OK;
+}
+
+NodalArgs nodal_for(const llg_params* p) {
+  NodalArgs na{};
+  na.lam = p->shift;
+  na.hs = 1.0 + p->alpha * p->alpha;
+  na.chat = (1.0 + p->alpha * p->alpha) * p->cexc;
+  na.hu0 = p->h_uniform[0];
+  na.hu1 = p->h_uniform[1];
+  na.hu2 = p->h_uniform[2];
+  na.half_k = 0.5 * p->dt;
+  na.hfield = p->h_field;
+  return na;
+}
+
+double hcoef(const llg_params* p) { return p->theta * p->dt * (1.0 + p->alpha * p->alpha) * p->cexc; }
+
+hipStream_t as_stream(void* s) { return reinterpret_cast<hipStream_t>(s); }
+
+llg_status ensure_device(const Ctx& c) {
+  int cur = -1;
+  if (hipGetDevice(&cur) != hipSuccess) return fail(LLG_EHIP, "hipGetDevice failed");
+  if (cur != c.device && hipSetDevice(c.device) != hipSuccess) return fail(LLG_EHIP, "hipSetDevice failed");
+  return LLG_OK;
+}
+
+#define CHK(expr)                                                                          \
+  do {                                                                                     \
+    hipError_t e_ = (expr);                                                                \
+    if (e_ != hipSuccess) return fail(LLG_EHIP, std::string(#expr) + ": " + hipGetErrorString(e_)); \
+  } while (0)
+
+#define CHK_STATUS(expr)             \
+  do {                               \
+    llg_status s_ = (expr);          \
+    if (s_ != LLG_OK) return s_;     \
+  } while (0)
+
+// ---- pipelines (float64) ---------------------------------------------------
+hipError_t pipe_d(const Ctx& c, int pro, int epi, const SymArgs& sym, const NodalArgs& na, const double* in,
+                  const double* m, double* out, hipStream_t st, const double* aux_v = nullptr,
+                  const double* aux_r = nullptr) {
+  PipeIO<double, double, double> io{in, m, out, c.ng, aux_v, aux_r};
+  return run_pipeline<double, double, double>(c, pro, epi, sym, na, io, st);
+}
+
+// A x (theta, k from p)
+hipError_t op_matvec(const Ctx& c, const llg_params* p, const double* m, const double* x, double* y, bool tr,
+                     hipStream_t st) {
+  return pipe_d(c, PRO_COPY3, tr ? EPI_MATVEC_T : EPI_MATVEC, sym_for(c, p->alpha, hcoef(p), false), nodal_for(p),
+                x, m, y, st);
+}
+// M^{-1} p or M^{-T} p
+hipError_t op_apply(const Ctx& c, const llg_params* p, const double* m, const double* x, double* z, bool tr,
+                    hipStream_t st) {
+  return pipe_d(c, tr ? PRO_M2T : PRO_COPY3, tr ? EPI_APPLY_T : EPI_APPLY,
+                sym_for(c, p->alpha + p->shift, hcoef(p), true), nodal_for(p), x, m, z, st);
+}
+// M^{-1} A x in one pipeline
+hipError_t op_fused(const Ctx& c, const llg_params* p, const double* m, const double* x, double* z, hipStream_t st) {
+  return pipe_d(c, PRO_SMINUS, EPI_FUSED, sym_for(c, p->alpha + p->shift, hcoef(p), true), nodal_for(p), x, m, z,
+                st);
+}
+// (-Delta_N) u for 3 planes
+hipError_t op_lap(const Ctx& c, const double* u, double* out, hipStream_t st) {
+  NodalArgs na{};
+  return pipe_d(c, PRO_COPY3, EPI_STORE3, sym_for(c, 0.0, 1.0, false), na, u, nullptr, out, st);
+}
+// b = (C_hat Delta_N m + (1+alpha^2) h, 0)
+hipError_t op_rhs(const Ctx& c, const llg_params* p, const double* m, double* b, hipStream_t st) {
+  return pipe_d(c, PRO_COPY3, EPI_RHS, sym_for(c, 0.0, 1.0, false), nodal_for(p), m, nullptr, b, st);
+}
+
+// Read n doubles of device memory (after the stream's queued work).
+llg_status fetch(const Ctx& c, const double* dev, int n, hipStream_t st, double* host_out) {
+  CHK(hipMemcpyAsync(c.host, dev, sizeof(double) * n, hipMemcpyDeviceToHost, st));
+  CHK(hipStreamSynchronize(st));
+  std::memcpy(host_out, c.host, sizeof(double) * n);
+  return LLG_OK;
+}
+
+// ---- workspace -----------------------------------------------------------
+size_t align256(size_t b) { return (b + 255) & ~size_t(255); }
+
+struct Work {
+  double* V = nullptr;   // (R + 1) x n4
+  double* r = nullptr;   // n4
+  double* t = nullptr;   // n4 temporary
+  float* Z = nullptr;    // R x n4 (precision form)
+  float* m32 = nullptr;  // 3 ng   (precision form)
+  double* b = nullptr;   // n4  stepper right-hand side
+  double* x = nullptr;   // n4  stepper unknown
+  double* m0 = nullptr;  // 3 ng
+  double* mh = nullptr;  // 3 ng
+  double* vold = nullptr;// 3 ng
+  double* l0 = nullptr;  // 3 ng
+  double* l1 = nullptr;  // 3 ng
+  size_t bytes = 0;
+};
+
+Work carve(const Ctx& c, int R, int prec, void* base) {
+  const size_t n4 = 4 * size_t(c.ng), n3 = 3 * size_t(c.ng);
+  Work w;
+  char* p = static_cast<char*>(base);
+  size_t off = 0;
+  auto take = [&](size_t bytes) -> char* {
+    char* q = p ? p + off : nullptr;
+    off += align256(bytes);
+    return q;
+  };
+  w.V = reinterpret_cast<double*>(take(sizeof(double) * n4 * (R + 1)));
+  w.r = reinterpret_cast<double*>(take(sizeof(double) * n4));
+  w.t = reinterpret_cast<double*>(take(sizeof(double) * n4));
+  if (prec == LLG_FP32_IR) {
+    w.Z = reinterpret_cast<float*>(take(sizeof(float) * n4 * R));
+    w.m32 = reinterpret_cast<float*>(take(sizeof(float) * n3));
+  }
+  w.b = reinterpret_cast<double*>(take(sizeof(double) * n4));
+  w.x = reinterpret_cast<double*>(take(sizeof(double) * n4));
+  w.m0 = reinterpret_cast<double*>(take(sizeof(double) * n3));
+  w.mh = reinterpret_cast<double*>(take(sizeof(double) * n3));
+  w.vold = reinterpret_cast<double*>(take(sizeof(double) * n3));
+  w.l0 = reinterpret_cast<double*>(take(sizeof(double) * n3));
+  w.l1 = reinterpret_cast<double*>(take(sizeof(double) * n3));
+  w.bytes = off;
+  return w;
+}
+
+// ---- GMRES ---------------------------------------------------------------
+using Op = std::function<hipError_t(const double* in, double* out)>;
+
+struct Hess {
+  int R;
+  std::vector<double> H, cs, sn, g;
+  explicit Hess(int r) : R(r), H(size_t(r + 1) * r, 0.0), cs(r, 0.0), sn(r, 0.0), g(r + 1, 0.0) {}
+  double& h(int i, int j) { return H[size_t(i) * R + j]; }
+  // Insert column j (values col[0..j+1]), rotate, return |g[j+1]|.
+  double add_column(int j, const double* col) {
+    for (int i = 0; i <= j + 1; ++i) h(i, j) = col[i];
+    for (int i = 0; i < j; ++i) {
+      const double t = cs[i] * h(i, j) + sn[i] * h(i + 1, j);
+      h(i + 1, j) = -sn[i] * h(i, j) + cs[i] * h(i + 1, j);
+      h(i, j) = t;
+    }
+    const double a = h(j, j), b = h(j + 1, j);
+    if (b == 0.0) {
+      cs[j] = 1.0;
+      sn[j] = 0.0;
+    } else {
+      const double rr = std::hypot(a, b);
+      cs[j] = a / rr;
+      sn[j] = b / rr;
+    }
+    h(j, j) = cs[j] * a + sn[j] * b;
+    h(j + 1, j) = 0.0;
+    g[j + 1] = -sn[j] * g[j];
+    g[j] = cs[j] * g[j];
+    return std::fabs(g[j + 1]);
+  }
+  void solve(int k, Coefs& y) {
+    y.n = k;
+    for (int i = k - 1; i >= 0; --i) {
+      double s = g[i];
+      for (int l = i + 1; l < k; ++l) s -= h(i, l) * y.c[l];
+      y.c[i] = s / h(i, i);
+    }
+  }
+};
+
+// One Arnoldi step on V_{j+1} (already holding the new direction): CGS2 against
+// V_0..V_j, normalization, column of H.  Returns status; fills col[0..j+1].
+llg_status arnoldi_step(const Ctx& c, double* V, long long n4, int j, double* col, hipStream_t st) {
+  double* w = V + size_t(j + 1) * n4;
+  const int nv = j + 1;
+  CHK(cgs_dots(c, V, n4, nv, w, n4, c.dots, st));
+  CHK(cgs_update_dots(c, V, n4, nv, c.dots, w, n4, c.dots2, st));
+  CHK(cgs_update_norm(c, V, n4, nv, c.dots2, w, w, n4, c.scal, st));
+  double hv[3 * kMaxDots];
+  CHK(hipMemcpyAsync(c.host, c.dots, sizeof(double) * 3 * kMaxDots, hipMemcpyDeviceToHost, st));
+  CHK(hipStreamSynchronize(st));
+  std::memcpy(hv, c.host, sizeof(hv));
+  for (int i = 0; i < nv; ++i) col[i] = hv[i] + hv[kMaxDots + i];
+  const double nrm2 = hv[2 * kMaxDots];
+  if (!is_fin(nrm2)) return fail(LLG_ENAN, "non-finite Arnoldi norm");
+  col[j + 1] = std::sqrt(nrm2);
+  if (nrm2 > 0.0) CHK(scale_invnorm(w, w, c.scal, n4, st));
+  return LLG_OK;
+}
+
+struct SolveResult {
+  int iters = 0, cycles = 0, outer = 0, converged = 0;
+  double rel_true = 0, rel_prec = 0;
+};
+
+// Left-preconditioned restarted GMRES (FP64) with true-residual acceptance.
+// A: true operator, M: preconditioner, MA: M^{-1} A.
+llg_status gmres_left(const Ctx& c, const Op& A, const Op& M, const Op& MA, const double* b, double* x,
+                      const llg_solver_opts& o, Work& w, SolveResult& res, hipStream_t st) {
+  const long long n4 = 4 * c.ng;
+  const int R = o.restart;
+  double nb[2];
+  CHK(dot_and_norm(c, b, nullptr, n4, c.scal, st));
+  CHK_STATUS(fetch(c, c.scal, 2, st, nb));
+  const double bnorm = std::sqrt(nb[1]);
+  if (!is_fin(bnorm)) return fail(LLG_ENAN, "right-hand side is not finite");
+  if (bnorm == 0.0) {
+    CHK(hipMemsetAsync(x, 0, sizeof(double) * n4, st));
+    CHK(hipStreamSynchronize(st));
+    res.converged = 1;
+    return LLG_OK;
+  }
+  const double target = o.rtol * bnorm;
+  if (o.use_x0) {
+    CHK(A(x, w.r));
+    CHK(axpby(n4, 1.0, b, -1.0, w.r, w.r, st));
+  } else {
+    CHK(hipMemsetAsync(x, 0, sizeof(double) * n4, st));
+    CHK(hipMemcpyAsync(w.r, b, sizeof(double) * n4, hipMemcpyDeviceToDevice, st));
+  }
+  double rn[2];
+  CHK(dot_and_norm(c, w.r, nullptr, n4, c.scal, st));
+  CHK_STATUS(fetch(c, c.scal, 2, st, rn));
+  double rho = std::sqrt(rn[1]);
+  double beta0 = -1.0;
+  Hess hs(R);
+  std::vector<double> col(R + 2);
+  while (true) {
+    if (!is_fin(rho)) return fail(LLG_ENAN, "non-finite residual");
+    res.rel_true = rho / bnorm;
+    if (rho <= target) {
+      res.converged = 1;
+      break;
+    }
+    if (res.iters >= o.maxiter) break;
+    res.cycles++;
+    CHK(M(w.r, w.V));
+    double bb[2];
+    CHK(dot_and_norm(c, w.V, nullptr, n4, c.scal, st));
+    CHK_STATUS(fetch(c, c.scal, 2, st, bb));
+    const double beta = std::sqrt(bb[1]);
+    if (!is_fin(beta)) return fail(LLG_ENAN, "non-finite preconditioned residual");
+    if (beta == 0.0) break;
+    if (beta0 < 0) beta0 = beta;
+    CHK(scale_invnorm(w.V, w.V, c.scal + 1, n4, st));
+    const double eta = target / rho;
+    std::fill(hs.g.begin(), hs.g.end(), 0.0);
+    hs.g[0] = beta;
+    int k = 0;
+    for (int j = 0; j < R; ++j) {
+      CHK(MA(w.V + size_t(j) * n4, w.V + size_t(j + 1) * n4));
+      CHK_STATUS(arnoldi_step(c, w.V, n4, j, col.data(), st));
+      const double gres = hs.add_column(j, col.data());
+      res.iters++;
+      k = j + 1;
+      res.rel_prec = gres / beta0;
+      if (gres <= eta * beta || res.iters >= o.maxiter || col[j + 1] == 0.0) break;
+    }
+    Coefs y{};
+    hs.solve(k, y);
+    CHK(lincomb(n4, y, w.V, n4, x, st));
+    CHK(A(x, w.r));
+    CHK(axpby(n4, 1.0, b, -1.0, w.r, w.r, st));
+    CHK(dot_and_norm(c, w.r, nullptr, n4, c.scal, st));
+    CHK_STATUS(fetch(c, c.scal, 2, st, rn));
+    rho = std::sqrt(rn[1]);
+  }
+  if (!res.converged) return fail(LLG_ENOCONV, "GMRES reached maxiter before the tolerance");
+  return LLG_OK;
+}
+
+// Precision form: FP64 iterative refinement around right-preconditioned
+// flexible GMRES whose preconditioner and matvec run in float32.
+llg_status gmres_ir(const Ctx& c, const llg_params* p, const double* m, const double* b, double* x,
+                    const llg_solver_opts& o, Work& w, SolveResult& res, hipStream_t st) {
+  const long long n4 = 4 * c.ng;
+  const int R = o.restart;
+  CHK(to_f32(3 * c.ng, m, w.m32, st));
+  const SymArgs sym_ap = sym_for(c, p->alpha + p->shift, hcoef(p), true);
+  const SymArgs sym_mv = sym_for(c, p->alpha, hcoef(p), false);
+  const NodalArgs na = nodal_for(p);
+  double nb[2];
+  CHK(dot_and_norm(c, b, nullptr, n4, c.scal, st));
+  CHK_STATUS(fetch(c, c.scal, 2, st, nb));
+  const double bnorm = std::sqrt(nb[1]);
+  if (!is_fin(bnorm)) return fail(LLG_ENAN, "right-hand side is not finite");
+  if (bnorm == 0.0) {
+    CHK(hipMemsetAsync(x, 0, sizeof(double) * n4, st));
+    CHK(hipStreamSynchronize(st));
+    res.converged = 1;
+    return LLG_OK;
+  }
+  const double target = o.rtol * bnorm;
+  if (o.use_x0) {
+    CHK(op_matvec(c, p, m, x, w.r, false, st));
+    CHK(axpby(n4, 1.0, b, -1.0, w.r, w.r, st));
+  } else {
+    CHK(hipMemsetAsync(x, 0, sizeof(double) * n4, st));
+    CHK(hipMemcpyAsync(w.r, b, sizeof(double) * n4, hipMemcpyDeviceToDevice, st));
+  }
+  double rn[2];
+  CHK(dot_and_norm(c, w.r, nullptr, n4, c.scal, st));
+  CHK_STATUS(fetch(c, c.scal, 2, st, rn));
+  double rho = std::sqrt(rn[1]);
+  Hess hs(R);
+  std::vector<double> col(R + 2);
+  while (true) {
+    if (!is_fin(rho)) return fail(LLG_ENAN, "non-finite residual");
+    res.rel_true = rho / bnorm;
+    if (rho <= target) {
+      res.converged = 1;
+      break;
+    }
+    if (res.outer >= o.max_outer || res.iters >= o.maxiter) break;
+    res.outer++;
+    res.cycles++;
+    CHK(axpby(n4, 1.0 / rho, w.r, 0.0, w.r, w.V, st));
+    const double eta = std::max(o.inner_rtol, target / rho);
+    std::fill(hs.g.begin(), hs.g.end(), 0.0);
+    hs.g[0] = rho;
+    int k = 0;
+    for (int j = 0; j < R; ++j) {
+      float* zj = w.Z + size_t(j) * n4;
+      PipeIO<float, double, float> io_ap{w.V + size_t(j) * n4, w.m32, zj, c.ng, nullptr, nullptr};
+      CHK((run_pipeline<float, double, float>(c, PRO_COPY3, EPI_APPLY, sym_ap, na, io_ap, st)));
+      PipeIO<float, float, double> io_mv{zj, w.m32, w.V + size_t(j + 1) * n4, c.ng, nullptr, nullptr};
+      CHK((run_pipeline<float, float, double>(c, PRO_COPY3, EPI_MATVEC, sym_mv, na, io_mv, st)));
+      CHK_STATUS(arnoldi_step(c, w.V, n4, j, col.data(), st));
+      const double gres = hs.add_column(j, col.data());
+      res.iters++;
+      k = j + 1;
+      res.rel_prec = gres / bnorm;
+      if (gres <= eta * rho || res.iters >= o.maxiter || col[j + 1] == 0.0) break;
+    }
+    Coefs y{};
+    hs.solve(k, y);
+    CHK(lincomb(n4, y, w.Z, n4, x, st));
+    CHK(op_matvec(c, p, m, x, w.r, false, st));
+    CHK(axpby(n4, 1.0, b, -1.0, w.r, w.r, st));
+    CHK(dot_and_norm(c, w.r, nullptr, n4, c.scal, st));
+    CHK_STATUS(fetch(c, c.scal, 2, st, rn));
+    rho = std::sqrt(rn[1]);
+  }
+  if (!res.converged) return fail(LLG_ENOCONV, "refinement reached its limit before the tolerance");
+  return LLG_OK;
+}
+
+llg_status check_m(const Ctx& c, const double* m, hipStream_t st) {
+  double o[2];
+  CHK(m_check(c, m, c.scal, st));
+  CHK_STATUS(fetch(c, c.scal, 2, st, o));
+  if (o[1] != 0.0) return fail(LLG_ENAN, "magnetization contains non-finite values");
+  if (!(o[0] > 1e-300)) return fail(LLG_EZERO_M, "some nodal magnetization is zero (Proposition 1 needs m_i != 0)");
+  return LLG_OK;
+}
+
+llg_status solve(const Ctx& c, const llg_params* p, const double* m, const double* b, double* x,
+                 const llg_solver_opts& o, Work& w, SolveResult& res, hipStream_t st) {
+  CHK_STATUS(check_m(c, m, st));
+  if (o.prec == LLG_FP32_IR) return gmres_ir(c, p, m, b, x, o, w, res, st);
+  Op A = [&](const double* in, double* out) { return op_matvec(c, p, m, in, out, false, st); };
+  Op M = [&](const double* in, double* out) { return op_apply(c, p, m, in, out, false, st); };
+  Op MA = [&](const double* in, double* out) { return op_fused(c, p, m, in, out, st); };
+  return gmres_left(c, A, M, MA, b, x, o, w, res, st);
+}
+
+void fill_stats(const SolveResult& r, llg_solver_stats* s) {
+  if (!s) return;
+  s->iters = r.iters;
+  s->cycles = r.cycles;
+  s->outer_steps = r.outer;
+  s->converged = r.converged;
+  s->rel_res_true = r.rel_true;
+  s->rel_res_prec = r.rel_prec;
+}
+
+llg_status energy_of(const Ctx& c, const llg_params* p, const double* m, double* lm, double* e, hipStream_t st) {
+  CHK(op_lap(c, m, lm, st));
+  CHK(energy_sum(c, nodal_for(p), p->cexc, m, lm, c.scal, st));
+  double s;
+  CHK_STATUS(fetch(c, c.scal, 1, st, &s));
+  const double vol = c.Lx * c.Ly * (c.dim == 3 ? c.Lz : 1.0);
+  *e = s * vol / double(c.ng);
+  return LLG_OK;
+}
+
+}  // namespace
+}  // namespace llg
+
+using namespace llg;
+
+// ---------------------------------------------------------------------------
+extern "C" {
+
+const char* llg_last_error(void) { return g_err.c_str(); }
+
+llg_status llg_ctx_create(llg_ctx** out, int nx, int ny, int nz, double h, int device) {
+  if (!out) return fail(LLG_EARG, "out is null");
+  *out = nullptr;
+  if (!pow2_in(nx, 4, 512) || !pow2_in(ny, 4, 512) || !(nz == 1 || pow2_in(nz, 4, 512)))
+    return fail(LLG_EARG, "each of nx, ny must be a power of two in [4, 512]; nz must be 1 or such a power");
+  if (!is_fin(h) || h <= 0) return fail(LLG_EARG, "h must be finite and > 0");
+  if (device < 0) return fail(LLG_EARG, "device must be >= 0");
+  int ndev = 0;
+  if (hipGetDeviceCount(&ndev) != hipSuccess || device >= ndev) return fail(LLG_EHIP, "no such HIP device");
+  if (hipSetDevice(device) != hipSuccess) return fail(LLG_EHIP, "hipSetDevice failed");
+  llg_ctx* ctx = new llg_ctx();
+  Ctx& c = ctx->c;
+  c.nx = nx;
+  c.ny = ny;
+  c.nz = nz;
+  c.dim = nz == 1 ? 2 : 3;
+  c.device = device;
+  c.h = h;
+  c.Lx = nx * h;
+  c.Ly = ny * h;
+  c.Lz = nz * h;
+  c.ng = (long long)nx * ny * nz;
+  c.geom.nx = nx;
+  c.geom.ny = ny;
+  c.geom.nz = nz;
+  c.geom.nh = nx / 2;
+  c.geom.cs = 3 * (nx / 2 + 1);
+  c.geom.rs = (c.geom.cs + 15) / 16 * 16;
+  c.geom.ng = c.ng;
+  c.spec_bytes = sizeof(cx<double>) * size_t(c.geom.rs) * ny * nz;
+  auto cleanup = [&](llg_status s, const std::string& m) {
+    llg_ctx_destroy(ctx);
+    return fail(s, m);
+  };
+  if (hipMalloc(&c.spec, c.spec_bytes) != hipSuccess) return cleanup(LLG_ENOMEM, "spectral scratch allocation failed");
+  if (hipMalloc(&c.partial, sizeof(double) * kRedBlocks * kMaxDots) != hipSuccess)
+    return cleanup(LLG_ENOMEM, "reduction buffer allocation failed");
+  if (hipMalloc(&c.dots, sizeof(double) * 4 * kMaxDots) != hipSuccess)
+    return cleanup(LLG_ENOMEM, "reduction buffer allocation failed");
+  c.dots2 = c.dots + kMaxDots;
+  c.scal = c.dots + 2 * kMaxDots;
+  if (hipHostMalloc(reinterpret_cast<void**>(&c.host), sizeof(double) * 4 * kMaxDots, hipHostMallocDefault) !=
+      hipSuccess)
+    return cleanup(LLG_ENOMEM, "pinned host buffer allocation failed");
+  const int ns[3] = {nx, ny, nz};
+  for (int a = 0; a < 3; ++a) {
+    const int n = ns[a];
+    if (n < 2) continue;
+    std::vector<cx<double>> td(n);
+    std::vector<cx<float>> tf(n);
+    for (int m = 0; m < n; ++m) {
+      const long double ang = -2.0L * 3.14159265358979323846264338327950288L * (long double)m / (long double)n;
+      td[m] = {(double)cosl(ang), (double)sinl(ang)};
+      tf[m] = {(float)cosl(ang), (float)sinl(ang)};
+    }
+    if (hipMalloc(&c.tw_d[a], sizeof(cx<double>) * n) != hipSuccess ||
+        hipMalloc(&c.tw_f[a], sizeof(cx<float>) * n) != hipSuccess)
+      return cleanup(LLG_ENOMEM, "twiddle allocation failed");
+    if (hipMemcpy(c.tw_d[a], td.data(), sizeof(cx<double>) * n, hipMemcpyHostToDevice) != hipSuccess ||
+        hipMemcpy(c.tw_f[a], tf.data(), sizeof(cx<float>) * n, hipMemcpyHostToDevice) != hipSuccess)
+      return cleanup(LLG_EHIP, "twiddle upload failed");
+  }
+  *out = ctx;
+  return LLG_OK;
+}
+
+llg_status llg_ctx_destroy(llg_ctx* ctx) {
+  if (!ctx) return LLG_OK;
+  Ctx& c = ctx->c;
+  int cur = -1;
+  (void)hipGetDevice(&cur);
+  if (cur != c.device) (void)hipSetDevice(c.device);
+  (void)hipDeviceSynchronize();
+  for (int a = 0; a < 3; ++a) {
+    if (c.tw_d[a]) (void)hipFree(c.tw_d[a]);
+    if (c.tw_f[a]) (void)hipFree(c.tw_f[a]);
+  }
+  if (c.spec) (void)hipFree(c.spec);
+  if (c.partial) (void)hipFree(c.partial);
+  if (c.dots) (void)hipFree(c.dots);
+  if (c.host) (void)hipHostFree(c.host);
+  delete ctx;
+  return LLG_OK;
+}
+
+size_t llg_workspace_bytes(const llg_ctx* ctx, int restart, int prec) {
+  if (!ctx || restart < 1 || restart > kMaxDots - 2 || (prec != LLG_FP64 && prec != LLG_FP32_IR)) return 0;
+  return carve(ctx->c, restart, prec, nullptr).bytes;
+}
+
+llg_status llg_matvec(llg_ctx* ctx, const llg_params* prm, const double* m, const double* x, double* y,
+                      int transpose, void* stream) {
+  if (!ctx || !m || !x || !y) return fail(LLG_EARG, "null argument");
+  if (x == y) return fail(LLG_EARG, "llg_matvec: y must not alias x");
+  CHK_STATUS(check_params(prm));
+  CHK_STATUS(ensure_device(ctx->c));
+  CHK(op_matvec(ctx->c, prm, m, x, y, transpose != 0, as_stream(stream)));
+  return LLG_OK;
+}
+
+llg_status fft_hss_apply(llg_ctx* ctx, const llg_params* prm, const double* m, const double* p, double* z,
+                         int transpose, void* stream) {
+  if (!ctx || !m || !p || !z) return fail(LLG_EARG, "null argument");
+  CHK_STATUS(check_params(prm));
+  CHK_STATUS(ensure_device(ctx->c));
+  CHK(op_apply(ctx->c, prm, m, p, z, transpose != 0, as_stream(stream)));
+  return LLG_OK;
+}
+
+llg_status llg_matvec_f32(llg_ctx* ctx, const llg_params* prm, const float* m, const float* x, float* y,
+                          int transpose, void* stream) {
+  if (!ctx || !m || !x || !y) return fail(LLG_EARG, "null argument");
+  if (x == y) return fail(LLG_EARG, "llg_matvec_f32: y must not alias x");
+  CHK_STATUS(check_params(prm));
+  CHK_STATUS(ensure_device(ctx->c));
+  const Ctx& c = ctx->c;
+  PipeIO<float, float, float> io{x, m, y, c.ng, nullptr, nullptr};
+  CHK((run_pipeline<float, float, float>(c, PRO_COPY3, transpose ? EPI_MATVEC_T : EPI_MATVEC,
+                                         sym_for(c, prm->alpha, hcoef(prm), false), nodal_for(prm), io,
+                                         as_stream(stream))));
+  return LLG_OK;
+}
+
+llg_status fft_hss_apply_f32(llg_ctx* ctx, const llg_params* prm, const float* m, const float* p, float* z,
+                             int transpose, void* stream) {
+  if (!ctx || !m || !p || !z) return fail(LLG_EARG, "null argument");
+  CHK_STATUS(check_params(prm));
+  CHK_STATUS(ensure_device(ctx->c));
+  const Ctx& c = ctx->c;
+  PipeIO<float, float, float> io{p, m, z, c.ng, nullptr, nullptr};
+  CHK((run_pipeline<float, float, float>(c, transpose ? PRO_M2T : PRO_COPY3, transpose ? EPI_APPLY_T : EPI_APPLY,
+                                         sym_for(c, prm->alpha + prm->shift, hcoef(prm), true), nodal_for(prm), io,
+                                         as_stream(stream))));
+  return LLG_OK;
+}
+
+llg_status gmres_solve(llg_ctx* ctx, const llg_params* prm, const double* m, const double* b, double* x,
+                       const llg_solver_opts* opts, llg_solver_stats* stats, void* work, size_t work_bytes,
+                       void* stream) {
+  if (!ctx || !m || !b || !x || !work) return fail(LLG_EARG, "null argument");
+  CHK_STATUS(check_params(prm));
+  CHK_STATUS(check_opts(opts));
+  if (x == b) return fail(LLG_EARG, "gmres_solve: x must not alias b");
+  const Ctx& c = ctx->c;
+  Work w = carve(c, opts->restart, opts->prec, work);
+  if (work_bytes < w.bytes) return fail(LLG_ENOMEM, "workspace smaller than llg_workspace_bytes()");
+  CHK_STATUS(ensure_device(c));
+  SolveResult r;
+  const llg_status s = solve(c, prm, m, b, x, *opts, w, r, as_stream(stream));
+  fill_stats(r, stats);
+  return s;
+}
+
+llg_status llg_energy(llg_ctx* ctx, const llg_params* prm, const double* m, double* energy, void* stream) {
+  if (!ctx || !m || !energy) return fail(LLG_EARG, "null argument");
+  CHK_STATUS(check_params(prm));
+  CHK_STATUS(ensure_device(ctx->c));
+  const Ctx& c = ctx->c;
+  double* lm = nullptr;
+  CHK(hipMalloc(&lm, sizeof(double) * 3 * c.ng));
+  const llg_status s = energy_of(c, prm, m, lm, energy, as_stream(stream));
+  (void)hipFree(lm);
+  return s;
+}
+
+llg_status llg_step_euler(llg_ctx* ctx, const llg_params* prm, double* m, double* v_out, double* lam_out,
+                          const llg_solver_opts* opts, llg_step_stats* stats, void* work, size_t work_bytes,
+                          void* stream) {
+  if (!ctx || !m || !work) return fail(LLG_EARG, "null argument");
+  CHK_STATUS(check_params(prm));
+  CHK_STATUS(check_opts(opts));
+  const Ctx& c = ctx->c;
+  Work w = carve(c, opts->restart, opts->prec, work);
+  if (work_bytes < w.bytes) return fail(LLG_ENOMEM, "workspace smaller than llg_workspace_bytes()");
+  CHK_STATUS(ensure_device(c));
+  hipStream_t st = as_stream(stream);
+  llg_params p1 = *prm;
+  p1.theta = 1.0;
+  llg_solver_opts o = *opts;
+  o.use_x0 = 0;
+  const long long ng = c.ng;
+  if (stats) std::memset(stats, 0, sizeof(*stats));
+  double e0 = 0;
+  if (stats) CHK_STATUS(energy_of(c, &p1, m, w.l0, &e0, st));
+  CHK(op_rhs(c, &p1, m, w.b, st));
+  SolveResult r;
+  const llg_status s = solve(c, &p1, m, w.b, w.x, o, w, r, st);
+  if (stats) {
+    stats->picard_iters = 1;
+    stats->lin_iters_total = r.iters;
+    stats->converged = r.converged;
+  }
+  if (s != LLG_OK) return s;
+  double len;
+  CHK(euler_update(c, m, w.x, p1.dt, c.scal, st));
+  CHK_STATUS(fetch(c, c.scal, 1, st, &len));
+  if (v_out) CHK(hipMemcpyAsync(v_out, w.x, sizeof(double) * 3 * ng, hipMemcpyDeviceToDevice, st));
+  if (lam_out) CHK(hipMemcpyAsync(lam_out, w.x + 3 * ng, sizeof(double) * ng, hipMemcpyDeviceToDevice, st));
+  if (stats) {
+    double e1 = 0, vv[2];
+    CHK_STATUS(energy_of(c, &p1, m, w.l0, &e1, st));
+    CHK(dot_and_norm(c, w.x, nullptr, 3 * ng, c.scal, st));
+    CHK_STATUS(fetch(c, c.scal, 2, st, vv));
+    const double wq = c.Lx * c.Ly * (c.dim == 3 ? c.Lz : 1.0) / double(ng);
+    stats->max_len_err = len;
+    stats->energy_before = e0;
+    stats->energy_after = e1;
+    stats->v_norm2 = wq * vv[1];
+    const double a = p1.alpha;
+    stats->dissipation_defect = e1 - e0 + a * p1.dt / (1 + a * a) * stats->v_norm2;
+  }
+  CHK(hipStreamSynchronize(st));
+  return LLG_OK;
+}
+
+llg_status llg_step_midpoint(llg_ctx* ctx, const llg_params* prm, double* m, double* v_half, double* lam,
+                             double picard_tol, int picard_max, const llg_solver_opts* opts,
+                             llg_step_stats* stats, void* work, size_t work_bytes, void* stream) {
+  if (!ctx || !m || !work) return fail(LLG_EARG, "null argument");
+  CHK_STATUS(check_params(prm));
+  CHK_STATUS(check_opts(opts));
+  if (!is_fin(picard_tol) || picard_tol <= 0 || picard_max < 1)
+    return fail(LLG_EARG, "picard_tol must be > 0 and picard_max >= 1");
+  const Ctx& c = ctx->c;
+  Work w = carve(c, opts->restart, opts->prec, work);
+  if (work_bytes < w.bytes) return fail(LLG_ENOMEM, "workspace smaller than llg_workspace_bytes()");
+  CHK_STATUS(ensure_device(c));
+  hipStream_t st = as_stream(stream);
+  const long long ng = c.ng;
+  llg_params p2 = *prm;
+  p2.theta = 0.5;
+  llg_solver_opts o = *opts;
+  o.use_x0 = 1;
+  const double k = prm->dt;
+  if (stats) std::memset(stats, 0, sizeof(*stats));
+  CHK(hipMemcpyAsync(w.m0, m, sizeof(double) * 3 * ng, hipMemcpyDeviceToDevice, st));
+  CHK(op_rhs(c, &p2, w.m0, w.b, st));
+  if (v_half) {
+    CHK(hipMemcpyAsync(w.vold, v_half, sizeof(double) * 3 * ng, hipMemcpyDeviceToDevice, st));
+    CHK(hipMemcpyAsync(w.x, v_half, sizeof(double) * 3 * ng, hipMemcpyDeviceToDevice, st));
+  } else {
+    CHK(hipMemsetAsync(w.vold, 0, sizeof(double) * 3 * ng, st));
+    CHK(hipMemsetAsync(w.x, 0, sizeof(double) * 3 * ng, st));
+  }
+  if (lam) CHK(hipMemcpyAsync(w.x + 3 * ng, lam, sizeof(double) * ng, hipMemcpyDeviceToDevice, st));
+  else CHK(hipMemsetAsync(w.x + 3 * ng, 0, sizeof(double) * ng, st));
+  int iters = 0, pic = 0;
+  bool pconv = false, lconv = true;
+  double change = 0;
+  llg_status lin = LLG_OK;
+  for (int p = 0; p < picard_max; ++p) {
+    CHK(nodal_axpy3(c, w.m0, 0.5 * k, w.vold, w.mh, st));
+    SolveResult r;
+    lin = solve(c, &p2, w.mh, w.b, w.x, o, w, r, st);
+    iters += r.iters;
+    pic++;
+    if (lin != LLG_OK && lin != LLG_ENOCONV) return lin;
+    if (lin == LLG_ENOCONV) lconv = false;
+    double dn[2];
+    CHK(diff_norms(c, w.x, w.vold, 3 * ng, c.scal, st));
+    CHK_STATUS(fetch(c, c.scal, 2, st, dn));
+    CHK(hipMemcpyAsync(w.vold, w.x, sizeof(double) * 3 * ng, hipMemcpyDeviceToDevice, st));
+    const double vn = std::sqrt(dn[1]), dd = std::sqrt(dn[0]);
+    change = vn > 0 ? dd / vn : dd;
+    if (!is_fin(change)) return fail(LLG_ENAN, "non-finite Picard update");
+    if (dd <= picard_tol * vn) {
+      pconv = true;
+      break;
+    }
+  }
+  CHK(nodal_axpy3(c, w.m0, k, w.x, m, st));
+  if (v_half) CHK(hipMemcpyAsync(v_half, w.x, sizeof(double) * 3 * ng, hipMemcpyDeviceToDevice, st));
+  if (lam) CHK(hipMemcpyAsync(lam, w.x + 3 * ng, sizeof(double) * ng, hipMemcpyDeviceToDevice, st));
+  if (stats) {
+    stats->picard_iters = pic;
+    stats->lin_iters_total = iters;
+    stats->converged = (pconv && lconv) ? 1 : 0;
+    stats->picard_rel_change = change;
+    CHK(op_lap(c, w.m0, w.l0, st));
+    CHK(op_lap(c, w.x, w.l1, st));
+    double d[5], len;
+    CHK(midpoint_diag(c, nodal_for(prm), prm->alpha, prm->cexc, k, w.m0, w.x, w.x + 3 * ng, w.l0, w.l1, c.scal, st));
+    CHK_STATUS(fetch(c, c.scal, 5, st, d));
+    CHK(len_err(c, m, c.scal, st));
+    CHK_STATUS(fetch(c, c.scal, 1, st, &len));
+    const double wq = c.Lx * c.Ly * (c.dim == 3 ? c.Lz : 1.0) / double(ng);
+    const double a = prm->alpha;
+    stats->energy_before = wq * d[0];
+    stats->energy_after = wq * d[1];
+    stats->v_norm2 = wq * d[2];
+    stats->dissipation_defect = stats->energy_after - stats->energy_before + a * k / (1 + a * a) * stats->v_norm2;
+    stats->inexact_correction = k / (1 + a * a) * (wq * d[3] - wq * d[4]);
+    stats->max_len_err = len;
+  }
+  CHK(hipStreamSynchronize(st));
+  if (!lconv) return fail(LLG_ENOCONV, "a Picard linear solve did not converge");
+  if (!pconv) return fail(LLG_EPICARD, "Picard iteration reached picard_max");
+  return LLG_OK;
+}
+
+llg_status llg_step_midpoint_adjoint(llg_ctx* ctx, const llg_params* prm, const double* m_n, const double* v,
+                                     const double* lam, double* gbar, double* hbar_field, double* hbar_uniform,
+                                     const llg_solver_opts* opts, llg_solver_stats* stats, void* work,
+                                     size_t work_bytes, void* stream) {
+  if (!ctx || !m_n || !v || !lam || !gbar || !work) return fail(LLG_EARG, "null argument");
+  CHK_STATUS(check_params(prm));
+  CHK_STATUS(check_opts(opts));
+  if (opts->prec != LLG_FP64) return fail(LLG_EARG, "the adjoint solve runs in float64 only");
+  const Ctx& c = ctx->c;
+  Work w = carve(c, opts->restart, opts->prec, work);
+  if (work_bytes < w.bytes) return fail(LLG_ENOMEM, "workspace smaller than llg_workspace_bytes()");
+  CHK_STATUS(ensure_device(c));
+  hipStream_t st = as_stream(stream);
+  const long long ng = c.ng, n4 = 4 * ng;
+  llg_params p2 = *prm;
+  p2.theta = 0.5;
+  const double k = prm->dt;
+  // midpoint m_half = m^n + (k/2) v builds the transposed preconditioner
+  CHK(nodal_axpy3(c, m_n, 0.5 * k, v, w.mh, st));
+  CHK_STATUS(check_m(c, w.mh, st));
+  // rhs = (k gbar, 0)
+  CHK(axpby(3 * ng, k, gbar, 0.0, gbar, w.b, st));
+  CHK(hipMemsetAsync(w.b + 3 * ng, 0, sizeof(double) * ng, st));
+  const SymArgs sym_h = sym_for(c, p2.alpha, hcoef(&p2), false);
+  const NodalArgs na = nodal_for(&p2);
+  Op JT = [&](const double* in, double* out) {
+    return pipe_d(c, PRO_COPY3, EPI_JT, sym_h, na, in, m_n, out, st, v, lam);
+  };
+  Op MT = [&](const double* in, double* out) { return op_apply(c, &p2, w.mh, in, out, true, st); };
+  Op MTJT = [&](const double* in, double* out) {
+    hipError_t e = JT(in, w.t);
+    if (e != hipSuccess) return e;
+    return MT(w.t, out);
+  };
+  llg_solver_opts o = *opts;
+  o.use_x0 = 0;
+  SolveResult r;
+  const llg_status s = gmres_left(c, JT, MT, MTJT, w.b, w.x, o, w, r, st);
+  fill_stats(r, stats);
+  if (s != LLG_OK) return s;
+  // gbar update and field gradients
+  CHK(op_lap(c, w.x, w.l0, st));
+  CHK(adjoint_finish(c, na, v, lam, w.x, w.l0, gbar, hbar_field, c.scal, st));
+  double hs3[3];
+  CHK_STATUS(fetch(c, c.scal, 3, st, hs3));
+  if (hbar_uniform)
+    for (int i = 0; i < 3; ++i) hbar_uniform[i] += hs3[i];
+  (void)n4;
+  return LLG_OK;
+}
+
+}  // extern "C"

@@ -1,0 +1,265 @@
+// Device building blocks of the batched line FFTs used by every spectral pass.
+//
+// The exchange block H = a I + b(-Delta_N) of the saddle operator and the
+// shifted factor calH + lambda I of the split preconditioner are diagonal in
+// Fourier space (Sec. 2.3; Sec. 3.2, Algorithm 1).  Every spectral pass of the
+// library is therefore a set of independent 1-D DFTs along one grid axis
+// ("lines"), each computed by a small team of threads with a Stockham
+// autosort schedule: a line of N complex points is held by TPL = N / P
+// threads, P points each, and the radix stages exchange data through LDS.
+//
+// Conventions
+//  * forward DFT X[k] = sum_n x[n] exp(-2 pi i k n / N), inverse with +i, both
+//    unnormalized (the 1/N_g factor is folded into the Fourier symbol);
+//  * a thread t of a line always holds, at the start of the first stage and at
+//    the end of the last stage, the positions t + TPL*q, q = 0..P-1; the slot
+//    of position q is fixed at compile time (in_slot / out_q below), so
+//    global loads/stores and the fused forward->scale->inverse hand-over need
+//    no data movement;
+//  * twiddles come from a per-length table tw[m] = exp(-2 pi i m / L) built on
+//    the host in extended precision.
+
+#pragma once
+#include <hip/hip_runtime.h>
+
+namespace llg {
+
+template <typename T>
+struct cx {
+  T x, y;
+};
+
+template <typename T>
+__device__ __forceinline__ cx<T> cadd(cx<T> a, cx<T> b) { return {a.x + b.x, a.y + b.y}; }
+template <typename T>
+__device__ __forceinline__ cx<T> csub(cx<T> a, cx<T> b) { return {a.x - b.x, a.y - b.y}; }
+template <typename T>
+__device__ __forceinline__ cx<T> cmul(cx<T> a, cx<T> b) {
+  return {a.x * b.x - a.y * b.y, a.x * b.y + a.y * b.x};
+}
+// a * conj(b)
+template <typename T>
+__device__ __forceinline__ cx<T> cmulc(cx<T> a, cx<T> b) {
+  return {a.x * b.x + a.y * b.y, a.y * b.x - a.x * b.y};
+}
+template <typename T>
+__device__ __forceinline__ cx<T> cscale(cx<T> a, T s) { return {a.x * s, a.y * s}; }
+// multiply by -i (DIR = -1, forward) or +i (DIR = +1, inverse)
+template <typename T, int DIR>
+__device__ __forceinline__ cx<T> mul_dir_i(cx<T> a) {
+  return DIR < 0 ? cx<T>{a.y, -a.x} : cx<T>{-a.y, a.x};
+}
+
+// ---------------------------------------------------------------------------
+// Radix plans: P points per thread, up to three stages.
+//   N:   2   4   8  16  32    64    128    256     512      1024
+//   R:  [2] [4] [8][16][8,4] [8,8] [16,8] [16,16] [8,8,8] [16,16,4]
+// ---------------------------------------------------------------------------
+__host__ __device__ constexpr int plan_p(int n) {
+  return n <= 16 ? n : (n == 32 || n == 64 || n == 512) ? 8 : 16;
+}
+__host__ __device__ constexpr int plan_stages(int n) {
+  return n <= 16 ? 1 : (n <= 256 ? 2 : 3);
+}
+__host__ __device__ constexpr int plan_radix(int n, int s) {
+  return n <= 16 ? n
+         : n == 32   ? (s == 0 ? 8 : 4)
+         : n == 64   ? 8
+         : n == 128  ? (s == 0 ? 16 : 8)
+         : n == 256  ? 16
+         : n == 512  ? 8
+                     : (s < 2 ? 16 : 4);
+}
+// product of the radices of the stages before s
+__host__ __device__ constexpr int plan_ns(int n, int s) {
+  return s == 0 ? 1 : plan_ns(n, s - 1) * plan_radix(n, s - 1);
+}
+// slot of input position t + TPL*q (first stage has radix P, so slot = q)
+template <int N>
+__device__ __forceinline__ constexpr int in_slot(int q) { return q; }
+// position index q held by output slot s of the last stage
+template <int N>
+__device__ __forceinline__ constexpr int out_q(int slot) {
+  constexpr int P = plan_p(N);
+  constexpr int R = plan_radix(N, plan_stages(N) - 1);
+  return (slot / R) + (slot % R) * (P / R);
+}
+
+// ---------------------------------------------------------------------------
+// In-register DFTs of size 2, 4, 8, 16 (natural order in and out).
+// ---------------------------------------------------------------------------
+template <typename T, int DIR>
+__device__ __forceinline__ void dft2(cx<T>& a, cx<T>& b) {
+  cx<T> t = a;
+  a = cadd(t, b);
+  b = csub(t, b);
+}
+
+template <typename T, int DIR>
+__device__ __forceinline__ void dft4(cx<T>& x0, cx<T>& x1, cx<T>& x2, cx<T>& x3) {
+  cx<T> s02 = cadd(x0, x2), d02 = csub(x0, x2);
+  cx<T> s13 = cadd(x1, x3), d13 = mul_dir_i<T, DIR>(csub(x1, x3));
+  x0 = cadd(s02, s13);
+  x2 = csub(s02, s13);
+  x1 = cadd(d02, d13);
+  x3 = csub(d02, d13);
+}
+
+template <typename T>
+struct Consts {
+  static constexpr T r2 = T(0.70710678118654752440084436210484903928483593768847);
+  static constexpr T c8 = T(0.92387953251128675612818318939678828682241662586364);  // cos(pi/8)
+  static constexpr T s8 = T(0.38268343236508977172845998403039886676134456248563);  // sin(pi/8)
+};
+
+// multiply by exp(DIR * 2 pi i * e / 16), e = 0..9 (compile time)
+template <typename T, int DIR, int E>
+__device__ __forceinline__ cx<T> w16(cx<T> a) {
+  constexpr T r2 = Consts<T>::r2, c = Consts<T>::c8, s = Consts<T>::s8;
+  constexpr int e = E % 16;
+  if constexpr (e == 0) return a;
+  else if constexpr (e == 4) return mul_dir_i<T, DIR>(a);
+  else if constexpr (e == 8) return {-a.x, -a.y};
+  else if constexpr (e == 12) return mul_dir_i<T, -DIR>(a);
+  else {
+    // angle = DIR * 2 pi e / 16 ; cos/sin from the octant table
+    constexpr int ea = e;  // 1..15 except 4, 8, 12
+    constexpr T cs[16] = {T(1), c, r2, s, T(0), -s, -r2, -c, T(-1), -c, -r2, -s, T(0), s, r2, c};
+    constexpr T sn[16] = {T(0), s, r2, c, T(1), c, r2, s, T(0), -s, -r2, -c, T(-1), -c, -r2, -s};
+    constexpr T wr = cs[ea];
+    constexpr T wi = DIR < 0 ? -sn[ea] : sn[ea];
+    return {a.x * wr - a.y * wi, a.x * wi + a.y * wr};
+  }
+}
+
+template <typename T, int DIR>
+__device__ __forceinline__ void dft8(cx<T>* v) {
+  // even / odd split: E = DFT4(v0, v2, v4, v6), O = DFT4(v1, v3, v5, v7)
+  dft4<T, DIR>(v[0], v[2], v[4], v[6]);
+  dft4<T, DIR>(v[1], v[3], v[5], v[7]);
+  cx<T> o1 = w16<T, DIR, 2>(v[3]);
+  cx<T> o2 = w16<T, DIR, 4>(v[5]);
+  cx<T> o3 = w16<T, DIR, 6>(v[7]);
+  cx<T> e0 = v[0], e1 = v[2], e2 = v[4], e3 = v[6], o0 = v[1];
+  v[0] = cadd(e0, o0);
+  v[4] = csub(e0, o0);
+  v[1] = cadd(e1, o1);
+  v[5] = csub(e1, o1);
+  v[2] = cadd(e2, o2);
+  v[6] = csub(e2, o2);
+  v[3] = cadd(e3, o3);
+  v[7] = csub(e3, o3);
+}
+
+template <typename T, int DIR>
+__device__ __forceinline__ void dft16(cx<T>* v) {
+  // n = n1 + 4 n2, k = k2 + 4 k1
+  dft4<T, DIR>(v[0], v[4], v[8], v[12]);
+  dft4<T, DIR>(v[1], v[5], v[9], v[13]);
+  dft4<T, DIR>(v[2], v[6], v[10], v[14]);
+  dft4<T, DIR>(v[3], v[7], v[11], v[15]);
+  // v[n1 + 4 k2] *= w16^(n1 k2)
+  v[5] = w16<T, DIR, 1>(v[5]);
+  v[9] = w16<T, DIR, 2>(v[9]);
+  v[13] = w16<T, DIR, 3>(v[13]);
+  v[6] = w16<T, DIR, 2>(v[6]);
+  v[10] = w16<T, DIR, 4>(v[10]);
+  v[14] = w16<T, DIR, 6>(v[14]);
+  v[7] = w16<T, DIR, 3>(v[7]);
+  v[11] = w16<T, DIR, 6>(v[11]);
+  v[15] = w16<T, DIR, 9>(v[15]);
+  // DFT4 over n1 for each k2; result index k2 + 4 k1 lands at slot 4 k2 + k1
+  dft4<T, DIR>(v[0], v[1], v[2], v[3]);
+  dft4<T, DIR>(v[4], v[5], v[6], v[7]);
+  dft4<T, DIR>(v[8], v[9], v[10], v[11]);
+  dft4<T, DIR>(v[12], v[13], v[14], v[15]);
+  // transpose the 4x4 index grid back to natural order
+  cx<T> t;
+  t = v[1]; v[1] = v[4]; v[4] = t;
+  t = v[2]; v[2] = v[8]; v[8] = t;
+  t = v[3]; v[3] = v[12]; v[12] = t;
+  t = v[6]; v[6] = v[9]; v[9] = t;
+  t = v[7]; v[7] = v[13]; v[13] = t;
+  t = v[11]; v[11] = v[14]; v[14] = t;
+}
+
+template <typename T, int R, int DIR>
+__device__ __forceinline__ void dft(cx<T>* v) {
+  if constexpr (R == 1) {
+  } else if constexpr (R == 2) dft2<T, DIR>(v[0], v[1]);
+  else if constexpr (R == 4) dft4<T, DIR>(v[0], v[1], v[2], v[3]);
+  else if constexpr (R == 8) dft8<T, DIR>(v);
+  else dft16<T, DIR>(v);
+}
+
+// ---------------------------------------------------------------------------
+// One Stockham radix-R stage on registers: twiddle then DFT.  Butterfly b of
+// thread t is j = t + TPL*b; its inputs are positions j + r N/R; its outputs
+// go to (j/Ns)*Ns*R + j%Ns + r*Ns.  tw: table exp(-2 pi i m / N), m < N,
+// possibly a strided view (stride tws) of a longer table.
+// ---------------------------------------------------------------------------
+template <typename T, int N, int S, int DIR>
+__device__ __forceinline__ void stage_compute(cx<T>* v, int t, const cx<T>* __restrict__ tw, int tws) {
+  constexpr int P = plan_p(N), TPL = N / P, R = plan_radix(N, S), B = P / R, NS = plan_ns(N, S);
+#pragma unroll
+  for (int b = 0; b < B; ++b) {
+    if constexpr (NS > 1) {
+      const int j = t + TPL * b;
+      const int k = j % NS;
+#pragma unroll
+      for (int r = 1; r < R; ++r) {
+        const cx<T> w = tw[(k * r * (N / (NS * R))) * tws];
+        v[b * R + r] = DIR < 0 ? cmul(v[b * R + r], w) : cmulc(v[b * R + r], w);
+      }
+    }
+    dft<T, R, DIR>(v + b * R);
+  }
+}
+
+// Output position of slot (b*R + r) of stage S for thread t.
+template <int N, int S>
+__device__ __forceinline__ int stage_out_pos(int t, int slot) {
+  constexpr int P = plan_p(N), TPL = N / P, R = plan_radix(N, S), NS = plan_ns(N, S);
+  const int b = slot / R, r = slot % R;
+  const int j = t + TPL * b;
+  return (j / NS) * NS * R + (j % NS) + r * NS;
+}
+// Input position of slot (b*R + r) of stage S for thread t.
+template <int N, int S>
+__device__ __forceinline__ int stage_in_pos(int t, int slot) {
+  constexpr int P = plan_p(N), TPL = N / P, R = plan_radix(N, S);
+  const int b = slot / R, r = slot % R;
+  return t + TPL * b + r * (N / R);
+}
+
+// Full line FFT on registers, exchanging through LDS between stages.
+// Lds is an accessor with operator()(pos) -> cx<T>& for this thread's line.
+// Starts with the input pattern (slot q <-> position t + TPL q) and ends with
+// the output pattern (slot s <-> position t + TPL out_q(s)).  Contains block
+// barriers when there is more than one stage: every thread of the block must
+// call it the same number of times.
+template <typename T, int N, int DIR, class Lds>
+__device__ __forceinline__ void line_fft(cx<T>* v, int t, Lds lds, const cx<T>* __restrict__ tw, int tws) {
+  constexpr int P = plan_p(N), NST = plan_stages(N);
+  stage_compute<T, N, 0, DIR>(v, t, tw, tws);
+  if constexpr (NST > 1) {
+    __syncthreads();
+#pragma unroll
+    for (int s = 0; s < P; ++s) lds(stage_out_pos<N, 0>(t, s)) = v[s];
+    __syncthreads();
+#pragma unroll
+    for (int s = 0; s < P; ++s) v[s] = lds(stage_in_pos<N, 1>(t, s));
+    stage_compute<T, N, 1, DIR>(v, t, tw, tws);
+  }
+  if constexpr (NST > 2) {
+    __syncthreads();
+#pragma unroll
+    for (int s = 0; s < P; ++s) lds(stage_out_pos<N, 1>(t, s)) = v[s];
+    __syncthreads();
+#pragma unroll
+    for (int s = 0; s < P; ++s) v[s] = lds(stage_in_pos<N, 2>(t, s));
+    stage_compute<T, N, 2, DIR>(v, t, tw, tws);
+  }
+}
+
+}  // namespace llg

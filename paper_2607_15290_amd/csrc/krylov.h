@@ -1,0 +1,53 @@
+// Launchers of the streaming vector kernels (krylov.hip) and the nodal
+// kernels of the steppers (nodal.hip).
+#pragma once
+#include "llg_internal.h"
+
+namespace llg {
+
+struct Coefs {
+  double c[64];
+  int n;
+};
+
+hipError_t reduce_partials(const Ctx& c, int nv, double* out, bool is_max, hipStream_t st);
+// out[i] = V_i . w  (i < nv; V_i = V + i*ld)
+hipError_t cgs_dots(const Ctx& c, const double* V, long long ld, int nv, const double* w, long long n, double* out,
+                    hipStream_t st);
+// w -= sum_i cf[i] V_i ; out[i] = V_i . w
+hipError_t cgs_update_dots(const Ctx& c, const double* V, long long ld, int nv, const double* cf, double* w,
+                           long long n, double* out, hipStream_t st);
+// out_vec = w - sum_i cf[i] V_i ; out_nrm2[0] = ||out_vec||^2
+hipError_t cgs_update_norm(const Ctx& c, const double* V, long long ld, int nv, const double* cf, const double* w,
+                           double* out_vec, long long n, double* out_nrm2, hipStream_t st);
+hipError_t scale_invnorm(double* y, const double* x, const double* nrm2, long long n, hipStream_t st);
+hipError_t axpby(long long n, double a, const double* x, double b, const double* y, double* out, hipStream_t st);
+hipError_t lincomb(long long n, const Coefs& cf, const double* V, long long ld, double* x, hipStream_t st);
+hipError_t lincomb(long long n, const Coefs& cf, const float* V, long long ld, double* x, hipStream_t st);
+hipError_t to_f32(long long n, const double* a, float* b, hipStream_t st);
+// out[0] = x.y (x.x if y null), out[1] = x.x
+hipError_t dot_and_norm(const Ctx& c, const double* x, const double* y, long long n, double* out, hipStream_t st);
+// out[0] = ||a - b||^2 (b may be null), out[1] = ||a||^2
+hipError_t diff_norms(const Ctx& c, const double* a, const double* b, long long n, double* out, hipStream_t st);
+
+// ---- nodal.hip ----
+// out[0] = min_i |m_i|^2, out[1] = 1 if any entry of m is non-finite
+hipError_t m_check(const Ctx& c, const double* m, double* out, hipStream_t st);
+// m <- (m + k v) / |m + k v| ; out[0] = max_i | |m_i| - 1 | after normalization
+hipError_t euler_update(const Ctx& c, double* m, const double* v, double k, double* out, hipStream_t st);
+// out = m + a v  (3 planes)
+hipError_t nodal_axpy3(const Ctx& c, const double* m, double a, const double* v, double* out, hipStream_t st);
+// max_i | |m_i| - 1 |
+hipError_t len_err(const Ctx& c, const double* m, double* out, hipStream_t st);
+// Midpoint diagnostics (see nodal.hip); out[0..6]
+hipError_t midpoint_diag(const Ctx& c, const NodalArgs& na, double alpha, double cexc, double k, const double* m0,
+                         const double* v, const double* r, const double* lm0, const double* lv, double* out,
+                         hipStream_t st);
+// Energy sums: out[0] = sum [cexc/2 m.lm - m.h]
+hipError_t energy_sum(const Ctx& c, const NodalArgs& na, double cexc, const double* m, const double* lm, double* out,
+                      hipStream_t st);
+// Adjoint helpers (nodal.hip)
+hipError_t adjoint_finish(const Ctx& c, const NodalArgs& na, const double* v, const double* r, const double* mu,
+                          const double* lmu, double* gbar, double* hbar_field, double* out_hsum, hipStream_t st);
+
+}  // namespace llg

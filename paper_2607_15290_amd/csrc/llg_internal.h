@@ -1,0 +1,58 @@
+// Host-side internals shared by the translation units of the library.
+#pragma once
+#include <hip/hip_runtime.h>
+
+#include <string>
+
+#include "../../include/llg.h"
+#include "pipeline.h"
+
+namespace llg {
+
+// Per-thread last error message (llg_last_error).
+void set_error(const std::string& msg);
+
+#define LLG_HIP_CHECK(expr)                                                            \
+  do {                                                                                 \
+    hipError_t e_ = (expr);                                                            \
+    if (e_ != hipSuccess) {                                                            \
+      ::llg::set_error(std::string(#expr) + ": " + hipGetErrorString(e_));             \
+      return LLG_EHIP;                                                                 \
+    }                                                                                  \
+  } while (0)
+
+// Number of blocks used by every streaming reduction (fixed per context so the
+// reduction order, and hence every reduced value, is bitwise reproducible).
+constexpr int kRedBlocks = 1024;
+constexpr int kRedThreads = 256;
+constexpr int kMaxDots = 64;
+
+struct Ctx {
+  int nx = 0, ny = 0, nz = 0, dim = 0, device = 0;
+  double h = 0, Lx = 0, Ly = 0, Lz = 0;
+  long long ng = 0;
+  SpecGeom geom{};
+  cx<double>* tw_d[3] = {nullptr, nullptr, nullptr};  // exp(-2 pi i m / n_axis)
+  cx<float>* tw_f[3] = {nullptr, nullptr, nullptr};
+  void* spec = nullptr;  // spectral scratch (complex double capacity)
+  size_t spec_bytes = 0;
+  double* partial = nullptr;  // kRedBlocks x kMaxDots reduction partials
+  double* dots = nullptr;     // kMaxDots reduced values (device)
+  double* dots2 = nullptr;    // second set (CGS2 re-orthogonalization)
+  double* scal = nullptr;     // small device scalars
+  double* host = nullptr;     // pinned host mirror (4 * kMaxDots doubles)
+};
+
+SymArgs sym_for(const Ctx& c, double a, double b, bool invert);
+
+// Launch one spectral pipeline (pipeline.h).  Defined per type combination
+// in the pipeline_*.hip translation units.
+template <typename T, typename TIn, typename TOut>
+hipError_t run_pipeline(const Ctx& c, int pro, int epi, const SymArgs& sym, const NodalArgs& na,
+                        const PipeIO<T, TIn, TOut>& io, hipStream_t st);
+
+// Axis passes (axis.hip).
+template <typename T>
+hipError_t launch_axis(const Ctx& c, int axis, int mode, const SymArgs& sym, cx<T>* spec, hipStream_t st);
+
+}  // namespace llg

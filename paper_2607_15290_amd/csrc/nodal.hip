@@ -1,0 +1,267 @@
+// Nodal kernels of the time steppers and their diagnostics.
+//
+//   euler_update   projected Euler update m <- (m + k v)/|m + k v| (Sec. 3.2)
+//   nodal_axpy3    frozen midpoint m^n + (k/2) v and the update m^n + k v
+//                  (Sec. 3.3, eq. "hatm")
+//   midpoint_diag  energies, ||v||^2 and the residual functionals rho(v) and
+//                  chi(r) of eq. "C-N" at the exact midpoint (Remark on the
+//                  effect of an inexact midpoint solve)
+//   adjoint_finish back-propagation through m^n of one midpoint step
+#include <cmath>
+
+#include "krylov.h"
+
+namespace llg {
+
+__device__ __forceinline__ double wsum(double v) {
+#pragma unroll
+  for (int off = 32; off > 0; off >>= 1) v += __shfl_xor(v, off, 64);
+  return v;
+}
+__device__ __forceinline__ double wmax(double v) {
+#pragma unroll
+  for (int off = 32; off > 0; off >>= 1) v = fmax(v, __shfl_xor(v, off, 64));
+  return v;
+}
+
+// op 0: sum, 1: max, 2: min
+template <int NV, int OP>
+__device__ __forceinline__ void bstore(double (&acc)[NV], double* __restrict__ partial) {
+  __shared__ double sm[kRedThreads / 64][NV];
+  const int lane = threadIdx.x & 63, w = threadIdx.x >> 6;
+#pragma unroll
+  for (int i = 0; i < NV; ++i) {
+    double s = acc[i];
+    if (OP == 0) s = wsum(s);
+    else if (OP == 1) s = wmax(s);
+    else s = -wmax(-s);
+    if (lane == 0) sm[w][i] = s;
+  }
+  __syncthreads();
+  if (threadIdx.x < NV) {
+    double s = sm[0][threadIdx.x];
+    for (int k = 1; k < kRedThreads / 64; ++k) {
+      const double o = sm[k][threadIdx.x];
+      s = OP == 0 ? s + o : (OP == 1 ? fmax(s, o) : fmin(s, o));
+    }
+    partial[blockIdx.x * kMaxDots + threadIdx.x] = s;
+  }
+}
+
+#define GRID_LOOP(e, n) \
+  for (long long e = (long long)blockIdx.x * blockDim.x + threadIdx.x; e < (n); e += (long long)gridDim.x * blockDim.x)
+
+__global__ __launch_bounds__(kRedThreads) void k_m_check(const double* __restrict__ m, long long ng,
+                                                        double* __restrict__ partial) {
+  double mn[1] = {INFINITY};
+  double bad[1] = {0.0};
+  GRID_LOOP(i, ng) {
+    const double a = m[i], b = m[ng + i], c = m[2 * ng + i];
+    const double n2 = a * a + b * b + c * c;
+    if (!isfinite(n2)) bad[0] = 1.0;
+    mn[0] = fmin(mn[0], n2);
+  }
+  bstore<1, 2>(mn, partial);
+  __syncthreads();
+  bstore<1, 1>(bad, partial + 1);
+}
+
+__global__ __launch_bounds__(kRedThreads) void k_euler_update(double* __restrict__ m, const double* __restrict__ v,
+                                                             double k, long long ng, double* __restrict__ partial) {
+  double mx[1] = {0.0};
+  GRID_LOOP(i, ng) {
+    double a = m[i] + k * v[i], b = m[ng + i] + k * v[ng + i], c = m[2 * ng + i] + k * v[2 * ng + i];
+    const double s = 1.0 / sqrt(a * a + b * b + c * c);
+    a *= s;
+    b *= s;
+    c *= s;
+    m[i] = a;
+    m[ng + i] = b;
+    m[2 * ng + i] = c;
+    mx[0] = fmax(mx[0], fabs(sqrt(a * a + b * b + c * c) - 1.0));
+  }
+  bstore<1, 1>(mx, partial);
+}
+
+__global__ void k_axpy3(const double* __restrict__ m, double a, const double* __restrict__ v,
+                        double* __restrict__ out, long long n) {
+  GRID_LOOP(i, n) out[i] = m[i] + a * v[i];
+}
+
+__global__ __launch_bounds__(kRedThreads) void k_len_err(const double* __restrict__ m, long long ng,
+                                                        double* __restrict__ partial) {
+  double mx[1] = {0.0};
+  GRID_LOOP(i, ng) {
+    const double a = m[i], b = m[ng + i], c = m[2 * ng + i];
+    mx[0] = fmax(mx[0], fabs(sqrt(a * a + b * b + c * c) - 1.0));
+  }
+  bstore<1, 1>(mx, partial);
+}
+
+__device__ __forceinline__ void field_at(const NodalArgs& na, long long ng, long long i, double (&h)[3]) {
+  h[0] = na.hu0;
+  h[1] = na.hu1;
+  h[2] = na.hu2;
+  if (na.hfield) {
+    h[0] += na.hfield[i];
+    h[1] += na.hfield[ng + i];
+    h[2] += na.hfield[2 * ng + i];
+  }
+}
+
+__global__ __launch_bounds__(kRedThreads) void k_midpoint_diag(NodalArgs na, double alpha, double cexc, double k,
+                                                              const double* __restrict__ m0,
+                                                              const double* __restrict__ v,
+                                                              const double* __restrict__ r,
+                                                              const double* __restrict__ lm0,
+                                                              const double* __restrict__ lv, long long ng,
+                                                              double* __restrict__ partial) {
+  double acc[5] = {0, 0, 0, 0, 0};
+  GRID_LOOP(i, ng) {
+    double h[3];
+    field_at(na, ng, i, h);
+    double a[3], vv[3], l0[3], l1[3], m1[3], mh[3], lmh[3];
+    for (int c = 0; c < 3; ++c) {
+      a[c] = m0[c * ng + i];
+      vv[c] = v[c * ng + i];
+      l0[c] = lm0[c * ng + i];
+      const double lvc = lv[c * ng + i];
+      m1[c] = a[c] + k * vv[c];
+      mh[c] = a[c] + 0.5 * k * vv[c];
+      l1[c] = l0[c] + k * lvc;
+      lmh[c] = l0[c] + 0.5 * k * lvc;
+    }
+    const double rr = r[i];
+    const double cr[3] = {mh[1] * vv[2] - mh[2] * vv[1], mh[2] * vv[0] - mh[0] * vv[2], mh[0] * vv[1] - mh[1] * vv[0]};
+    double e0 = 0, e1 = 0, v2 = 0, rho = 0, mv = 0;
+    for (int c = 0; c < 3; ++c) {
+      e0 += 0.5 * cexc * a[c] * l0[c] - a[c] * h[c];
+      e1 += 0.5 * cexc * m1[c] * l1[c] - m1[c] * h[c];
+      v2 += vv[c] * vv[c];
+      const double rv = alpha * vv[c] + cr[c] + na.chat * lmh[c] + mh[c] * rr - na.hs * h[c];
+      rho += rv * vv[c];
+      mv += vv[c] * mh[c];
+    }
+    acc[0] += e0;
+    acc[1] += e1;
+    acc[2] += v2;
+    acc[3] += rho;
+    acc[4] += mv * rr;
+  }
+  bstore<5, 0>(acc, partial);
+}
+
+__global__ __launch_bounds__(kRedThreads) void k_energy(NodalArgs na, double cexc, const double* __restrict__ m,
+                                                       const double* __restrict__ lm, long long ng,
+                                                       double* __restrict__ partial) {
+  double acc[1] = {0.0};
+  GRID_LOOP(i, ng) {
+    double h[3];
+    field_at(na, ng, i, h);
+    for (int c = 0; c < 3; ++c) acc[0] += 0.5 * cexc * m[c * ng + i] * lm[c * ng + i] - m[c * ng + i] * h[c];
+  }
+  bstore<1, 0>(acc, partial);
+}
+
+// gbar -= v x mu_v + C_hat L mu_v + r mu_v - v mu_r ; hbar_field += hs mu_v ; sums of hs mu_v
+__global__ __launch_bounds__(kRedThreads) void k_adjoint_finish(NodalArgs na, const double* __restrict__ v,
+                                                               const double* __restrict__ r,
+                                                               const double* __restrict__ mu,
+                                                               const double* __restrict__ lmu,
+                                                               double* __restrict__ gbar,
+                                                               double* __restrict__ hbar, long long ng,
+                                                               double* __restrict__ partial) {
+  double acc[3] = {0, 0, 0};
+  GRID_LOOP(i, ng) {
+    double vv[3], mv[3];
+    for (int c = 0; c < 3; ++c) {
+      vv[c] = v[c * ng + i];
+      mv[c] = mu[c * ng + i];
+    }
+    const double mr = mu[3 * ng + i], rr = r[i];
+    const double cr[3] = {vv[1] * mv[2] - vv[2] * mv[1], vv[2] * mv[0] - vv[0] * mv[2], vv[0] * mv[1] - vv[1] * mv[0]};
+    for (int c = 0; c < 3; ++c) {
+      gbar[c * ng + i] -= cr[c] + na.chat * lmu[c * ng + i] + rr * mv[c] - vv[c] * mr;
+      const double hb = na.hs * mv[c];
+      if (hbar) hbar[c * ng + i] += hb;
+      acc[c] += hb;
+    }
+  }
+  bstore<3, 0>(acc, partial);
+}
+
+__global__ __launch_bounds__(kRedThreads) void k_reduce_min_max(const double* __restrict__ partial, int nb,
+                                                               double* __restrict__ out) {
+  double mn[1] = {INFINITY}, mx[1] = {-INFINITY};
+  for (int b = threadIdx.x; b < nb; b += kRedThreads) {
+    mn[0] = fmin(mn[0], partial[b * kMaxDots]);
+    mx[0] = fmax(mx[0], partial[b * kMaxDots + 1]);
+  }
+  __shared__ double sm[2][kRedThreads / 64];
+  const double a = -wmax(-mn[0]), b = wmax(mx[0]);
+  if ((threadIdx.x & 63) == 0) {
+    sm[0][threadIdx.x >> 6] = a;
+    sm[1][threadIdx.x >> 6] = b;
+  }
+  __syncthreads();
+  if (threadIdx.x == 0) {
+    double x = sm[0][0], y = sm[1][0];
+    for (int w = 1; w < kRedThreads / 64; ++w) {
+      x = fmin(x, sm[0][w]);
+      y = fmax(y, sm[1][w]);
+    }
+    out[0] = x;
+    out[1] = y;
+  }
+}
+
+// ---- launchers --------------------------------------------------------------
+static inline unsigned grid_n(long long n) {
+  long long g = (n + 255) / 256;
+  if (g > 4096) g = 4096;
+  return (unsigned)(g < 1 ? 1 : g);
+}
+
+hipError_t m_check(const Ctx& c, const double* m, double* out, hipStream_t st) {
+  hipLaunchKernelGGL(k_m_check, dim3(kRedBlocks), dim3(kRedThreads), 0, st, m, c.ng, c.partial);
+  hipLaunchKernelGGL((k_reduce_min_max), dim3(1), dim3(kRedThreads), 0, st, c.partial, kRedBlocks, out);
+  return hipGetLastError();
+}
+
+hipError_t euler_update(const Ctx& c, double* m, const double* v, double k, double* out, hipStream_t st) {
+  hipLaunchKernelGGL(k_euler_update, dim3(kRedBlocks), dim3(kRedThreads), 0, st, m, v, k, c.ng, c.partial);
+  return reduce_partials(c, 1, out, true, st);
+}
+
+hipError_t nodal_axpy3(const Ctx& c, const double* m, double a, const double* v, double* out, hipStream_t st) {
+  hipLaunchKernelGGL(k_axpy3, dim3(grid_n(3 * c.ng)), dim3(256), 0, st, m, a, v, out, 3 * c.ng);
+  return hipGetLastError();
+}
+
+hipError_t len_err(const Ctx& c, const double* m, double* out, hipStream_t st) {
+  hipLaunchKernelGGL(k_len_err, dim3(kRedBlocks), dim3(kRedThreads), 0, st, m, c.ng, c.partial);
+  return reduce_partials(c, 1, out, true, st);
+}
+
+hipError_t midpoint_diag(const Ctx& c, const NodalArgs& na, double alpha, double cexc, double k, const double* m0,
+                         const double* v, const double* r, const double* lm0, const double* lv, double* out,
+                         hipStream_t st) {
+  hipLaunchKernelGGL(k_midpoint_diag, dim3(kRedBlocks), dim3(kRedThreads), 0, st, na, alpha, cexc, k, m0, v, r, lm0,
+                     lv, c.ng, c.partial);
+  return reduce_partials(c, 5, out, false, st);
+}
+
+hipError_t energy_sum(const Ctx& c, const NodalArgs& na, double cexc, const double* m, const double* lm, double* out,
+                      hipStream_t st) {
+  hipLaunchKernelGGL(k_energy, dim3(kRedBlocks), dim3(kRedThreads), 0, st, na, cexc, m, lm, c.ng, c.partial);
+  return reduce_partials(c, 1, out, false, st);
+}
+
+hipError_t adjoint_finish(const Ctx& c, const NodalArgs& na, const double* v, const double* r, const double* mu,
+                          const double* lmu, double* gbar, double* hbar_field, double* out_hsum, hipStream_t st) {
+  hipLaunchKernelGGL(k_adjoint_finish, dim3(kRedBlocks), dim3(kRedThreads), 0, st, na, v, r, mu, lmu, gbar,
+                     hbar_field, c.ng, c.partial);
+  return reduce_partials(c, 3, out_hsum, false, st);
+}
+
+}  // namespace llg

@@ -1,0 +1,81 @@
+// Spectral pipeline: layout, argument blocks, prologue / epilogue modes.
+//
+// A pipeline applies one real, even Fourier multiplier to three real grid
+// planes ("filtered fields") and combines the result node by node with other
+// planes.  Every operator of the hot path is such a pipeline:
+//
+//   matvec      A x         : filtered v with a + b|xi|^2, a = alpha,
+//                             b = theta k C_hat (Sec. 2.4, eq. "saddle point
+//                             system"), epilogue adds m x v + m r, -m.v
+//   apply       M^{-1} p    : filtered p_v with 1/(alpha + lambda + b|xi|^2)
+//                             (Algorithm 1), epilogue = closed-form 4x4
+//                             nodal inverse (eq. "inverse S")
+//   apply^T     M^{-T} p    : prologue = transposed nodal inverse, then
+//                             Algorithm 1
+//   fused       M^{-1} A x  : M2^{-1}[x + M1^{-1}((calS - lambda I) x)], an
+//                             identity because A = M1 + calS - lambda I
+//   rhs         C_hat Delta_N m + (1+alpha^2) h (Sec. 2.4, eq. "total system")
+//
+// Grid planes are SoA, node index i = x + nx (y + ny z).  Between passes the
+// three filtered fields live in one complex spectral buffer: each (y, z) row
+// holds three half spectra (kx = 0..nx/2) back to back, 3 (nx/2+1) complex
+// values, padded to a row stride rs that is a multiple of 16 elements.
+#pragma once
+#include "fft_core.h"
+
+namespace llg {
+
+struct SpecGeom {
+  int nx, ny, nz, nh;  // nh = nx / 2
+  int cs;              // 3 (nh + 1) valid columns per row
+  int rs;              // row stride in complex elements
+  long long ng;        // nodes
+};
+
+struct SymArgs {
+  double a, b;           // multiplier a + b |xi|^2 (or its inverse)
+  double cx, cy, cz;     // 2 pi / L per axis
+  double inv_ng;         // 1 / N_g
+  int invert;            // 1: use 1 / (a + b |xi|^2)
+};
+
+struct NodalArgs {
+  double lam;            // HSS shift lambda
+  double hs;             // 1 + alpha^2 (field scaling)
+  double chat;           // C_hat
+  double hu0, hu1, hu2;  // uniform applied field
+  double half_k;         // k / 2 (adjoint operator)
+  const double* hfield;  // optional spatial field (3 planes) or null
+};
+
+enum ProMode : int {
+  PRO_COPY3 = 0,   // u = in[0..2]
+  PRO_SMINUS = 1,  // u = m x v + m r - lambda v  (first half of the fused op)
+  PRO_M2T = 2,     // u = ((lambda I + S~) p)_v / (lambda^2 + |m|^2)
+};
+
+enum EpiMode : int {
+  EPI_STORE3 = 0,    // out[0..2] = F
+  EPI_APPLY = 1,     // out = M2^{-1} (F, p_r / lambda)
+  EPI_APPLY_T = 2,   // out = (F, ((lambda I + S~) p)_r / (lambda d))
+  EPI_MATVEC = 3,    // out = (F + m x v + m r, -m.v)
+  EPI_MATVEC_T = 4,  // out = (F - m x v - m r, m.v)
+  EPI_FUSED = 5,     // out = M2^{-1} (x + (F, (-m.v - lambda r) / lambda))
+  EPI_RHS = 6,       // out = (-C_hat F + (1+alpha^2) h, 0)
+  EPI_JT = 7,        // out = J^T mu of the midpoint residual (adjoint), F = H mu_v
+};
+
+// Pointers of one pipeline call.  "in" planes feed the prologue (and are
+// re-read by epilogues that need x or p); "m" is the magnetization the
+// nodal blocks are built on.
+template <typename T, typename TIn, typename TOut>
+struct PipeIO {
+  const TIn* in;     // 4 planes (x or p), or 3 planes for PRO_COPY3 + EPI_STORE3/RHS
+  const T* m;        // 3 planes (may be null for modes that do not use it)
+  TOut* out;         // 4 planes (3 for EPI_STORE3)
+  long long ng;
+  const T* aux_v;    // EPI_JT: forward velocity v (3 planes)
+  const T* aux_r;    // EPI_JT: forward multiplier (1 plane)
+};
+
+}  // namespace llg

@@ -1,0 +1,403 @@
+// Kernels of the spectral pipeline (see pipeline.h for the operators).
+//
+//   k_xfwd : per (y, z) row, compute the three fields to filter (prologue),
+//            real-to-complex DFT along x of each (half-length complex DFT of
+//            the even/odd packing plus the split step), write the row of three
+//            half spectra.
+//   k_axis : DFTs along y or z of W spectral columns at a time; the last
+//            axis pass of the pipeline runs forward DFT -> Fourier multiplier
+//            -> inverse DFT on the data while it is in registers.
+//   k_xinv : per row, complex-to-real inverse DFT along x of the three fields,
+//            then the nodal epilogue and the output write.
+//
+// In two dimensions a pipeline is k_xfwd, k_axis(y, fused), k_xinv; in three
+// it is k_xfwd, k_axis(y, fwd), k_axis(z, fused), k_axis(y, inv), k_xinv.
+#pragma once
+#include "pipeline.h"
+
+namespace llg {
+
+template <int NH>
+struct XCfg {
+  static constexpr int P = plan_p(NH);
+  static constexpr int TPL = NH / P;
+  static constexpr int LX = 64 / TPL;           // rows per block
+  static constexpr int NT = 192;                // 3 fields x LX rows x TPL
+  static constexpr int SL = NH + (NH >> 4) + 1; // LDS line stride (complex)
+};
+
+__device__ __forceinline__ int xphys(int pos) { return pos + (pos >> 4); }
+
+template <typename U>
+__device__ __forceinline__ void load2(const U* __restrict__ p, U& a, U& b) {
+  if constexpr (sizeof(U) == 8) {
+    const double2 t = *reinterpret_cast<const double2*>(p);
+    a = t.x;
+    b = t.y;
+  } else {
+    const float2 t = *reinterpret_cast<const float2*>(p);
+    a = t.x;
+    b = t.y;
+  }
+}
+
+template <typename U>
+__device__ __forceinline__ void store2(U* __restrict__ p, U a, U b) {
+  if constexpr (sizeof(U) == 8) {
+    *reinterpret_cast<double2*>(p) = double2{a, b};
+  } else {
+    *reinterpret_cast<float2*>(p) = float2{a, b};
+  }
+}
+
+// ---------------------------------------------------------------------------
+// Nodal algebra (Sec. 3.1, eqs. (S) and (Lambda); Sec. 3.2, eq. "inverse S")
+// ---------------------------------------------------------------------------
+template <typename T>
+struct V3 {
+  T x, y, z;
+};
+template <typename T>
+__device__ __forceinline__ V3<T> cross3(V3<T> a, V3<T> b) {
+  return {a.y * b.z - a.z * b.y, a.z * b.x - a.x * b.z, a.x * b.y - a.y * b.x};
+}
+template <typename T>
+__device__ __forceinline__ T dot3(V3<T> a, V3<T> b) {
+  return a.x * b.x + a.y * b.y + a.z * b.z;
+}
+
+// (S~ + lambda I)^{-1} (w, wr) = (lambda w - m x w - wr m, m.w + lambda wr) / (lambda^2 + |m|^2)
+template <typename T>
+__device__ __forceinline__ void shift_solve(V3<T> m, V3<T> w, T wr, T lam, V3<T>& zv, T& zr) {
+  const T inv_d = T(1) / (lam * lam + dot3(m, m));
+  const V3<T> c = cross3(m, w);
+  zv.x = (lam * w.x - c.x - wr * m.x) * inv_d;
+  zv.y = (lam * w.y - c.y - wr * m.y) * inv_d;
+  zv.z = (lam * w.z - c.z - wr * m.z) * inv_d;
+  zr = (dot3(m, w) + lam * wr) * inv_d;
+}
+// (S~ + lambda I)^{-T} (w, wr) = (lambda w + m x w + wr m, -m.w + lambda wr) / (lambda^2 + |m|^2)
+template <typename T>
+__device__ __forceinline__ void shift_solve_t(V3<T> m, V3<T> w, T wr, T lam, V3<T>& zv, T& zr) {
+  const T inv_d = T(1) / (lam * lam + dot3(m, m));
+  const V3<T> c = cross3(m, w);
+  zv.x = (lam * w.x + c.x + wr * m.x) * inv_d;
+  zv.y = (lam * w.y + c.y + wr * m.y) * inv_d;
+  zv.z = (lam * w.z + c.z + wr * m.z) * inv_d;
+  zr = (lam * wr - dot3(m, w)) * inv_d;
+}
+
+// ---------------------------------------------------------------------------
+// Prologue: values of the three filtered fields at nodes i and i+1.
+// ---------------------------------------------------------------------------
+template <typename T, typename TIn, int PRO>
+__device__ __forceinline__ void prologue(const TIn* __restrict__ in, const T* __restrict__ m, long long ng,
+                                         long long i, const NodalArgs& na, cx<T> (&u)[3]) {
+  if constexpr (PRO == PRO_COPY3) {
+#pragma unroll
+    for (int f = 0; f < 3; ++f) {
+      TIn a, b;
+      load2(in + f * ng + i, a, b);
+      u[f] = {T(a), T(b)};
+    }
+  } else {
+    TIn va[4], vb[4];
+#pragma unroll
+    for (int f = 0; f < 4; ++f) load2(in + f * ng + i, va[f], vb[f]);
+    T ma[3], mb[3];
+#pragma unroll
+    for (int f = 0; f < 3; ++f) load2(m + f * ng + i, ma[f], mb[f]);
+    const T lam = T(na.lam);
+#pragma unroll
+    for (int h = 0; h < 2; ++h) {
+      const TIn* vv = h ? vb : va;
+      const T* mm = h ? mb : ma;
+      V3<T> mv{mm[0], mm[1], mm[2]};
+      V3<T> v{T(vv[0]), T(vv[1]), T(vv[2])};
+      const T r = T(vv[3]);
+      V3<T> o;
+      if constexpr (PRO == PRO_SMINUS) {
+        const V3<T> c = cross3(mv, v);
+        o = {c.x + mv.x * r - lam * v.x, c.y + mv.y * r - lam * v.y, c.z + mv.z * r - lam * v.z};
+      } else {  // PRO_M2T
+        T orr;
+        shift_solve_t(mv, v, r, lam, o, orr);
+      }
+      if (h == 0) {
+        u[0].x = o.x;
+        u[1].x = o.y;
+        u[2].x = o.z;
+      } else {
+        u[0].y = o.x;
+        u[1].y = o.y;
+        u[2].y = o.z;
+      }
+    }
+  }
+}
+
+// ---------------------------------------------------------------------------
+// Epilogue at one node: F = filtered fields at this node; j = node index.
+// ---------------------------------------------------------------------------
+template <typename T, typename TIn, typename TOut, int EPI>
+__device__ __forceinline__ void epilogue_node(const PipeIO<T, TIn, TOut>& io, long long j, const T (&F)[3],
+                                              const NodalArgs& na, T (&o)[4]) {
+  const long long ng = io.ng;
+  const T lam = T(na.lam);
+  if constexpr (EPI == EPI_STORE3) {
+    o[0] = F[0];
+    o[1] = F[1];
+    o[2] = F[2];
+    o[3] = T(0);
+  } else if constexpr (EPI == EPI_RHS) {
+    T h0 = T(na.hu0), h1 = T(na.hu1), h2 = T(na.hu2);
+    if (na.hfield) {
+      h0 += T(na.hfield[j]);
+      h1 += T(na.hfield[ng + j]);
+      h2 += T(na.hfield[2 * ng + j]);
+    }
+    const T c = T(na.chat), hs = T(na.hs);
+    o[0] = -c * F[0] + hs * h0;
+    o[1] = -c * F[1] + hs * h1;
+    o[2] = -c * F[2] + hs * h2;
+    o[3] = T(0);
+  } else {
+    const V3<T> m{io.m[j], io.m[ng + j], io.m[2 * ng + j]};
+    const V3<T> v{T(io.in[j]), T(io.in[ng + j]), T(io.in[2 * ng + j])};
+    const T r = T(io.in[3 * ng + j]);
+    if constexpr (EPI == EPI_APPLY) {
+      V3<T> z;
+      T zr;
+      shift_solve(m, V3<T>{F[0], F[1], F[2]}, r / lam, lam, z, zr);
+      o[0] = z.x;
+      o[1] = z.y;
+      o[2] = z.z;
+      o[3] = zr;
+    } else if constexpr (EPI == EPI_APPLY_T) {
+      const T inv_d = T(1) / (lam * lam + dot3(m, m));
+      o[0] = F[0];
+      o[1] = F[1];
+      o[2] = F[2];
+      o[3] = (lam * r - dot3(m, v)) * inv_d / lam;
+    } else if constexpr (EPI == EPI_MATVEC || EPI == EPI_MATVEC_T) {
+      const V3<T> c = cross3(m, v);
+      const T sg = EPI == EPI_MATVEC ? T(1) : T(-1);
+      o[0] = F[0] + sg * (c.x + m.x * r);
+      o[1] = F[1] + sg * (c.y + m.y * r);
+      o[2] = F[2] + sg * (c.z + m.z * r);
+      o[3] = -sg * dot3(m, v);
+    } else if constexpr (EPI == EPI_JT) {
+      // J^T mu = (H mu_v - m^n x mu_v + (k/2) r_f mu_v - m^{n+1} mu_r, m_half . mu_v),
+      // m = m^n, (v_f, r_f) the forward solution, m^{n+1} = m^n + k v_f,
+      // m_half = m^n + (k/2) v_f; here v = mu_v and r = mu_r.
+      const T hk = T(na.half_k);
+      const V3<T> vf{io.aux_v[j], io.aux_v[ng + j], io.aux_v[2 * ng + j]};
+      const T rf = io.aux_r[j];
+      const V3<T> c = cross3(m, v);
+      const V3<T> m1{m.x + T(2) * hk * vf.x, m.y + T(2) * hk * vf.y, m.z + T(2) * hk * vf.z};
+      const V3<T> mh{m.x + hk * vf.x, m.y + hk * vf.y, m.z + hk * vf.z};
+      o[0] = F[0] - c.x + hk * rf * v.x - m1.x * r;
+      o[1] = F[1] - c.y + hk * rf * v.y - m1.y * r;
+      o[2] = F[2] - c.z + hk * rf * v.z - m1.z * r;
+      o[3] = dot3(mh, v);
+    } else {  // EPI_FUSED
+      const T ur = -dot3(m, v) - lam * r;
+      const V3<T> w{v.x + F[0], v.y + F[1], v.z + F[2]};
+      const T wr = r + ur / lam;
+      V3<T> z;
+      T zr;
+      shift_solve(m, w, wr, lam, z, zr);
+      o[0] = z.x;
+      o[1] = z.y;
+      o[2] = z.z;
+      o[3] = zr;
+    }
+  }
+}
+
+// ---------------------------------------------------------------------------
+// k_xfwd
+// ---------------------------------------------------------------------------
+template <typename T, typename TIn, int NH, int PRO>
+__global__ __launch_bounds__(192) void k_xfwd(const TIn* __restrict__ in, const T* __restrict__ m,
+                                              cx<T>* __restrict__ spec, SpecGeom g, NodalArgs na,
+                                              const cx<T>* __restrict__ twx) {
+  using C = XCfg<NH>;
+  __shared__ cx<T> lds[3 * C::LX * C::SL];
+  const int tid = threadIdx.x;
+  const long long nlines = (long long)g.ny * g.nz;
+  const long long line0 = (long long)blockIdx.x * C::LX;
+  constexpr int NX = 2 * NH;
+
+  for (int e = tid; e < C::LX * NH; e += C::NT) {
+    const int l = e / NH, xp = e % NH;
+    const long long line = line0 + l;
+    cx<T> u[3] = {{T(0), T(0)}, {T(0), T(0)}, {T(0), T(0)}};
+    if (line < nlines) prologue<T, TIn, PRO>(in, m, g.ng, line * NX + 2 * xp, na, u);
+#pragma unroll
+    for (int f = 0; f < 3; ++f) lds[(f * C::LX + l) * C::SL + xphys(xp)] = u[f];
+  }
+  __syncthreads();
+
+  const int t = tid % C::TPL, ln = tid / C::TPL;
+  cx<T>* line_lds = lds + ln * C::SL;
+  auto acc = [line_lds](int pos) -> cx<T>& { return line_lds[xphys(pos)]; };
+  cx<T> v[C::P];
+#pragma unroll
+  for (int q = 0; q < C::P; ++q) v[q] = acc(t + C::TPL * q);
+  line_fft<T, NH, -1>(v, t, acc, twx, 2);
+  __syncthreads();
+#pragma unroll
+  for (int s = 0; s < C::P; ++s) acc(t + C::TPL * out_q<NH>(s)) = v[s];
+  __syncthreads();
+
+  // split step: U[k] = E[k] + w^k O[k], E/O the DFTs of even/odd samples
+  constexpr int CS = 3 * (NH + 1);
+  for (int e = tid; e < C::LX * CS; e += C::NT) {
+    const int l = e / CS, col = e % CS;
+    const long long line = line0 + l;
+    if (line >= nlines) continue;
+    const int f = col / (NH + 1), k = col % (NH + 1);
+    const cx<T>* Z = lds + (f * C::LX + l) * C::SL;
+    const cx<T> a = Z[xphys(k == NH ? 0 : k)];
+    const cx<T> bc = Z[xphys(k == 0 ? 0 : NH - k)];
+    const cx<T> b{bc.x, -bc.y};
+    const cx<T> E{T(0.5) * (a.x + b.x), T(0.5) * (a.y + b.y)};
+    const cx<T> O{T(0.5) * (a.y - b.y), T(-0.5) * (a.x - b.x)};
+    const cx<T> w = twx[k];
+    spec[line * g.rs + col] = cadd(E, cmul(w, O));
+  }
+}
+
+// ---------------------------------------------------------------------------
+// k_xinv
+// ---------------------------------------------------------------------------
+template <typename T, typename TIn, typename TOut, int NH, int EPI>
+__global__ __launch_bounds__(192) void k_xinv(PipeIO<T, TIn, TOut> io, const cx<T>* __restrict__ spec,
+                                              SpecGeom g, NodalArgs na, const cx<T>* __restrict__ twx) {
+  using C = XCfg<NH>;
+  __shared__ cx<T> lds[3 * C::LX * C::SL];
+  const int tid = threadIdx.x;
+  const long long nlines = (long long)g.ny * g.nz;
+  const long long line0 = (long long)blockIdx.x * C::LX;
+  constexpr int NX = 2 * NH;
+  constexpr int CS = 3 * (NH + 1);
+
+  for (int e = tid; e < C::LX * CS; e += C::NT) {
+    const int l = e / CS, col = e % CS;
+    const long long line = line0 + l;
+    const int f = col / (NH + 1), k = col % (NH + 1);
+    lds[(f * C::LX + l) * C::SL + xphys(k)] = line < nlines ? spec[line * g.rs + col] : cx<T>{T(0), T(0)};
+  }
+  __syncthreads();
+
+  const int t = tid % C::TPL, ln = tid / C::TPL;
+  cx<T>* line_lds = lds + ln * C::SL;
+  auto acc = [line_lds](int pos) -> cx<T>& { return line_lds[xphys(pos)]; };
+  cx<T> v[C::P];
+#pragma unroll
+  for (int q = 0; q < C::P; ++q) {
+    // Z[k] = (U[k] + conj U[NH-k]) + i w^{-k} (U[k] - conj U[NH-k])
+    const int k = t + C::TPL * q;
+    const cx<T> a = acc(k);
+    const cx<T> bc = acc(NH - k);
+    const cx<T> e{a.x + bc.x, a.y - bc.y};
+    const cx<T> d{a.x - bc.x, a.y + bc.y};
+    const cx<T> o = cmulc(d, twx[k]);
+    v[q] = {e.x - o.y, e.y + o.x};
+  }
+  line_fft<T, NH, 1>(v, t, acc, twx, 2);
+  __syncthreads();
+#pragma unroll
+  for (int s = 0; s < C::P; ++s) acc(t + C::TPL * out_q<NH>(s)) = v[s];
+  __syncthreads();
+
+  for (int e = tid; e < C::LX * NH; e += C::NT) {
+    const int l = e / NH, xp = e % NH;
+    const long long line = line0 + l;
+    if (line >= nlines) continue;
+    const long long i = line * NX + 2 * xp;
+    cx<T> fz[3];
+#pragma unroll
+    for (int f = 0; f < 3; ++f) fz[f] = lds[(f * C::LX + l) * C::SL + xphys(xp)];
+    T o0[4], o1[4];
+    {
+      const T F0[3] = {fz[0].x, fz[1].x, fz[2].x};
+      epilogue_node<T, TIn, TOut, EPI>(io, i, F0, na, o0);
+      const T F1[3] = {fz[0].y, fz[1].y, fz[2].y};
+      epilogue_node<T, TIn, TOut, EPI>(io, i + 1, F1, na, o1);
+    }
+    constexpr int NOUT = EPI == EPI_STORE3 ? 3 : 4;
+#pragma unroll
+    for (int f = 0; f < NOUT; ++f) store2(io.out + f * io.ng + i, TOut(o0[f]), TOut(o1[f]));
+  }
+}
+
+// ---------------------------------------------------------------------------
+// k_axis: DFTs along y (axis 1) or z (axis 2).  MODE 0 forward, 1 inverse,
+// 2 forward -> multiplier -> inverse.
+// ---------------------------------------------------------------------------
+__host__ __device__ constexpr int axis_w(int n) { return n <= 16 ? 64 : (n >= 512 ? 4 : 16); }
+
+template <typename T, int N, int MODE>
+__global__ __launch_bounds__(axis_w(N) * (N / plan_p(N))) void k_axis(cx<T>* __restrict__ spec, SpecGeom g,
+                                                                      int axis, SymArgs sym,
+                                                                      const cx<T>* __restrict__ tw) {
+  constexpr int P = plan_p(N), TPL = N / P, W = axis_w(N);
+  __shared__ cx<T> lds[N * (W + 1)];
+  const int c = threadIdx.x % W, t = threadIdx.x / W;
+  const int col = blockIdx.x * W + c;
+  const int outer = blockIdx.y;
+  long long sp, so;
+  if (axis == 1) {
+    sp = g.rs;
+    so = (long long)g.rs * g.ny;
+  } else {
+    sp = (long long)g.rs * g.ny;
+    so = g.rs;
+  }
+  const bool valid = col < g.cs;
+  cx<T>* base = spec + outer * so + (valid ? col : 0);
+  cx<T> v[P];
+#pragma unroll
+  for (int q = 0; q < P; ++q) v[q] = valid ? base[(t + TPL * q) * sp] : cx<T>{T(0), T(0)};
+  cx<T>* col_lds = lds + c;
+  auto acc = [col_lds](int pos) -> cx<T>& { return col_lds[pos * (W + 1)]; };
+
+  if constexpr (MODE == 0 || MODE == 1) {
+    line_fft<T, N, MODE == 0 ? -1 : 1>(v, t, acc, tw, 1);
+  } else {
+    line_fft<T, N, -1>(v, t, acc, tw, 1);
+    // Fourier multiplier (a + b |xi|^2)^{+-1} / N_g
+    const int kx = col % (g.nh + 1);
+    const double xx = sym.cx * kx;
+    double base2 = xx * xx;
+    if (axis == 2) {
+      const int ky = outer < g.ny / 2 ? outer : outer - g.ny;
+      const double yy = sym.cy * ky;
+      base2 += yy * yy;
+    }
+    const double caxis = axis == 1 ? sym.cy : sym.cz;
+    cx<T> w[P];
+#pragma unroll
+    for (int s = 0; s < P; ++s) {
+      const int q = out_q<N>(s);
+      const int kp = t + TPL * q;
+      const int ks = kp < N / 2 ? kp : kp - N;
+      const double aa = caxis * ks;
+      const double lam2 = base2 + aa * aa;
+      double mult = sym.a + sym.b * lam2;
+      mult = sym.invert ? sym.inv_ng / mult : sym.inv_ng * mult;
+      w[q] = cscale(v[s], T(mult));
+    }
+    line_fft<T, N, 1>(w, t, acc, tw, 1);
+#pragma unroll
+    for (int s = 0; s < P; ++s) v[s] = w[s];
+  }
+  if (valid) {
+#pragma unroll
+    for (int s = 0; s < P; ++s) base[(t + TPL * out_q<N>(s)) * sp] = v[s];
+  }
+}
+
+}  // namespace llg

@@ -1,0 +1,99 @@
+// Host dispatch of one spectral pipeline: x-forward, axis passes, x-inverse.
+// Included by the per-precision translation units, which instantiate
+// run_pipeline for the type combinations they need.
+#pragma once
+#include "llg_internal.h"
+#include "pipeline_kernels.h"
+
+namespace llg {
+
+// Which (prologue, epilogue) modes exist for a type combination.  The mixed
+// combinations serve only the precision form: float32 apply reading float64
+// Krylov vectors, and float32 matvec writing float64 Krylov vectors.
+template <typename T, typename TIn, typename TOut>
+constexpr bool has_pro(int pro) {
+  if constexpr (std::is_same<T, TIn>::value && std::is_same<T, TOut>::value) return true;
+  else return pro == PRO_COPY3;
+}
+template <typename T, typename TIn, typename TOut>
+constexpr bool has_epi(int epi) {
+  if constexpr (std::is_same<T, TIn>::value && std::is_same<T, TOut>::value) return true;
+  else if constexpr (std::is_same<TIn, double>::value) return epi == EPI_APPLY;
+  else return epi == EPI_MATVEC;
+}
+
+template <typename T, typename TIn, typename TOut, int NH, int PRO>
+void launch_xfwd(const Ctx& c, const NodalArgs& na, const PipeIO<T, TIn, TOut>& io, hipStream_t st) {
+  if constexpr (has_pro<T, TIn, TOut>(PRO)) {
+    using C = XCfg<NH>;
+    const long long lines = (long long)c.ny * c.nz;
+    const unsigned grid = (unsigned)((lines + C::LX - 1) / C::LX);
+    const cx<T>* tw;
+    if constexpr (std::is_same<T, double>::value) tw = c.tw_d[0]; else tw = c.tw_f[0];
+    hipLaunchKernelGGL((k_xfwd<T, TIn, NH, PRO>), dim3(grid), dim3(C::NT), 0, st, io.in, io.m,
+                       reinterpret_cast<cx<T>*>(c.spec), c.geom, na, tw);
+  }
+}
+
+template <typename T, typename TIn, typename TOut, int NH, int EPI>
+void launch_xinv(const Ctx& c, const NodalArgs& na, const PipeIO<T, TIn, TOut>& io, hipStream_t st) {
+  if constexpr (has_epi<T, TIn, TOut>(EPI)) {
+    using C = XCfg<NH>;
+    const long long lines = (long long)c.ny * c.nz;
+    const unsigned grid = (unsigned)((lines + C::LX - 1) / C::LX);
+    const cx<T>* tw;
+    if constexpr (std::is_same<T, double>::value) tw = c.tw_d[0]; else tw = c.tw_f[0];
+    hipLaunchKernelGGL((k_xinv<T, TIn, TOut, NH, EPI>), dim3(grid), dim3(C::NT), 0, st, io,
+                       reinterpret_cast<const cx<T>*>(c.spec), c.geom, na, tw);
+  }
+}
+
+template <typename T, typename TIn, typename TOut, int NH>
+hipError_t run_nh(const Ctx& c, int pro, int epi, const SymArgs& sym, const NodalArgs& na,
+                  const PipeIO<T, TIn, TOut>& io, hipStream_t st) {
+  switch (pro) {
+    case PRO_COPY3: launch_xfwd<T, TIn, TOut, NH, PRO_COPY3>(c, na, io, st); break;
+    case PRO_SMINUS: launch_xfwd<T, TIn, TOut, NH, PRO_SMINUS>(c, na, io, st); break;
+    case PRO_M2T: launch_xfwd<T, TIn, TOut, NH, PRO_M2T>(c, na, io, st); break;
+    default: return hipErrorInvalidValue;
+  }
+  cx<T>* spec = reinterpret_cast<cx<T>*>(c.spec);
+  hipError_t e;
+  if (c.dim == 2) {
+    if ((e = launch_axis<T>(c, 1, 2, sym, spec, st)) != hipSuccess) return e;
+  } else {
+    if ((e = launch_axis<T>(c, 1, 0, sym, spec, st)) != hipSuccess) return e;
+    if ((e = launch_axis<T>(c, 2, 2, sym, spec, st)) != hipSuccess) return e;
+    if ((e = launch_axis<T>(c, 1, 1, sym, spec, st)) != hipSuccess) return e;
+  }
+  switch (epi) {
+    case EPI_STORE3: launch_xinv<T, TIn, TOut, NH, EPI_STORE3>(c, na, io, st); break;
+    case EPI_APPLY: launch_xinv<T, TIn, TOut, NH, EPI_APPLY>(c, na, io, st); break;
+    case EPI_APPLY_T: launch_xinv<T, TIn, TOut, NH, EPI_APPLY_T>(c, na, io, st); break;
+    case EPI_MATVEC: launch_xinv<T, TIn, TOut, NH, EPI_MATVEC>(c, na, io, st); break;
+    case EPI_MATVEC_T: launch_xinv<T, TIn, TOut, NH, EPI_MATVEC_T>(c, na, io, st); break;
+    case EPI_FUSED: launch_xinv<T, TIn, TOut, NH, EPI_FUSED>(c, na, io, st); break;
+    case EPI_RHS: launch_xinv<T, TIn, TOut, NH, EPI_RHS>(c, na, io, st); break;
+    case EPI_JT: launch_xinv<T, TIn, TOut, NH, EPI_JT>(c, na, io, st); break;
+    default: return hipErrorInvalidValue;
+  }
+  return hipGetLastError();
+}
+
+template <typename T, typename TIn, typename TOut>
+hipError_t run_pipeline(const Ctx& c, int pro, int epi, const SymArgs& sym, const NodalArgs& na,
+                        const PipeIO<T, TIn, TOut>& io, hipStream_t st) {
+  switch (c.geom.nh) {
+    case 2: return run_nh<T, TIn, TOut, 2>(c, pro, epi, sym, na, io, st);
+    case 4: return run_nh<T, TIn, TOut, 4>(c, pro, epi, sym, na, io, st);
+    case 8: return run_nh<T, TIn, TOut, 8>(c, pro, epi, sym, na, io, st);
+    case 16: return run_nh<T, TIn, TOut, 16>(c, pro, epi, sym, na, io, st);
+    case 32: return run_nh<T, TIn, TOut, 32>(c, pro, epi, sym, na, io, st);
+    case 64: return run_nh<T, TIn, TOut, 64>(c, pro, epi, sym, na, io, st);
+    case 128: return run_nh<T, TIn, TOut, 128>(c, pro, epi, sym, na, io, st);
+    case 256: return run_nh<T, TIn, TOut, 256>(c, pro, epi, sym, na, io, st);
+    default: return hipErrorInvalidValue;
+  }
+}
+
+}  // namespace llg

@@ -1,0 +1,66 @@
+"""Host-only checks of the C ABI: the library loads, exports every function
+include/llg.h declares, and rejects invalid arguments before touching a GPU."""
+
+import ctypes
+import os
+import re
+
+import pytest
+
+ROOT = os.path.dirname(os.path.dirname(os.path.abspath(__file__)))
+HEADER = os.path.join(ROOT, "include", "llg.h")
+
+
+def declared_functions():
+    text = open(HEADER).read()
+    text = re.sub(r"/\*.*?\*/", "", text, flags=re.S)
+    names = re.findall(r"^\s*(?:const\s+)?[A-Za-z_][A-Za-z0-9_]*\s*\*?\s*([a-z_][a-z0-9_]*)\s*\(", text, flags=re.M)
+    return sorted(set(n for n in names if n not in ("if", "while", "sizeof")))
+
+
+@pytest.fixture(scope="module")
+def lib():
+    from paper_2607_15290_amd import _lib
+    return _lib.load()
+
+
+def test_header_lists_the_five_path_entry_points():
+    names = declared_functions()
+    for n in ("llg_matvec", "fft_hss_apply", "gmres_solve", "llg_step_euler", "llg_step_midpoint"):
+        assert n in names
+
+
+def test_library_exports_every_declared_symbol(lib):
+    for name in declared_functions():
+        assert hasattr(lib, name), name
+
+
+def test_binding_signatures_cover_header():
+    from paper_2607_15290_amd import _lib
+    assert set(declared_functions()) == set(_lib.SIGNATURES)
+
+
+def test_ctx_create_rejects_bad_sizes(lib):
+    h = ctypes.c_void_p()
+    for nx, ny, nz, hh in [(3, 4, 1, 0.1), (4, 6, 1, 0.1), (1024, 4, 1, 0.1), (4, 4, 2, 0.1), (4, 4, 1, 0.0),
+                           (4, 4, 1, -1.0), (8, 8, 3, 0.1), (0, 8, 1, 0.1)]:
+        assert lib.llg_ctx_create(ctypes.byref(h), nx, ny, nz, hh, 0) == 1
+        assert h.value is None
+        assert len(lib.llg_last_error()) > 0
+    assert lib.llg_ctx_create(None, 8, 8, 1, 0.1, 0) == 1
+
+
+def test_entry_points_reject_null_context(lib):
+    from paper_2607_15290_amd import _lib
+    p = _lib.LLGParams()
+    p.alpha, p.cexc, p.dt, p.theta, p.shift = 0.1, 1.0, 1e-3, 1.0, 0.5
+    assert lib.llg_matvec(None, ctypes.byref(p), None, None, None, 0, None) == 1
+    assert lib.fft_hss_apply(None, ctypes.byref(p), None, None, None, 0, None) == 1
+    o = _lib.LLGSolverOpts()
+    o.restart, o.maxiter, o.rtol = 30, 100, 1e-10
+    assert lib.gmres_solve(None, ctypes.byref(p), None, None, None, ctypes.byref(o), None, None, 0, None) == 1
+    assert lib.llg_step_euler(None, ctypes.byref(p), None, None, None, ctypes.byref(o), None, None, 0, None) == 1
+    assert lib.llg_step_midpoint(None, ctypes.byref(p), None, None, None, 1e-10, 10, ctypes.byref(o), None, None,
+                                 0, None) == 1
+    assert lib.llg_workspace_bytes(None, 30, 0) == 0
+    assert lib.llg_ctx_destroy(None) == 0
