@@ -189,10 +189,34 @@ llg_status llg_step_midpoint_adjoint(llg_ctx* ctx, const llg_params* prm, const 
                                      const llg_solver_opts* opts, llg_solver_stats* stats, void* work,
                                      size_t work_bytes, void* stream);
 
+/* Right-hand side of one time step (Sec. 2.4, eq. "total system"; Sec. 3.3,
+ * eq. "C-N"): b = (C_hat Delta_N m + (1 + alpha^2) h, 0) with h the uniform
+ * plus spatial applied field.  m: 3 planes; b: 4 planes (last plane zeroed).
+ * Asynchronous. */
+llg_status llg_rhs(llg_ctx* ctx, const llg_params* prm, const double* m, double* b, void* stream);
+
 /* Discrete energy g_N(m) = |Omega|/N_g sum_i [cexc/2 m_i.(-Delta_N m)_i - m_i.h_i]
  * (exchange + Zeeman; Sec. 3.3, Proposition on the energy law).  Result to
  * the host double *energy.  Synchronizes. */
 llg_status llg_energy(llg_ctx* ctx, const llg_params* prm, const double* m, double* energy, void* stream);
+
+/* Instrumentation: per-kernel timing with HIP events.
+ * llg_profile_enable(ctx, 1) clears the record and from then on brackets
+ * every kernel the context launches with a pair of HIP events recorded on the
+ * launch stream, together with the algorithmic bytes of that launch (one
+ * read of its inputs and one write of its outputs); llg_profile_enable(ctx,
+ * 0) stops recording.  llg_profile_read synchronizes the recorded events and
+ * fills up to max_entries per-kernel totals, returning the number of kernel
+ * kinds seen (or -1 on error).  name points to a static string. */
+typedef struct {
+  const char* name;
+  int launches;
+  double total_ms;
+  double bytes;
+} llg_kernel_profile;
+
+llg_status llg_profile_enable(llg_ctx* ctx, int enable);
+int llg_profile_read(llg_ctx* ctx, llg_kernel_profile* out, int max_entries);
 
 /* Message describing the last error on this thread ("" if none). */
 const char* llg_last_error(void);

@@ -42,6 +42,11 @@ class LLGStepStats(ctypes.Structure):
                 ("v_norm2", ctypes.c_double)]
 
 
+class LLGKernelProfile(ctypes.Structure):
+    _fields_ = [("name", ctypes.c_char_p), ("launches", ctypes.c_int), ("total_ms", ctypes.c_double),
+                ("bytes", ctypes.c_double)]
+
+
 # name -> (restype, argtypes); mirrors include/llg.h
 P = ctypes.c_void_p
 I = ctypes.c_int
@@ -63,6 +68,9 @@ SIGNATURES = {
                                       ctypes.POINTER(LLGSolverOpts), ctypes.POINTER(LLGSolverStats), P,
                                       ctypes.c_size_t, P]),
     "llg_energy": (I, [P, ctypes.POINTER(LLGParams), P, c_double_p, P]),
+    "llg_rhs": (I, [P, ctypes.POINTER(LLGParams), P, P, P]),
+    "llg_profile_enable": (I, [P, I]),
+    "llg_profile_read": (I, [P, ctypes.POINTER(LLGKernelProfile), I]),
     "llg_last_error": (ctypes.c_char_p, []),
 }
 

@@ -14,6 +14,8 @@ static hipError_t axis_n(const Ctx& c, int axis, int mode, const SymArgs& sym, c
   const cx<T>* tw;
   if constexpr (std::is_same<T, double>::value) tw = c.tw_d[axis];
   else tw = c.tw_f[axis];
+  const double bytes = 2.0 * c.geom.cs * double(c.ny) * c.nz * 2 * sizeof(T);
+  ProfScope ps(c.prof, st, mode == 0 ? KK_AXIS_FWD : (mode == 1 ? KK_AXIS_INV : KK_AXIS_FUSED), bytes);
   switch (mode) {
     case 0: hipLaunchKernelGGL((k_axis<T, N, 0>), dim3(gx, gy), dim3(W * TPL), 0, st, spec, c.geom, axis, sym, tw); break;
     case 1: hipLaunchKernelGGL((k_axis<T, N, 1>), dim3(gx, gy), dim3(W * TPL), 0, st, spec, c.geom, axis, sym, tw); break;

@@ -21,6 +21,11 @@ struct llg_ctx {
 
 namespace llg {
 
+Profiler* profiler_new();
+void profiler_delete(Profiler* p);
+void profiler_enable(Profiler* p, bool on);
+int profiler_read(Profiler* p, llg_kernel_profile* out, int max_entries);
+
 static thread_local std::string g_err;
 void set_error(const std::string& msg) { g_err = msg; }
 
@@ -255,7 +260,7 @@ llg_status arnoldi_step(const Ctx& c, double* V, long long n4, int j, double* co
   const double nrm2 = hv[2 * kMaxDots];
   if (!is_fin(nrm2)) return fail(LLG_ENAN, "non-finite Arnoldi norm");
   col[j + 1] = std::sqrt(nrm2);
-  if (nrm2 > 0.0) CHK(scale_invnorm(w, w, c.scal, n4, st));
+  if (nrm2 > 0.0) CHK(scale_invnorm(c, w, w, c.scal, n4, st));
   return LLG_OK;
 }
 
@@ -284,7 +289,7 @@ llg_status gmres_left(const Ctx& c, const Op& A, const Op& M, const Op& MA, cons
   const double target = o.rtol * bnorm;
   if (o.use_x0) {
     CHK(A(x, w.r));
-    CHK(axpby(n4, 1.0, b, -1.0, w.r, w.r, st));
+    CHK(axpby(c, n4, 1.0, b, -1.0, w.r, w.r, st));
   } else {
     CHK(hipMemsetAsync(x, 0, sizeof(double) * n4, st));
     CHK(hipMemcpyAsync(w.r, b, sizeof(double) * n4, hipMemcpyDeviceToDevice, st));
@@ -313,7 +318,7 @@ llg_status gmres_left(const Ctx& c, const Op& A, const Op& M, const Op& MA, cons
     if (!is_fin(beta)) return fail(LLG_ENAN, "non-finite preconditioned residual");
     if (beta == 0.0) break;
     if (beta0 < 0) beta0 = beta;
-    CHK(scale_invnorm(w.V, w.V, c.scal + 1, n4, st));
+    CHK(scale_invnorm(c, w.V, w.V, c.scal + 1, n4, st));
     const double eta = target / rho;
     std::fill(hs.g.begin(), hs.g.end(), 0.0);
     hs.g[0] = beta;
@@ -329,9 +334,9 @@ llg_status gmres_left(const Ctx& c, const Op& A, const Op& M, const Op& MA, cons
     }
     Coefs y{};
     hs.solve(k, y);
-    CHK(lincomb(n4, y, w.V, n4, x, st));
+    CHK(lincomb(c, n4, y, w.V, n4, x, st));
     CHK(A(x, w.r));
-    CHK(axpby(n4, 1.0, b, -1.0, w.r, w.r, st));
+    CHK(axpby(c, n4, 1.0, b, -1.0, w.r, w.r, st));
     CHK(dot_and_norm(c, w.r, nullptr, n4, c.scal, st));
     CHK_STATUS(fetch(c, c.scal, 2, st, rn));
     rho = std::sqrt(rn[1]);
@@ -346,7 +351,7 @@ llg_status gmres_ir(const Ctx& c, const llg_params* p, const double* m, const do
                     const llg_solver_opts& o, Work& w, SolveResult& res, hipStream_t st) {
   const long long n4 = 4 * c.ng;
   const int R = o.restart;
-  CHK(to_f32(3 * c.ng, m, w.m32, st));
+  CHK(to_f32(c, 3 * c.ng, m, w.m32, st));
   const SymArgs sym_ap = sym_for(c, p->alpha + p->shift, hcoef(p), true);
   const SymArgs sym_mv = sym_for(c, p->alpha, hcoef(p), false);
   const NodalArgs na = nodal_for(p);
@@ -364,7 +369,7 @@ llg_status gmres_ir(const Ctx& c, const llg_params* p, const double* m, const do
   const double target = o.rtol * bnorm;
   if (o.use_x0) {
     CHK(op_matvec(c, p, m, x, w.r, false, st));
-    CHK(axpby(n4, 1.0, b, -1.0, w.r, w.r, st));
+    CHK(axpby(c, n4, 1.0, b, -1.0, w.r, w.r, st));
   } else {
     CHK(hipMemsetAsync(x, 0, sizeof(double) * n4, st));
     CHK(hipMemcpyAsync(w.r, b, sizeof(double) * n4, hipMemcpyDeviceToDevice, st));
@@ -385,7 +390,7 @@ llg_status gmres_ir(const Ctx& c, const llg_params* p, const double* m, const do
     if (res.outer >= o.max_outer || res.iters >= o.maxiter) break;
     res.outer++;
     res.cycles++;
-    CHK(axpby(n4, 1.0 / rho, w.r, 0.0, w.r, w.V, st));
+    CHK(axpby(c, n4, 1.0 / rho, w.r, 0.0, w.r, w.V, st));
     const double eta = std::max(o.inner_rtol, target / rho);
     std::fill(hs.g.begin(), hs.g.end(), 0.0);
     hs.g[0] = rho;
@@ -405,9 +410,9 @@ llg_status gmres_ir(const Ctx& c, const llg_params* p, const double* m, const do
     }
     Coefs y{};
     hs.solve(k, y);
-    CHK(lincomb(n4, y, w.Z, n4, x, st));
+    CHK(lincomb(c, n4, y, w.Z, n4, x, st));
     CHK(op_matvec(c, p, m, x, w.r, false, st));
-    CHK(axpby(n4, 1.0, b, -1.0, w.r, w.r, st));
+    CHK(axpby(c, n4, 1.0, b, -1.0, w.r, w.r, st));
     CHK(dot_and_norm(c, w.r, nullptr, n4, c.scal, st));
     CHK_STATUS(fetch(c, c.scal, 2, st, rn));
     rho = std::sqrt(rn[1]);
@@ -499,6 +504,7 @@ llg_status llg_ctx_create(llg_ctx** out, int nx, int ny, int nz, double h, int d
     llg_ctx_destroy(ctx);
     return fail(s, m);
   };
+  c.prof = profiler_new();
   if (hipMalloc(&c.spec, c.spec_bytes) != hipSuccess) return cleanup(LLG_ENOMEM, "spectral scratch allocation failed");
   if (hipMalloc(&c.partial, sizeof(double) * kRedBlocks * kMaxDots) != hipSuccess)
     return cleanup(LLG_ENOMEM, "reduction buffer allocation failed");
@@ -546,6 +552,7 @@ llg_status llg_ctx_destroy(llg_ctx* ctx) {
   if (c.partial) (void)hipFree(c.partial);
   if (c.dots) (void)hipFree(c.dots);
   if (c.host) (void)hipHostFree(c.host);
+  if (c.prof) profiler_delete(c.prof);
   delete ctx;
   return LLG_OK;
 }
@@ -553,6 +560,23 @@ llg_status llg_ctx_destroy(llg_ctx* ctx) {
 size_t llg_workspace_bytes(const llg_ctx* ctx, int restart, int prec) {
   if (!ctx || restart < 1 || restart > kMaxDots - 2 || (prec != LLG_FP64 && prec != LLG_FP32_IR)) return 0;
   return carve(ctx->c, restart, prec, nullptr).bytes;
+}
+
+llg_status llg_profile_enable(llg_ctx* ctx, int enable) {
+  if (!ctx || !ctx->c.prof) return fail(LLG_EARG, "null context");
+  profiler_enable(ctx->c.prof, enable != 0);
+  return LLG_OK;
+}
+
+int llg_profile_read(llg_ctx* ctx, llg_kernel_profile* out, int max_entries) {
+  if (!ctx || !ctx->c.prof || max_entries < 0) {
+    set_error("llg_profile_read: bad argument");
+    return -1;
+  }
+  if (ensure_device(ctx->c) != LLG_OK) return -1;
+  const int n = profiler_read(ctx->c.prof, out, max_entries);
+  if (n < 0) set_error("llg_profile_read: event query failed");
+  return n;
 }
 
 llg_status llg_matvec(llg_ctx* ctx, const llg_params* prm, const double* m, const double* x, double* y,
@@ -616,6 +640,14 @@ llg_status gmres_solve(llg_ctx* ctx, const llg_params* prm, const double* m, con
   const llg_status s = solve(c, prm, m, b, x, *opts, w, r, as_stream(stream));
   fill_stats(r, stats);
   return s;
+}
+
+llg_status llg_rhs(llg_ctx* ctx, const llg_params* prm, const double* m, double* b, void* stream) {
+  if (!ctx || !m || !b) return fail(LLG_EARG, "null argument");
+  CHK_STATUS(check_params(prm));
+  CHK_STATUS(ensure_device(ctx->c));
+  CHK(op_rhs(ctx->c, prm, m, b, as_stream(stream)));
+  return LLG_OK;
 }
 
 llg_status llg_energy(llg_ctx* ctx, const llg_params* prm, const double* m, double* energy, void* stream) {
@@ -786,7 +818,7 @@ llg_status llg_step_midpoint_adjoint(llg_ctx* ctx, const llg_params* prm, const 
   CHK(nodal_axpy3(c, m_n, 0.5 * k, v, w.mh, st));
   CHK_STATUS(check_m(c, w.mh, st));
   // rhs = (k gbar, 0)
-  CHK(axpby(3 * ng, k, gbar, 0.0, gbar, w.b, st));
+  CHK(axpby(c, 3 * ng, k, gbar, 0.0, gbar, w.b, st));
   CHK(hipMemsetAsync(w.b + 3 * ng, 0, sizeof(double) * ng, st));
   const SymArgs sym_h = sym_for(c, p2.alpha, hcoef(&p2), false);
   const NodalArgs na = nodal_for(&p2);

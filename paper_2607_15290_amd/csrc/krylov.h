@@ -20,11 +20,11 @@ hipError_t cgs_update_dots(const Ctx& c, const double* V, long long ld, int nv, 
 // out_vec = w - sum_i cf[i] V_i ; out_nrm2[0] = ||out_vec||^2
 hipError_t cgs_update_norm(const Ctx& c, const double* V, long long ld, int nv, const double* cf, const double* w,
                            double* out_vec, long long n, double* out_nrm2, hipStream_t st);
-hipError_t scale_invnorm(double* y, const double* x, const double* nrm2, long long n, hipStream_t st);
-hipError_t axpby(long long n, double a, const double* x, double b, const double* y, double* out, hipStream_t st);
-hipError_t lincomb(long long n, const Coefs& cf, const double* V, long long ld, double* x, hipStream_t st);
-hipError_t lincomb(long long n, const Coefs& cf, const float* V, long long ld, double* x, hipStream_t st);
-hipError_t to_f32(long long n, const double* a, float* b, hipStream_t st);
+hipError_t scale_invnorm(const Ctx& c, double* y, const double* x, const double* nrm2, long long n, hipStream_t st);
+hipError_t axpby(const Ctx& c, long long n, double a, const double* x, double b, const double* y, double* out, hipStream_t st);
+hipError_t lincomb(const Ctx& c, long long n, const Coefs& cf, const double* V, long long ld, double* x, hipStream_t st);
+hipError_t lincomb(const Ctx& c, long long n, const Coefs& cf, const float* V, long long ld, double* x, hipStream_t st);
+hipError_t to_f32(const Ctx& c, long long n, const double* a, float* b, hipStream_t st);
 // out[0] = x.y (x.x if y null), out[1] = x.x
 hipError_t dot_and_norm(const Ctx& c, const double* x, const double* y, long long n, double* out, hipStream_t st);
 // out[0] = ||a - b||^2 (b may be null), out[1] = ||a||^2

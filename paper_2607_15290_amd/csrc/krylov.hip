@@ -202,6 +202,7 @@ static inline unsigned grid_for(long long n) {
 }
 
 hipError_t reduce_partials(const Ctx& c, int nv, double* out, bool is_max, hipStream_t st) {
+  ProfScope ps(c.prof, st, KK_REDUCE, 8.0 * kRedBlocks * nv);
   if (is_max)
     hipLaunchKernelGGL((k_reduce<true>), dim3(nv), dim3(kRedThreads), 0, st, c.partial, kRedBlocks, out);
   else
@@ -215,10 +216,13 @@ static void mdot_t(const Ctx& c, const double* V, long long ld, int nv, const do
 }
 hipError_t cgs_dots(const Ctx& c, const double* V, long long ld, int nv, const double* w, long long n, double* out,
                     hipStream_t st) {
+  {
+  ProfScope ps(c.prof, st, KK_CGS_DOTS, 8.0 * n * (nv + 1));
   if (nv <= 8) mdot_t<8>(c, V, ld, nv, w, n, st);
   else if (nv <= 16) mdot_t<16>(c, V, ld, nv, w, n, st);
   else if (nv <= 32) mdot_t<32>(c, V, ld, nv, w, n, st);
   else mdot_t<64>(c, V, ld, nv, w, n, st);
+  }
   return reduce_partials(c, nv, out, false, st);
 }
 
@@ -229,10 +233,13 @@ static void upd_t(const Ctx& c, const double* V, long long ld, int nv, const dou
 }
 hipError_t cgs_update_dots(const Ctx& c, const double* V, long long ld, int nv, const double* cf, double* w,
                            long long n, double* out, hipStream_t st) {
+  {
+  ProfScope ps(c.prof, st, KK_CGS_UPDATE_DOTS, 8.0 * n * (nv + 2));
   if (nv <= 8) upd_t<8>(c, V, ld, nv, cf, w, n, st);
   else if (nv <= 16) upd_t<16>(c, V, ld, nv, cf, w, n, st);
   else if (nv <= 32) upd_t<32>(c, V, ld, nv, cf, w, n, st);
   else upd_t<64>(c, V, ld, nv, cf, w, n, st);
+  }
   return reduce_partials(c, nv, out, false, st);
 }
 
@@ -244,44 +251,61 @@ static void updn_t(const Ctx& c, const double* V, long long ld, int nv, const do
 }
 hipError_t cgs_update_norm(const Ctx& c, const double* V, long long ld, int nv, const double* cf, const double* w,
                            double* out_vec, long long n, double* out_nrm2, hipStream_t st) {
+  {
+  ProfScope ps(c.prof, st, KK_CGS_UPDATE_NORM, 8.0 * n * (nv + 2));
   if (nv <= 8) updn_t<8>(c, V, ld, nv, cf, w, out_vec, n, st);
   else if (nv <= 16) updn_t<16>(c, V, ld, nv, cf, w, out_vec, n, st);
   else if (nv <= 32) updn_t<32>(c, V, ld, nv, cf, w, out_vec, n, st);
   else updn_t<64>(c, V, ld, nv, cf, w, out_vec, n, st);
+  }
   return reduce_partials(c, 1, out_nrm2, false, st);
 }
 
-hipError_t scale_invnorm(double* y, const double* x, const double* nrm2, long long n, hipStream_t st) {
+hipError_t scale_invnorm(const Ctx& c, double* y, const double* x, const double* nrm2, long long n, hipStream_t st) {
+  ProfScope ps(c.prof, st, KK_SCALE, 16.0 * n);
   hipLaunchKernelGGL(k_scale_invnorm, dim3(grid_for(n)), dim3(256), 0, st, y, x, nrm2, n);
   return hipGetLastError();
 }
 
-hipError_t axpby(long long n, double a, const double* x, double b, const double* y, double* out, hipStream_t st) {
+hipError_t axpby(const Ctx& c, long long n, double a, const double* x, double b, const double* y, double* out,
+                 hipStream_t st) {
+  ProfScope ps(c.prof, st, KK_AXPBY, 24.0 * n);
   hipLaunchKernelGGL(k_axpby, dim3(grid_for(n)), dim3(256), 0, st, n, a, x, b, y, out);
   return hipGetLastError();
 }
 
-hipError_t lincomb(long long n, const Coefs& cf, const double* V, long long ld, double* x, hipStream_t st) {
+hipError_t lincomb(const Ctx& c, long long n, const Coefs& cf, const double* V, long long ld, double* x,
+                   hipStream_t st) {
+  ProfScope ps(c.prof, st, KK_LINCOMB, double(n) * (8.0 * cf.n + 16.0));
   hipLaunchKernelGGL((k_lincomb<double>), dim3(grid_for(n)), dim3(256), 0, st, n, cf, V, ld, x);
   return hipGetLastError();
 }
-hipError_t lincomb(long long n, const Coefs& cf, const float* V, long long ld, double* x, hipStream_t st) {
+hipError_t lincomb(const Ctx& c, long long n, const Coefs& cf, const float* V, long long ld, double* x,
+                   hipStream_t st) {
+  ProfScope ps(c.prof, st, KK_LINCOMB, double(n) * (4.0 * cf.n + 16.0));
   hipLaunchKernelGGL((k_lincomb<float>), dim3(grid_for(n)), dim3(256), 0, st, n, cf, V, ld, x);
   return hipGetLastError();
 }
 
-hipError_t to_f32(long long n, const double* a, float* b, hipStream_t st) {
+hipError_t to_f32(const Ctx& c, long long n, const double* a, float* b, hipStream_t st) {
+  ProfScope ps(c.prof, st, KK_CONVERT, 12.0 * n);
   hipLaunchKernelGGL((k_convert<double, float>), dim3(grid_for(n)), dim3(256), 0, st, n, a, b);
   return hipGetLastError();
 }
 
 hipError_t dot_and_norm(const Ctx& c, const double* x, const double* y, long long n, double* out, hipStream_t st) {
+  {
+  ProfScope ps(c.prof, st, KK_DOT2, 8.0 * n * (y ? 2 : 1));
   hipLaunchKernelGGL(k_dot2, dim3(kRedBlocks), dim3(kRedThreads), 0, st, x, y, n, c.partial);
+  }
   return reduce_partials(c, 2, out, false, st);
 }
 
 hipError_t diff_norms(const Ctx& c, const double* a, const double* b, long long n, double* out, hipStream_t st) {
+  {
+  ProfScope ps(c.prof, st, KK_DOT2, 8.0 * n * (b ? 2 : 1));
   hipLaunchKernelGGL(k_diffnorm, dim3(kRedBlocks), dim3(kRedThreads), 0, st, a, b, n, c.partial);
+  }
   return reduce_partials(c, 2, out, false, st);
 }
 

@@ -27,7 +27,27 @@ constexpr int kRedBlocks = 1024;
 constexpr int kRedThreads = 256;
 constexpr int kMaxDots = 64;
 
+// Kernel kinds known to the event profiler.
+enum KernelKind : int {
+  KK_XFWD = 0, KK_AXIS_FWD, KK_AXIS_FUSED, KK_AXIS_INV, KK_XINV, KK_CGS_DOTS, KK_CGS_UPDATE_DOTS,
+  KK_CGS_UPDATE_NORM, KK_REDUCE, KK_SCALE, KK_AXPBY, KK_LINCOMB, KK_CONVERT, KK_DOT2, KK_NODAL, KK_COUNT
+};
+const char* kernel_kind_name(int k);
+
+struct Profiler;
+// Bracket one launch with events when the context's profiler is on.
+struct ProfScope {
+  Profiler* p;
+  hipStream_t st;
+  int kind;
+  double bytes;
+  hipEvent_t a;
+  ProfScope(Profiler* prof, hipStream_t s, int k, double b);
+  ~ProfScope();
+};
+
 struct Ctx {
+  Profiler* prof = nullptr;
   int nx = 0, ny = 0, nz = 0, dim = 0, device = 0;
   double h = 0, Lx = 0, Ly = 0, Lz = 0;
   long long ng = 0;

@@ -223,45 +223,80 @@ static inline unsigned grid_n(long long n) {
 }
 
 hipError_t m_check(const Ctx& c, const double* m, double* out, hipStream_t st) {
+  hipError_t e_ = hipSuccess;
+  {
+  ProfScope ps(c.prof, st, KK_NODAL, 0.0);
   hipLaunchKernelGGL(k_m_check, dim3(kRedBlocks), dim3(kRedThreads), 0, st, m, c.ng, c.partial);
   hipLaunchKernelGGL((k_reduce_min_max), dim3(1), dim3(kRedThreads), 0, st, c.partial, kRedBlocks, out);
-  return hipGetLastError();
+  e_ = hipGetLastError();
+  }
+  return e_;
 }
 
 hipError_t euler_update(const Ctx& c, double* m, const double* v, double k, double* out, hipStream_t st) {
+  hipError_t e_ = hipSuccess;
+  {
+  ProfScope ps(c.prof, st, KK_NODAL, 0.0);
   hipLaunchKernelGGL(k_euler_update, dim3(kRedBlocks), dim3(kRedThreads), 0, st, m, v, k, c.ng, c.partial);
-  return reduce_partials(c, 1, out, true, st);
+  e_ = reduce_partials(c, 1, out, true, st);
+  }
+  return e_;
 }
 
 hipError_t nodal_axpy3(const Ctx& c, const double* m, double a, const double* v, double* out, hipStream_t st) {
+  hipError_t e_ = hipSuccess;
+  {
+  ProfScope ps(c.prof, st, KK_NODAL, 0.0);
   hipLaunchKernelGGL(k_axpy3, dim3(grid_n(3 * c.ng)), dim3(256), 0, st, m, a, v, out, 3 * c.ng);
-  return hipGetLastError();
+  e_ = hipGetLastError();
+  }
+  return e_;
 }
 
 hipError_t len_err(const Ctx& c, const double* m, double* out, hipStream_t st) {
+  hipError_t e_ = hipSuccess;
+  {
+  ProfScope ps(c.prof, st, KK_NODAL, 0.0);
   hipLaunchKernelGGL(k_len_err, dim3(kRedBlocks), dim3(kRedThreads), 0, st, m, c.ng, c.partial);
-  return reduce_partials(c, 1, out, true, st);
+  e_ = reduce_partials(c, 1, out, true, st);
+  }
+  return e_;
 }
 
 hipError_t midpoint_diag(const Ctx& c, const NodalArgs& na, double alpha, double cexc, double k, const double* m0,
                          const double* v, const double* r, const double* lm0, const double* lv, double* out,
                          hipStream_t st) {
+  hipError_t e_ = hipSuccess;
+  {
+  ProfScope ps(c.prof, st, KK_NODAL, 0.0);
   hipLaunchKernelGGL(k_midpoint_diag, dim3(kRedBlocks), dim3(kRedThreads), 0, st, na, alpha, cexc, k, m0, v, r, lm0,
                      lv, c.ng, c.partial);
-  return reduce_partials(c, 5, out, false, st);
+  e_ = reduce_partials(c, 5, out, false, st);
+  }
+  return e_;
 }
 
 hipError_t energy_sum(const Ctx& c, const NodalArgs& na, double cexc, const double* m, const double* lm, double* out,
                       hipStream_t st) {
+  hipError_t e_ = hipSuccess;
+  {
+  ProfScope ps(c.prof, st, KK_NODAL, 0.0);
   hipLaunchKernelGGL(k_energy, dim3(kRedBlocks), dim3(kRedThreads), 0, st, na, cexc, m, lm, c.ng, c.partial);
-  return reduce_partials(c, 1, out, false, st);
+  e_ = reduce_partials(c, 1, out, false, st);
+  }
+  return e_;
 }
 
 hipError_t adjoint_finish(const Ctx& c, const NodalArgs& na, const double* v, const double* r, const double* mu,
                           const double* lmu, double* gbar, double* hbar_field, double* out_hsum, hipStream_t st) {
+  hipError_t e_ = hipSuccess;
+  {
+  ProfScope ps(c.prof, st, KK_NODAL, 0.0);
   hipLaunchKernelGGL(k_adjoint_finish, dim3(kRedBlocks), dim3(kRedThreads), 0, st, na, v, r, mu, lmu, gbar,
                      hbar_field, c.ng, c.partial);
-  return reduce_partials(c, 3, out_hsum, false, st);
+  e_ = reduce_partials(c, 3, out_hsum, false, st);
+  }
+  return e_;
 }
 
 }  // namespace llg

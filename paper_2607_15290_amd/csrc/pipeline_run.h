@@ -30,6 +30,8 @@ void launch_xfwd(const Ctx& c, const NodalArgs& na, const PipeIO<T, TIn, TOut>& 
     const unsigned grid = (unsigned)((lines + C::LX - 1) / C::LX);
     const cx<T>* tw;
     if constexpr (std::is_same<T, double>::value) tw = c.tw_d[0]; else tw = c.tw_f[0];
+    const double in_b = PRO == PRO_COPY3 ? 3.0 * sizeof(TIn) : 4.0 * sizeof(TIn) + 3.0 * sizeof(T);
+    ProfScope ps(c.prof, st, KK_XFWD, double(c.ng) * in_b + double(c.geom.cs) * lines * 2 * sizeof(T));
     hipLaunchKernelGGL((k_xfwd<T, TIn, NH, PRO>), dim3(grid), dim3(C::NT), 0, st, io.in, io.m,
                        reinterpret_cast<cx<T>*>(c.spec), c.geom, na, tw);
   }
@@ -43,6 +45,13 @@ void launch_xinv(const Ctx& c, const NodalArgs& na, const PipeIO<T, TIn, TOut>& 
     const unsigned grid = (unsigned)((lines + C::LX - 1) / C::LX);
     const cx<T>* tw;
     if constexpr (std::is_same<T, double>::value) tw = c.tw_d[0]; else tw = c.tw_f[0];
+    double node_b = 0;  // per-node bytes of the epilogue reads and writes
+    if (EPI == EPI_STORE3) node_b = 3.0 * sizeof(TOut);
+    else if (EPI == EPI_RHS) node_b = 4.0 * sizeof(TOut) + (na.hfield ? 24.0 : 0.0);
+    else if (EPI == EPI_APPLY) node_b = 1.0 * sizeof(TIn) + 3.0 * sizeof(T) + 4.0 * sizeof(TOut);
+    else if (EPI == EPI_JT) node_b = 4.0 * sizeof(TIn) + 7.0 * sizeof(T) + 4.0 * sizeof(TOut);
+    else node_b = 4.0 * sizeof(TIn) + 3.0 * sizeof(T) + 4.0 * sizeof(TOut);
+    ProfScope ps(c.prof, st, KK_XINV, double(c.ng) * node_b + double(c.geom.cs) * lines * 2 * sizeof(T));
     hipLaunchKernelGGL((k_xinv<T, TIn, TOut, NH, EPI>), dim3(grid), dim3(C::NT), 0, st, io,
                        reinterpret_cast<const cx<T>*>(c.spec), c.geom, na, tw);
   }

@@ -1,0 +1,94 @@
+// Event profiler of the context: pairs of HIP events around kernel launches,
+// aggregated per kernel kind with the launches' algorithmic bytes.
+#include <hip/hip_runtime.h>
+
+#include <vector>
+
+#include "llg_internal.h"
+
+namespace llg {
+
+struct Profiler {
+  bool on = false;
+  struct Rec {
+    int kind;
+    hipEvent_t a, b;
+    double bytes;
+  };
+  std::vector<Rec> recs;
+  std::vector<hipEvent_t> pool;
+  hipEvent_t take() {
+    if (!pool.empty()) {
+      hipEvent_t e = pool.back();
+      pool.pop_back();
+      return e;
+    }
+    hipEvent_t e = nullptr;
+    if (hipEventCreate(&e) != hipSuccess) return nullptr;
+    return e;
+  }
+  void recycle() {
+    for (auto& r : recs) {
+      pool.push_back(r.a);
+      pool.push_back(r.b);
+    }
+    recs.clear();
+  }
+  ~Profiler() {
+    recycle();
+    for (auto e : pool) (void)hipEventDestroy(e);
+  }
+};
+
+static const char* kNames[KK_COUNT] = {"xfwd",      "axis_fwd",          "axis_fused",        "axis_inv",
+                                       "xinv",      "cgs_dots",          "cgs_update_dots",   "cgs_update_norm",
+                                       "reduce",    "scale",             "axpby",             "lincomb",
+                                       "convert",   "dot2",              "nodal"};
+
+const char* kernel_kind_name(int k) { return (k >= 0 && k < KK_COUNT) ? kNames[k] : "?"; }
+
+ProfScope::ProfScope(Profiler* prof, hipStream_t s, int k, double b) : p(prof), st(s), kind(k), bytes(b), a(nullptr) {
+  if (p && p->on) {
+    a = p->take();
+    if (a) (void)hipEventRecord(a, st);
+  }
+}
+
+ProfScope::~ProfScope() {
+  if (p && p->on && a) {
+    hipEvent_t b = p->take();
+    if (b) {
+      (void)hipEventRecord(b, st);
+      p->recs.push_back({kind, a, b, bytes});
+    }
+  }
+}
+
+Profiler* profiler_new() { return new Profiler(); }
+void profiler_delete(Profiler* p) { delete p; }
+void profiler_enable(Profiler* p, bool on) {
+  if (on) p->recycle();
+  p->on = on;
+}
+
+int profiler_read(Profiler* p, llg_kernel_profile* out, int max_entries) {
+  int launches[KK_COUNT] = {0};
+  double ms[KK_COUNT] = {0}, bytes[KK_COUNT] = {0};
+  for (auto& r : p->recs) {
+    if (hipEventSynchronize(r.b) != hipSuccess) return -1;
+    float t = 0;
+    if (hipEventElapsedTime(&t, r.a, r.b) != hipSuccess) return -1;
+    launches[r.kind]++;
+    ms[r.kind] += t;
+    bytes[r.kind] += r.bytes;
+  }
+  int n = 0;
+  for (int k = 0; k < KK_COUNT; ++k) {
+    if (!launches[k]) continue;
+    if (out && n < max_entries) out[n] = {kNames[k], launches[k], ms[k], bytes[k]};
+    n++;
+  }
+  return n;
+}
+
+}  // namespace llg

@@ -239,9 +239,34 @@ def llg_step_midpoint_adjoint(ctx, params, m_n, v, lam, gbar, hbar_field=None, h
     return [hu[0], hu[1], hu[2]], stats
 
 
+def llg_rhs(ctx, params, m, b=None):
+    """b = (C_hat Delta_N m + (1+alpha^2) h, 0).  See llg_rhs in include/llg.h."""
+    b = ctx.new(4) if b is None else b
+    pr = params.c_struct()
+    _check(ctx.lib.llg_rhs(ctx.handle, ctypes.byref(pr), ctx.check(m, 3, name="m"), ctx.check(b, 4, name="b"),
+                           ctx.stream()), "llg_rhs")
+    return b
+
+
 def llg_energy(ctx, params, m):
     e = ctypes.c_double()
     pr = params.c_struct()
     _check(ctx.lib.llg_energy(ctx.handle, ctypes.byref(pr), ctx.check(m, 3, name="m"), ctypes.byref(e), ctx.stream()),
            "llg_energy")
     return e.value
+
+
+def llg_profile_enable(ctx, enable=True):
+    """Start (clear) or stop per-kernel HIP-event timing in the library."""
+    _check(ctx.lib.llg_profile_enable(ctx.handle, int(bool(enable))), "llg_profile_enable")
+
+
+def llg_profile_read(ctx):
+    """Per-kernel totals recorded since llg_profile_enable:
+    {name: dict(launches, total_ms, bytes)}."""
+    buf = (L.LLGKernelProfile * 64)()
+    n = ctx.lib.llg_profile_read(ctx.handle, buf, 64)
+    if n < 0:
+        raise LLGError(6, "llg_profile_read")
+    return {buf[i].name.decode(): dict(launches=buf[i].launches, total_ms=buf[i].total_ms, bytes=buf[i].bytes)
+            for i in range(min(n, 64))}
