@@ -83,6 +83,10 @@ typedef struct {
   double rtol;       /* accept when ||b - A x||_2 <= rtol ||b||_2 */
   double inner_rtol; /* relative tolerance of each inner FGMRES cycle (FP32_IR) */
   int prec;          /* llg_precision */
+  int orth;          /* Arnoldi orthogonalization: 0 = CGS2 with the
+                        re-orthogonalization delayed by one iteration (two
+                        streaming passes, restart <= 31; default), 1 = CGS2 in
+                        three passes */
 } llg_solver_opts;
 
 typedef struct {

@@ -69,6 +69,8 @@ llg_status check_opts(const llg_solver_opts* o) {
   if (o->maxiter < 1) return fail(LLG_EARG, "maxiter must be >= 1");
   if (!is_fin(o->rtol) || o->rtol <= 0 || o->rtol >= 1) return fail(LLG_EARG, "rtol must be in (0, 1)");
   if (o->prec != LLG_FP64 && o->prec != LLG_FP32_IR) return fail(LLG_EARG, "unknown precision");
+  if (o->orth != 0 && o->orth != 1) return fail(LLG_EARG, "orth must be 0 (delayed CGS2) or 1 (CGS2)");
+  if (o->orth == 0 && o->restart > 31) return fail(LLG_EARG, "delayed CGS2 supports restart <= 31");
   if (o->prec == LLG_FP32_IR) {
     if (o->max_outer < 1) return fail(LLG_EARG, "max_outer must be >= 1");
     if (!is_fin(o->inner_rtol) || o->inner_rtol <= 0 || o->inner_rtol >= 1)
@@ -160,7 +162,7 @@ llg_status fetch(const Ctx& c, const double* dev, int n, hipStream_t st, double*
 size_t align256(size_t b) { return (b + 255) & ~size_t(255); }
 
 struct Work {
-  double* V = nullptr;   // (R + 1) x n4
+  double* V = nullptr;   // (R + 2) x n4: basis, plus the delayed-CGS2 u and w
   double* r = nullptr;   // n4
   double* t = nullptr;   // n4 temporary
   float* Z = nullptr;    // R x n4 (precision form)
@@ -185,7 +187,7 @@ Work carve(const Ctx& c, int R, int prec, void* base) {
     off += align256(bytes);
     return q;
   };
-  w.V = reinterpret_cast<double*>(take(sizeof(double) * n4 * (R + 1)));
+  w.V = reinterpret_cast<double*>(take(sizeof(double) * n4 * (R + 2)));
   w.r = reinterpret_cast<double*>(take(sizeof(double) * n4));
   w.t = reinterpret_cast<double*>(take(sizeof(double) * n4));
   if (prec == LLG_FP32_IR) {
@@ -264,6 +266,103 @@ llg_status arnoldi_step(const Ctx& c, double* V, long long n4, int j, double* co
   return LLG_OK;
 }
 
+// One Krylov cycle with CGS2 whose re-orthogonalization is delayed by one
+// iteration (two streaming passes and one reduction per iteration).
+//
+// U holds the start vector u_0 on entry (not normalized).  Iteration j:
+//   w = Op(u_j)                                   (speculative: Op of the
+//                                                  not yet re-orthogonalized u_j)
+//   pass 1: a = Q_j^T u_j, b = Q_j^T w, c = u_j.u_j, d = u_j.w
+//   beta = sqrt(c - a.a), q_j = (u_j - Q_j a) / beta;  column j-1 of H is
+//   h_{j-1} + a with subdiagonal beta (h_{j-1}: first projection of the
+//   previous iteration).  By the Arnoldi relation Op(Q_j a) = Q_{j+1} H a, so
+//   Op q_j = (w - Q_{j+1} g) / beta with g = H_{0:j+1,0:j} a, and the first
+//   projection of Op q_j onto Q_{j+1} follows from (a, b, d, g) alone:
+//   h_j[i] = (b_i - g_i)/beta (i < j), h_j[j] = ((d - a.b)/beta - g_j)/beta.
+//   pass 2: q_j = (u_j - Q_j a)/beta, u_{j+1} = (w - Q_{j+1} (g + beta h_j))/beta.
+// The cycle stops after finalizing column k-1 (the Givens residual estimate
+// is one iteration behind the speculative Op application).  With flexible =
+// true, Op also stores Ztilde_j = M^{-1} u_j and the returned coefficients
+// multiply Ztilde (q_j's preconditioned vector is (Ztilde_j - Z a)/beta, so
+// the Hessenberg solution is mapped through the triangular factor T).
+struct CycleResult {
+  int k = 0;
+  double beta0 = 0, gres = 0;
+  Coefs y{};
+};
+
+llg_status cycle_dcgs2(const Ctx& c, const std::function<hipError_t(int, const double*, double*)>& op, double* Q,
+                       double* U, double* W, long long n4, int R, double eta, int maxiter, int& iters, bool flexible,
+                       CycleResult& out, hipStream_t st) {
+  Hess hs(R);
+  std::vector<double> Hraw(size_t(R + 1) * R, 0.0), T(size_t(R + 1) * (R + 1), 0.0);
+  std::vector<double> hprev, col(R + 2), vals(2 * kMaxDots), g(R + 2), hnew(R + 2);
+  auto HR = [&](int i, int jj) -> double& { return Hraw[size_t(i) * R + jj]; };
+  auto TT = [&](int i, int jj) -> double& { return T[size_t(i) * (R + 1) + jj]; };
+  int k = 0;
+  for (int j = 0; j <= R; ++j) {
+    const bool need_w = j < R;
+    if (need_w) CHK(op(j, U, W));
+    CHK(dcgs_dots(c, Q, n4, j, U, need_w ? W : nullptr, n4, c.dots, st));
+    CHK_STATUS(fetch(c, c.dots, 2 * j + 2, st, vals.data()));
+    const double* a = vals.data();
+    const double* b = vals.data() + j;
+    const double cc = vals[2 * j], d = vals[2 * j + 1];
+    double aa = 0, ab = 0;
+    for (int i = 0; i < j; ++i) {
+      aa += a[i] * a[i];
+      ab += a[i] * b[i];
+    }
+    if (!is_fin(cc) || !is_fin(d) || !is_fin(aa)) return fail(LLG_ENAN, "non-finite Arnoldi inner products");
+    const double beta2 = cc - aa;
+    const double beta = beta2 > 0 ? std::sqrt(beta2) : 0.0;
+    if (j == 0) {
+      out.beta0 = beta;
+      hs.g[0] = beta;
+      if (beta == 0.0) break;
+    } else {
+      for (int i = 0; i < j; ++i) col[i] = hprev[i] + a[i];
+      col[j] = beta;
+      for (int i = 0; i <= j; ++i) HR(i, j - 1) = col[i];
+      out.gres = hs.add_column(j - 1, col.data());
+      iters++;
+      k = j;
+      if (out.gres <= eta * out.beta0 || iters >= maxiter || j == R || beta == 0.0) break;
+    }
+    for (int i = 0; i < j; ++i) TT(i, j) = a[i];
+    TT(j, j) = beta;
+    // g = H_{0:j+1, 0:j} a
+    for (int r = 0; r <= j; ++r) {
+      double sgm = 0;
+      for (int i = std::max(0, r - 1); i < j; ++i) sgm += HR(r, i) * a[i];
+      g[r] = sgm;
+    }
+    for (int i = 0; i < j; ++i) hnew[i] = (b[i] - g[i]) / beta;
+    hnew[j] = ((d - ab) / beta - g[j]) / beta;
+    DcgsCoef cf{};
+    for (int i = 0; i < j; ++i) {
+      cf.a[i] = a[i];
+      cf.e[i] = g[i] + beta * hnew[i];
+    }
+    cf.ej = g[j] + beta * hnew[j];
+    cf.inv_beta = 1.0 / beta;
+    cf.j = j;
+    CHK(dcgs_update(c, Q, n4, cf, U, W, Q + size_t(j) * n4, n4, st));
+    hprev.assign(hnew.begin(), hnew.begin() + j + 1);
+  }
+  out.k = k;
+  hs.solve(k, out.y);
+  if (flexible) {
+    // Z = Ztilde T^{-1}: coefficients on Ztilde solve T yt = y
+    for (int i = k - 1; i >= 0; --i) {
+      double sgm = out.y.c[i];
+      for (int l = i + 1; l < k; ++l) sgm -= TT(i, l) * out.y.c[l];
+      out.y.c[i] = sgm / TT(i, i);
+    }
+  }
+  return LLG_OK;
+}
+
 struct SolveResult {
   int iters = 0, cycles = 0, outer = 0, converged = 0;
   double rel_true = 0, rel_prec = 0;
@@ -310,6 +409,26 @@ llg_status gmres_left(const Ctx& c, const Op& A, const Op& M, const Op& MA, cons
     }
     if (res.iters >= o.maxiter) break;
     res.cycles++;
+    if (o.orth == 0) {
+      double* Q = w.V;
+      double* U = w.V + size_t(R) * n4;
+      double* W = w.V + size_t(R + 1) * n4;
+      CHK(M(w.r, U));
+      CycleResult cr;
+      auto op = [&](int, const double* u, double* wout) { return MA(u, wout); };
+      CHK_STATUS(cycle_dcgs2(c, op, Q, U, W, n4, R, target / rho, o.maxiter, res.iters, false, cr, st));
+      if (!is_fin(cr.beta0)) return fail(LLG_ENAN, "non-finite preconditioned residual");
+      if (beta0 < 0) beta0 = cr.beta0;
+      res.rel_prec = beta0 > 0 ? cr.gres / beta0 : 0.0;
+      if (cr.k == 0) break;
+      CHK(lincomb(c, n4, cr.y, Q, n4, x, st));
+      CHK(A(x, w.r));
+      CHK(axpby(c, n4, 1.0, b, -1.0, w.r, w.r, st));
+      CHK(dot_and_norm(c, w.r, nullptr, n4, c.scal, st));
+      CHK_STATUS(fetch(c, c.scal, 2, st, rn));
+      rho = std::sqrt(rn[1]);
+      continue;
+    }
     CHK(M(w.r, w.V));
     double bb[2];
     CHK(dot_and_norm(c, w.V, nullptr, n4, c.scal, st));
@@ -390,6 +509,31 @@ llg_status gmres_ir(const Ctx& c, const llg_params* p, const double* m, const do
     if (res.outer >= o.max_outer || res.iters >= o.maxiter) break;
     res.outer++;
     res.cycles++;
+    if (o.orth == 0) {
+      double* Q = w.V;
+      double* W = w.V + size_t(R + 1) * n4;
+      auto op = [&](int j, const double* u, double* wout) -> hipError_t {
+        float* zj = w.Z + size_t(j) * n4;
+        PipeIO<float, double, float> io_ap{u, w.m32, zj, c.ng, nullptr, nullptr};
+        hipError_t e = run_pipeline<float, double, float>(c, PRO_COPY3, EPI_APPLY, sym_ap, na, io_ap, st);
+        if (e != hipSuccess) return e;
+        PipeIO<float, float, double> io_mv{zj, w.m32, wout, c.ng, nullptr, nullptr};
+        return run_pipeline<float, float, double>(c, PRO_COPY3, EPI_MATVEC, sym_mv, na, io_mv, st);
+      };
+      CycleResult cr;
+      // u_0 = r (the residual buffer is consumed as the cycle's start vector)
+      CHK_STATUS(cycle_dcgs2(c, op, Q, w.r, W, n4, R, std::max(o.inner_rtol, target / rho), o.maxiter, res.iters,
+                             true, cr, st));
+      res.rel_prec = cr.gres / bnorm;
+      if (cr.k == 0) break;
+      CHK(lincomb(c, n4, cr.y, w.Z, n4, x, st));
+      CHK(op_matvec(c, p, m, x, w.r, false, st));
+      CHK(axpby(c, n4, 1.0, b, -1.0, w.r, w.r, st));
+      CHK(dot_and_norm(c, w.r, nullptr, n4, c.scal, st));
+      CHK_STATUS(fetch(c, c.scal, 2, st, rn));
+      rho = std::sqrt(rn[1]);
+      continue;
+    }
     CHK(axpby(c, n4, 1.0 / rho, w.r, 0.0, w.r, w.V, st));
     const double eta = std::max(o.inner_rtol, target / rho);
     std::fill(hs.g.begin(), hs.g.end(), 0.0);

@@ -10,6 +10,23 @@ struct Coefs {
   int n;
 };
 
+// Coefficients of the second pass of CGS2 with delayed re-orthogonalization.
+struct DcgsCoef {
+  double a[64];   // re-orthogonalization coefficients of u against Q_0..Q_{j-1}
+  double e[64];   // projection coefficients of w against Q_0..Q_{j-1}
+  double ej;      // coefficient of the new q_j in the projection of w
+  double inv_beta;
+  int j;
+};
+
+// out = [Q_i.u (i<j), Q_i.w (i<j), u.u, u.w]; with w null only Q_i.u and u.u
+// (out[2j] = u.u, out[2j+1] = 0).  j <= 31.
+hipError_t dcgs_dots(const Ctx& c, const double* Q, long long ld, int j, const double* u, const double* w,
+                     long long n, double* out, hipStream_t st);
+// qj = (u - sum a_i Q_i)/beta ; u <- (w - sum e_i Q_i - ej qj)/beta
+hipError_t dcgs_update(const Ctx& c, const double* Q, long long ld, const DcgsCoef& cf, double* u, const double* w,
+                       double* qj, long long n, hipStream_t st);
+
 hipError_t reduce_partials(const Ctx& c, int nv, double* out, bool is_max, hipStream_t st);
 // out[i] = V_i . w  (i < nv; V_i = V + i*ld)
 hipError_t cgs_dots(const Ctx& c, const double* V, long long ld, int nv, const double* w, long long n, double* out,

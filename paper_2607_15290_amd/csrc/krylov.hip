@@ -136,6 +136,98 @@ __global__ __launch_bounds__(kRedThreads) void k_update_norm(const double* __res
   block_store<1>(acc, 1, partial);
 }
 
+// ---- CGS2 with delayed re-orthogonalization (two passes per iteration) -------
+// Pass 1: out = [Q_i.u (i < j), Q_i.w (i < j), u.u, u.w]  (w may be null: then
+// only Q_i.u and u.u are formed).  Streams Q_0..Q_{j-1}, u and w once.
+template <int MAXV>
+__global__ __launch_bounds__(kRedThreads) void k_dcgs_dots(const double2* __restrict__ Q, long long ld2, int j,
+                                                          const double2* __restrict__ u,
+                                                          const double2* __restrict__ w, long long n2,
+                                                          double* __restrict__ partial) {
+  double au[MAXV], aw[MAXV];
+#pragma unroll
+  for (int i = 0; i < MAXV; ++i) au[i] = aw[i] = 0.0;
+  double cuu = 0.0, cuw = 0.0;
+  const long long stride = (long long)gridDim.x * blockDim.x;
+  if (w) {
+    for (long long e = (long long)blockIdx.x * blockDim.x + threadIdx.x; e < n2; e += stride) {
+      const double2 uu = u[e], ww = w[e];
+      cuu = fma(uu.x, uu.x, fma(uu.y, uu.y, cuu));
+      cuw = fma(uu.x, ww.x, fma(uu.y, ww.y, cuw));
+#pragma unroll
+      for (int i = 0; i < MAXV; ++i)
+        if (i < j) {
+          const double2 q = Q[i * ld2 + e];
+          au[i] = fma(q.x, uu.x, fma(q.y, uu.y, au[i]));
+          aw[i] = fma(q.x, ww.x, fma(q.y, ww.y, aw[i]));
+        }
+    }
+  } else {
+    for (long long e = (long long)blockIdx.x * blockDim.x + threadIdx.x; e < n2; e += stride) {
+      const double2 uu = u[e];
+      cuu = fma(uu.x, uu.x, fma(uu.y, uu.y, cuu));
+#pragma unroll
+      for (int i = 0; i < MAXV; ++i)
+        if (i < j) {
+          const double2 q = Q[i * ld2 + e];
+          au[i] = fma(q.x, uu.x, fma(q.y, uu.y, au[i]));
+        }
+    }
+  }
+  // block reduction of the 2j + 2 values into partial[block][0 .. 2j+2)
+  __shared__ double sm[kRedThreads / 64][2 * MAXV + 2];
+  const int lane = threadIdx.x & 63, wv = threadIdx.x >> 6;
+#pragma unroll
+  for (int i = 0; i < MAXV; ++i) {
+    if (i < j) {
+      const double x = wave_sum(au[i]);
+      const double y = wave_sum(aw[i]);
+      if (lane == 0) {
+        sm[wv][i] = x;
+        sm[wv][j + i] = y;
+      }
+    }
+  }
+  {
+    const double x = wave_sum(cuu), y = wave_sum(cuw);
+    if (lane == 0) {
+      sm[wv][2 * j] = x;
+      sm[wv][2 * j + 1] = y;
+    }
+  }
+  __syncthreads();
+  if (threadIdx.x < 2 * j + 2) {
+    double t = sm[0][threadIdx.x];
+#pragma unroll
+    for (int k = 1; k < kRedThreads / 64; ++k) t += sm[k][threadIdx.x];
+    partial[blockIdx.x * kMaxDots + threadIdx.x] = t;
+  }
+}
+
+// Pass 2: q_j = (u - sum_i a_i Q_i) / beta ;  u <- (w - sum_i e_i Q_i - e_j q_j) / beta.
+template <int MAXV>
+__global__ __launch_bounds__(256) void k_dcgs_update(const double2* __restrict__ Q, long long ld2, DcgsCoef cf,
+                                                    double2* u, const double2* __restrict__ w,
+                                                    double2* __restrict__ qj, long long n2) {
+  const long long stride = (long long)gridDim.x * blockDim.x;
+  const int j = cf.j;
+  for (long long e = (long long)blockIdx.x * blockDim.x + threadIdx.x; e < n2; e += stride) {
+    double2 sa = u[e], se = w[e];
+#pragma unroll
+    for (int i = 0; i < MAXV; ++i)
+      if (i < j) {
+        const double2 q = Q[i * ld2 + e];
+        sa.x = fma(-cf.a[i], q.x, sa.x);
+        sa.y = fma(-cf.a[i], q.y, sa.y);
+        se.x = fma(-cf.e[i], q.x, se.x);
+        se.y = fma(-cf.e[i], q.y, se.y);
+      }
+    const double2 qn{sa.x * cf.inv_beta, sa.y * cf.inv_beta};
+    qj[e] = qn;
+    u[e] = double2{(se.x - cf.ej * qn.x) * cf.inv_beta, (se.y - cf.ej * qn.y) * cf.inv_beta};
+  }
+}
+
 // ---- simple vector kernels -------------------------------------------------
 __global__ void k_scale_invnorm(double* __restrict__ y, const double* __restrict__ x,
                                 const double* __restrict__ nrm2, long long n) {
@@ -259,6 +351,47 @@ hipError_t cgs_update_norm(const Ctx& c, const double* V, long long ld, int nv, 
   else updn_t<64>(c, V, ld, nv, cf, w, out_vec, n, st);
   }
   return reduce_partials(c, 1, out_nrm2, false, st);
+}
+
+
+template <int MAXV>
+static void dd_t(const Ctx& c, const double* Q, long long ld, int j, const double* u, const double* w, long long n,
+                 hipStream_t st) {
+  hipLaunchKernelGGL((k_dcgs_dots<MAXV>), dim3(kRedBlocks), dim3(kRedThreads), 0, st,
+                     reinterpret_cast<const double2*>(Q), ld / 2, j, reinterpret_cast<const double2*>(u),
+                     reinterpret_cast<const double2*>(w), n / 2, c.partial);
+}
+hipError_t dcgs_dots(const Ctx& c, const double* Q, long long ld, int j, const double* u, const double* w,
+                     long long n, double* out, hipStream_t st) {
+  {
+    ProfScope ps(c.prof, st, KK_CGS_DOTS, 8.0 * n * (j + (w ? 2 : 1)));
+    if (j <= 4) dd_t<4>(c, Q, ld, j, u, w, n, st);
+    else if (j <= 8) dd_t<8>(c, Q, ld, j, u, w, n, st);
+    else if (j <= 16) dd_t<16>(c, Q, ld, j, u, w, n, st);
+    else dd_t<31>(c, Q, ld, j, u, w, n, st);
+  }
+  return reduce_partials(c, 2 * j + 2, out, false, st);
+}
+
+template <int MAXV>
+static void du_t(const Ctx& c, const double* Q, long long ld, const DcgsCoef& cf, double* u, const double* w,
+                 double* qj, long long n, hipStream_t st) {
+  const long long n2 = n / 2;
+  long long g = (n2 + 255) / 256;
+  if (g > 8192) g = 8192;
+  hipLaunchKernelGGL((k_dcgs_update<MAXV>), dim3((unsigned)g), dim3(256), 0, st,
+                     reinterpret_cast<const double2*>(Q), ld / 2, cf, reinterpret_cast<double2*>(u),
+                     reinterpret_cast<const double2*>(w), reinterpret_cast<double2*>(qj), n2);
+}
+hipError_t dcgs_update(const Ctx& c, const double* Q, long long ld, const DcgsCoef& cf, double* u, const double* w,
+                       double* qj, long long n, hipStream_t st) {
+  ProfScope ps(c.prof, st, KK_CGS_UPDATE_DOTS, 8.0 * n * (cf.j + 4));
+  if (cf.j <= 4) du_t<4>(c, Q, ld, cf, u, w, qj, n, st);
+  else if (cf.j <= 8) du_t<8>(c, Q, ld, cf, u, w, qj, n, st);
+  else if (cf.j <= 16) du_t<16>(c, Q, ld, cf, u, w, qj, n, st);
+  else if (cf.j <= 32) du_t<32>(c, Q, ld, cf, u, w, qj, n, st);
+  else du_t<64>(c, Q, ld, cf, u, w, qj, n, st);
+  return hipGetLastError();
 }
 
 hipError_t scale_invnorm(const Ctx& c, double* y, const double* x, const double* nrm2, long long n, hipStream_t st) {

@@ -56,8 +56,12 @@ class Params:
         return p
 
 
-def _opts(restart, maxiter, rtol, prec, inner_rtol, max_outer, use_x0):
+ORTH = {"dcgs2": 0, "cgs2": 1, 0: 0, 1: 1}
+
+
+def _opts(restart, maxiter, rtol, prec, inner_rtol, max_outer, use_x0, orth="dcgs2"):
     o = L.LLGSolverOpts()
+    o.orth = ORTH[orth]
     o.restart, o.maxiter, o.max_outer, o.use_x0 = int(restart), int(maxiter), int(max_outer), int(use_x0)
     o.rtol, o.inner_rtol = float(rtol), float(inner_rtol)
     o.prec = _PREC[prec]
@@ -160,12 +164,12 @@ def fft_hss_apply_f32(ctx, params, m, p, z=None, transpose=False):
 
 
 def gmres_solve(ctx, params, m, b, x=None, use_x0=False, restart=30, rtol=1e-10, maxiter=3000, prec="fp64",
-                inner_rtol=1e-5, max_outer=20, check=True):
+                inner_rtol=1e-5, max_outer=20, check=True, orth="dcgs2"):
     """Solve A(m) x = b; returns (x, stats).  See gmres_solve in include/llg.h."""
     if x is None:
         x = ctx.new(4)
         use_x0 = False
-    o = _opts(restart, maxiter, rtol, prec, inner_rtol, max_outer, use_x0)
+    o = _opts(restart, maxiter, rtol, prec, inner_rtol, max_outer, use_x0, orth)
     st = L.LLGSolverStats()
     work = ctx.workspace(restart, prec)
     pr = params.c_struct()
@@ -180,9 +184,9 @@ def gmres_solve(ctx, params, m, b, x=None, use_x0=False, restart=30, rtol=1e-10,
 
 
 def llg_step_euler(ctx, params, m, v_out=None, lam_out=None, restart=30, rtol=1e-10, maxiter=3000, prec="fp64",
-                   inner_rtol=1e-5, max_outer=20, check=True):
+                   inner_rtol=1e-5, max_outer=20, check=True, orth="dcgs2"):
     """One projected Euler step; m is updated in place.  Returns stats."""
-    o = _opts(restart, maxiter, rtol, prec, inner_rtol, max_outer, 0)
+    o = _opts(restart, maxiter, rtol, prec, inner_rtol, max_outer, 0, orth)
     st = L.LLGStepStats()
     work = ctx.workspace(restart, prec)
     pr = params.c_struct()
@@ -198,9 +202,10 @@ def llg_step_euler(ctx, params, m, v_out=None, lam_out=None, restart=30, rtol=1e
 
 
 def llg_step_midpoint(ctx, params, m, v_half=None, lam=None, picard_tol=1e-10, picard_max=50, restart=30,
-                      rtol=1e-10, maxiter=3000, prec="fp64", inner_rtol=1e-5, max_outer=20, check=True):
+                      rtol=1e-10, maxiter=3000, prec="fp64", inner_rtol=1e-5, max_outer=20, check=True,
+                      orth="dcgs2"):
     """One midpoint step; m, v_half, lam updated in place.  Returns stats."""
-    o = _opts(restart, maxiter, rtol, prec, inner_rtol, max_outer, 1)
+    o = _opts(restart, maxiter, rtol, prec, inner_rtol, max_outer, 1, orth)
     st = L.LLGStepStats()
     work = ctx.workspace(restart, prec)
     pr = params.c_struct()
@@ -217,11 +222,11 @@ def llg_step_midpoint(ctx, params, m, v_half=None, lam=None, picard_tol=1e-10, p
 
 
 def llg_step_midpoint_adjoint(ctx, params, m_n, v, lam, gbar, hbar_field=None, hbar_uniform=None, restart=30,
-                              rtol=1e-12, maxiter=3000, check=True):
+                              rtol=1e-12, maxiter=3000, check=True, orth="dcgs2"):
     """Back-propagate gbar (in/out) through one converged midpoint step.
     hbar_field (tensor, +=) and hbar_uniform (list of 3 floats, +=) are
     accumulated.  Returns (hbar_uniform, stats)."""
-    o = _opts(restart, maxiter, rtol, "fp64", 1e-5, 1, 0)
+    o = _opts(restart, maxiter, rtol, "fp64", 1e-5, 1, 0, orth)
     st = L.LLGSolverStats()
     work = ctx.workspace(restart, "fp64")
     hu = (ctypes.c_double * 3)(*(hbar_uniform if hbar_uniform is not None else (0.0, 0.0, 0.0)))
