@@ -150,6 +150,30 @@ hipError_t op_rhs(const Ctx& c, const llg_params* p, const double* m, double* b,
   return pipe_d(c, PRO_COPY3, EPI_RHS, sym_for(c, 0.0, 1.0, false), nodal_for(p), m, nullptr, b, st);
 }
 
+// Number of x-inverse blocks of a pipeline (one residual partial each).
+int xinv_blocks(const Ctx& c) {
+  const int nh = c.geom.nh;
+  const int tpl = nh / plan_p(nh);
+  const int lx = 64 / tpl;
+  return int(((long long)c.ny * c.nz + lx - 1) / lx);
+}
+
+// r = b - A x in residual form (fused into the operator's last pass); the
+// squared norm of r lands in c.scal[0].
+using ResidOp = std::function<hipError_t(const double* x, const double* b, double* r)>;
+
+ResidOp resid_op(const Ctx& c, int epi, const SymArgs& sym, const NodalArgs& na, const double* m, hipStream_t st,
+                 const double* aux_v = nullptr, const double* aux_r = nullptr) {
+  return [&c, epi, sym, na, m, st, aux_v, aux_r](const double* x, const double* b, double* r) -> hipError_t {
+    PipeIO<double, double, double> io{x, m, r, c.ng, aux_v, aux_r};
+    io.rhs = b;
+    io.red = c.partial;
+    hipError_t e = run_pipeline<double, double, double>(c, PRO_COPY3, epi, sym, na, io, st);
+    if (e != hipSuccess) return e;
+    return reduce_flat(c, xinv_blocks(c), c.scal, st);
+  };
+}
+
 // Read n doubles of device memory (after the stream's queued work).
 llg_status fetch(const Ctx& c, const double* dev, int n, hipStream_t st, double* host_out) {
   CHK(hipMemcpyAsync(c.host, dev, sizeof(double) * n, hipMemcpyDeviceToHost, st));
@@ -370,7 +394,7 @@ struct SolveResult {
 
 // Left-preconditioned restarted GMRES (FP64) with true-residual acceptance.
 // A: true operator, M: preconditioner, MA: M^{-1} A.
-llg_status gmres_left(const Ctx& c, const Op& A, const Op& M, const Op& MA, const double* b, double* x,
+llg_status gmres_left(const Ctx& c, const ResidOp& RA, const Op& M, const Op& MA, const double* b, double* x,
                       const llg_solver_opts& o, Work& w, SolveResult& res, hipStream_t st) {
   const long long n4 = 4 * c.ng;
   const int R = o.restart;
@@ -386,17 +410,17 @@ llg_status gmres_left(const Ctx& c, const Op& A, const Op& M, const Op& MA, cons
     return LLG_OK;
   }
   const double target = o.rtol * bnorm;
+  double rn[2];
+  double rho;
   if (o.use_x0) {
-    CHK(A(x, w.r));
-    CHK(axpby(c, n4, 1.0, b, -1.0, w.r, w.r, st));
+    CHK(RA(x, b, w.r));
+    CHK_STATUS(fetch(c, c.scal, 1, st, rn));
+    rho = std::sqrt(rn[0]);
   } else {
     CHK(hipMemsetAsync(x, 0, sizeof(double) * n4, st));
     CHK(hipMemcpyAsync(w.r, b, sizeof(double) * n4, hipMemcpyDeviceToDevice, st));
+    rho = bnorm;
   }
-  double rn[2];
-  CHK(dot_and_norm(c, w.r, nullptr, n4, c.scal, st));
-  CHK_STATUS(fetch(c, c.scal, 2, st, rn));
-  double rho = std::sqrt(rn[1]);
   double beta0 = -1.0;
   Hess hs(R);
   std::vector<double> col(R + 2);
@@ -422,11 +446,9 @@ llg_status gmres_left(const Ctx& c, const Op& A, const Op& M, const Op& MA, cons
       res.rel_prec = beta0 > 0 ? cr.gres / beta0 : 0.0;
       if (cr.k == 0) break;
       CHK(lincomb(c, n4, cr.y, Q, n4, x, st));
-      CHK(A(x, w.r));
-      CHK(axpby(c, n4, 1.0, b, -1.0, w.r, w.r, st));
-      CHK(dot_and_norm(c, w.r, nullptr, n4, c.scal, st));
-      CHK_STATUS(fetch(c, c.scal, 2, st, rn));
-      rho = std::sqrt(rn[1]);
+      CHK(RA(x, b, w.r));
+      CHK_STATUS(fetch(c, c.scal, 1, st, rn));
+      rho = std::sqrt(rn[0]);
       continue;
     }
     CHK(M(w.r, w.V));
@@ -454,11 +476,9 @@ llg_status gmres_left(const Ctx& c, const Op& A, const Op& M, const Op& MA, cons
     Coefs y{};
     hs.solve(k, y);
     CHK(lincomb(c, n4, y, w.V, n4, x, st));
-    CHK(A(x, w.r));
-    CHK(axpby(c, n4, 1.0, b, -1.0, w.r, w.r, st));
-    CHK(dot_and_norm(c, w.r, nullptr, n4, c.scal, st));
-    CHK_STATUS(fetch(c, c.scal, 2, st, rn));
-    rho = std::sqrt(rn[1]);
+    CHK(RA(x, b, w.r));
+    CHK_STATUS(fetch(c, c.scal, 1, st, rn));
+    rho = std::sqrt(rn[0]);
   }
   if (!res.converged) return fail(LLG_ENOCONV, "GMRES reached maxiter before the tolerance");
   return LLG_OK;
@@ -486,17 +506,18 @@ llg_status gmres_ir(const Ctx& c, const llg_params* p, const double* m, const do
     return LLG_OK;
   }
   const double target = o.rtol * bnorm;
+  const ResidOp RA = resid_op(c, EPI_MATVEC, sym_for(c, p->alpha, hcoef(p), false), na, m, st);
+  double rn[2];
+  double rho;
   if (o.use_x0) {
-    CHK(op_matvec(c, p, m, x, w.r, false, st));
-    CHK(axpby(c, n4, 1.0, b, -1.0, w.r, w.r, st));
+    CHK(RA(x, b, w.r));
+    CHK_STATUS(fetch(c, c.scal, 1, st, rn));
+    rho = std::sqrt(rn[0]);
   } else {
     CHK(hipMemsetAsync(x, 0, sizeof(double) * n4, st));
     CHK(hipMemcpyAsync(w.r, b, sizeof(double) * n4, hipMemcpyDeviceToDevice, st));
+    rho = bnorm;
   }
-  double rn[2];
-  CHK(dot_and_norm(c, w.r, nullptr, n4, c.scal, st));
-  CHK_STATUS(fetch(c, c.scal, 2, st, rn));
-  double rho = std::sqrt(rn[1]);
   Hess hs(R);
   std::vector<double> col(R + 2);
   while (true) {
@@ -527,11 +548,9 @@ llg_status gmres_ir(const Ctx& c, const llg_params* p, const double* m, const do
       res.rel_prec = cr.gres / bnorm;
       if (cr.k == 0) break;
       CHK(lincomb(c, n4, cr.y, w.Z, n4, x, st));
-      CHK(op_matvec(c, p, m, x, w.r, false, st));
-      CHK(axpby(c, n4, 1.0, b, -1.0, w.r, w.r, st));
-      CHK(dot_and_norm(c, w.r, nullptr, n4, c.scal, st));
-      CHK_STATUS(fetch(c, c.scal, 2, st, rn));
-      rho = std::sqrt(rn[1]);
+      CHK(RA(x, b, w.r));
+      CHK_STATUS(fetch(c, c.scal, 1, st, rn));
+      rho = std::sqrt(rn[0]);
       continue;
     }
     CHK(axpby(c, n4, 1.0 / rho, w.r, 0.0, w.r, w.V, st));
@@ -555,11 +574,9 @@ llg_status gmres_ir(const Ctx& c, const llg_params* p, const double* m, const do
     Coefs y{};
     hs.solve(k, y);
     CHK(lincomb(c, n4, y, w.Z, n4, x, st));
-    CHK(op_matvec(c, p, m, x, w.r, false, st));
-    CHK(axpby(c, n4, 1.0, b, -1.0, w.r, w.r, st));
-    CHK(dot_and_norm(c, w.r, nullptr, n4, c.scal, st));
-    CHK_STATUS(fetch(c, c.scal, 2, st, rn));
-    rho = std::sqrt(rn[1]);
+    CHK(RA(x, b, w.r));
+    CHK_STATUS(fetch(c, c.scal, 1, st, rn));
+    rho = std::sqrt(rn[0]);
   }
   if (!res.converged) return fail(LLG_ENOCONV, "refinement reached its limit before the tolerance");
   return LLG_OK;
@@ -578,10 +595,10 @@ llg_status solve(const Ctx& c, const llg_params* p, const double* m, const doubl
                  const llg_solver_opts& o, Work& w, SolveResult& res, hipStream_t st) {
   CHK_STATUS(check_m(c, m, st));
   if (o.prec == LLG_FP32_IR) return gmres_ir(c, p, m, b, x, o, w, res, st);
-  Op A = [&](const double* in, double* out) { return op_matvec(c, p, m, in, out, false, st); };
+  const ResidOp RA = resid_op(c, EPI_MATVEC, sym_for(c, p->alpha, hcoef(p), false), nodal_for(p), m, st);
   Op M = [&](const double* in, double* out) { return op_apply(c, p, m, in, out, false, st); };
   Op MA = [&](const double* in, double* out) { return op_fused(c, p, m, in, out, st); };
-  return gmres_left(c, A, M, MA, b, x, o, w, res, st);
+  return gmres_left(c, RA, M, MA, b, x, o, w, res, st);
 }
 
 void fill_stats(const SolveResult& r, llg_solver_stats* s) {
@@ -650,7 +667,7 @@ llg_status llg_ctx_create(llg_ctx** out, int nx, int ny, int nz, double h, int d
   };
   c.prof = profiler_new();
   if (hipMalloc(&c.spec, c.spec_bytes) != hipSuccess) return cleanup(LLG_ENOMEM, "spectral scratch allocation failed");
-  if (hipMalloc(&c.partial, sizeof(double) * kRedBlocks * kMaxDots) != hipSuccess)
+  if (hipMalloc(&c.partial, sizeof(double) * kRedBlocksMax * kMaxDots) != hipSuccess)
     return cleanup(LLG_ENOMEM, "reduction buffer allocation failed");
   if (hipMalloc(&c.dots, sizeof(double) * 4 * kMaxDots) != hipSuccess)
     return cleanup(LLG_ENOMEM, "reduction buffer allocation failed");
@@ -977,8 +994,9 @@ llg_status llg_step_midpoint_adjoint(llg_ctx* ctx, const llg_params* prm, const 
   };
   llg_solver_opts o = *opts;
   o.use_x0 = 0;
+  const ResidOp RJT = resid_op(c, EPI_JT, sym_h, na, m_n, st, v, lam);
   SolveResult r;
-  const llg_status s = gmres_left(c, JT, MT, MTJT, w.b, w.x, o, w, r, st);
+  const llg_status s = gmres_left(c, RJT, MT, MTJT, w.b, w.x, o, w, r, st);
   fill_stats(r, stats);
   if (s != LLG_OK) return s;
   // gbar update and field gradients

@@ -204,13 +204,18 @@ __device__ __forceinline__ void stage_compute(cx<T>* v, int t, const cx<T>* __re
 #pragma unroll
   for (int b = 0; b < B; ++b) {
     if constexpr (NS > 1) {
+      // twiddles w^r, r = 1..R-1, from one table load: w^2 = w w, then
+      // w^r = w^(r-2) w^2 (at most ~R/2 roundings per power)
       const int j = t + TPL * b;
       const int k = j % NS;
+      const cx<T> w1 = tw[(k * (N / (NS * R))) * tws];
+      const cx<T> w2 = cmul(w1, w1);
+      cx<T> wr[R];
+      wr[1] = w1;
 #pragma unroll
-      for (int r = 1; r < R; ++r) {
-        const cx<T> w = tw[(k * r * (N / (NS * R))) * tws];
-        v[b * R + r] = DIR < 0 ? cmul(v[b * R + r], w) : cmulc(v[b * R + r], w);
-      }
+      for (int r = 2; r < R; ++r) wr[r] = r == 2 ? w2 : cmul(wr[r - 2], w2);
+#pragma unroll
+      for (int r = 1; r < R; ++r) v[b * R + r] = DIR < 0 ? cmul(v[b * R + r], wr[r]) : cmulc(v[b * R + r], wr[r]);
     }
     dft<T, R, DIR>(v + b * R);
   }

@@ -28,6 +28,17 @@ hipError_t dcgs_update(const Ctx& c, const double* Q, long long ld, const DcgsCo
                        double* qj, long long n, hipStream_t st);
 
 hipError_t reduce_partials(const Ctx& c, int nv, double* out, bool is_max, hipStream_t st);
+// sum over the first nb block partials (stride kMaxDots) of nv values
+hipError_t reduce_partials_n(const Ctx& c, int nb, int nv, double* out, hipStream_t st);
+// Blocks of a delayed-CGS2 dot pass over n2 16-byte elements: about four
+// elements per thread, at most kRedBlocksMax; depends only on n2.
+inline int red_blocks(long long n2) {
+  long long g = (n2 + 4 * kRedThreads - 1) / (4 * kRedThreads);
+  if (g > kRedBlocksMax) g = kRedBlocksMax;
+  return int(g < 1 ? 1 : g);
+}
+// out[0] = sum of c.partial[0 .. nb) (the x-inverse residual partials)
+hipError_t reduce_flat(const Ctx& c, int nb, double* out, hipStream_t st);
 // out[i] = V_i . w  (i < nv; V_i = V + i*ld)
 hipError_t cgs_dots(const Ctx& c, const double* V, long long ld, int nv, const double* w, long long n, double* out,
                     hipStream_t st);

@@ -11,6 +11,7 @@
 // re-orthogonalization (CGS2), as three streaming passes over the basis:
 //   A: h = V^T w;   B: w -= V h, s = V^T w;   C: w -= V s, ||w||^2.
 #include <cmath>
+#include <utility>
 
 #include "krylov.h"
 
@@ -25,6 +26,19 @@ __device__ __forceinline__ double wave_max(double v) {
 #pragma unroll
   for (int off = 32; off > 0; off >>= 1) v = fmax(v, __shfl_xor(v, off, 64));
   return v;
+}
+
+// Non-temporal 16-byte load / store: the Krylov vectors (hundreds of MB each)
+// are streamed once per pass and never reused from cache before eviction.
+__device__ __forceinline__ double2 ldnt(const double2* p) {
+  double2 v;
+  v.x = __builtin_nontemporal_load(&p->x);
+  v.y = __builtin_nontemporal_load(&p->y);
+  return v;
+}
+__device__ __forceinline__ void stnt(double2* p, double2 v) {
+  __builtin_nontemporal_store(v.x, &p->x);
+  __builtin_nontemporal_store(v.y, &p->y);
 }
 
 // Reduce acc[0..nv) over the block and store partial[blockIdx.x * kMaxDots + i].
@@ -66,6 +80,22 @@ __global__ __launch_bounds__(kRedThreads) void k_reduce(const double* __restrict
     double t = sm[0];
     for (int w = 1; w < kRedThreads / 64; ++w) t = MAX ? fmax(t, sm[w]) : t + sm[w];
     out[i] = t;
+  }
+}
+
+// out[0] = sum of partial[0 .. nb) (stride 1), fixed order
+__global__ __launch_bounds__(kRedThreads) void k_reduce_flat(const double* __restrict__ partial, int nb,
+                                                            double* __restrict__ out) {
+  double s = 0.0;
+  for (int b = threadIdx.x; b < nb; b += kRedThreads) s += partial[b];
+  __shared__ double sm[kRedThreads / 64];
+  s = wave_sum(s);
+  if ((threadIdx.x & 63) == 0) sm[threadIdx.x >> 6] = s;
+  __syncthreads();
+  if (threadIdx.x == 0) {
+    double t = sm[0];
+    for (int w = 1; w < kRedThreads / 64; ++w) t += sm[w];
+    out[0] = t;
   }
 }
 
@@ -137,66 +167,58 @@ __global__ __launch_bounds__(kRedThreads) void k_update_norm(const double* __res
 }
 
 // ---- CGS2 with delayed re-orthogonalization (two passes per iteration) -------
-// Pass 1: out = [Q_i.u (i < j), Q_i.w (i < j), u.u, u.w]  (w may be null: then
-// only Q_i.u and u.u are formed).  Streams Q_0..Q_{j-1}, u and w once.
-template <int MAXV>
-__global__ __launch_bounds__(kRedThreads) void k_dcgs_dots(const double2* __restrict__ Q, long long ld2, int j,
+// Both passes are instantiated for the exact number J of basis vectors, so
+// every basis load of a thread is unconditional and the loads of one element
+// are all in flight together.
+//
+// Pass 1: out = [Q_i.u (i < J), Q_i.w (i < J), u.u, u.w]  (HAS_W = false: only
+// Q_i.u and u.u).  Streams Q_0..Q_{J-1}, u and w once.
+template <int J, bool HAS_W>
+__global__ __launch_bounds__(kRedThreads) void k_dcgs_dots(const double2* __restrict__ Q, long long ld2,
                                                           const double2* __restrict__ u,
                                                           const double2* __restrict__ w, long long n2,
                                                           double* __restrict__ partial) {
-  double au[MAXV], aw[MAXV];
+  constexpr int NA = J > 0 ? J : 1;
+  double au[NA], aw[NA];
 #pragma unroll
-  for (int i = 0; i < MAXV; ++i) au[i] = aw[i] = 0.0;
+  for (int i = 0; i < NA; ++i) au[i] = aw[i] = 0.0;
   double cuu = 0.0, cuw = 0.0;
   const long long stride = (long long)gridDim.x * blockDim.x;
-  if (w) {
-    for (long long e = (long long)blockIdx.x * blockDim.x + threadIdx.x; e < n2; e += stride) {
-      const double2 uu = u[e], ww = w[e];
-      cuu = fma(uu.x, uu.x, fma(uu.y, uu.y, cuu));
-      cuw = fma(uu.x, ww.x, fma(uu.y, ww.y, cuw));
+  for (long long e = (long long)blockIdx.x * blockDim.x + threadIdx.x; e < n2; e += stride) {
+    const double2 uu = ldnt(u + e);
+    double2 ww{0.0, 0.0};
+    if constexpr (HAS_W) ww = ldnt(w + e);
+    double2 q[NA];
 #pragma unroll
-      for (int i = 0; i < MAXV; ++i)
-        if (i < j) {
-          const double2 q = Q[i * ld2 + e];
-          au[i] = fma(q.x, uu.x, fma(q.y, uu.y, au[i]));
-          aw[i] = fma(q.x, ww.x, fma(q.y, ww.y, aw[i]));
-        }
-    }
-  } else {
-    for (long long e = (long long)blockIdx.x * blockDim.x + threadIdx.x; e < n2; e += stride) {
-      const double2 uu = u[e];
-      cuu = fma(uu.x, uu.x, fma(uu.y, uu.y, cuu));
+    for (int i = 0; i < J; ++i) q[i] = ldnt(Q + i * ld2 + e);
+    cuu = fma(uu.x, uu.x, fma(uu.y, uu.y, cuu));
+    if constexpr (HAS_W) cuw = fma(uu.x, ww.x, fma(uu.y, ww.y, cuw));
 #pragma unroll
-      for (int i = 0; i < MAXV; ++i)
-        if (i < j) {
-          const double2 q = Q[i * ld2 + e];
-          au[i] = fma(q.x, uu.x, fma(q.y, uu.y, au[i]));
-        }
+    for (int i = 0; i < J; ++i) {
+      au[i] = fma(q[i].x, uu.x, fma(q[i].y, uu.y, au[i]));
+      if constexpr (HAS_W) aw[i] = fma(q[i].x, ww.x, fma(q[i].y, ww.y, aw[i]));
     }
   }
-  // block reduction of the 2j + 2 values into partial[block][0 .. 2j+2)
-  __shared__ double sm[kRedThreads / 64][2 * MAXV + 2];
+  __shared__ double sm[kRedThreads / 64][2 * J + 2];
   const int lane = threadIdx.x & 63, wv = threadIdx.x >> 6;
 #pragma unroll
-  for (int i = 0; i < MAXV; ++i) {
-    if (i < j) {
-      const double x = wave_sum(au[i]);
-      const double y = wave_sum(aw[i]);
-      if (lane == 0) {
-        sm[wv][i] = x;
-        sm[wv][j + i] = y;
-      }
+  for (int i = 0; i < J; ++i) {
+    const double x = wave_sum(au[i]);
+    const double y = HAS_W ? wave_sum(aw[i]) : 0.0;
+    if (lane == 0) {
+      sm[wv][i] = x;
+      sm[wv][J + i] = y;
     }
   }
   {
-    const double x = wave_sum(cuu), y = wave_sum(cuw);
+    const double x = wave_sum(cuu), y = HAS_W ? wave_sum(cuw) : 0.0;
     if (lane == 0) {
-      sm[wv][2 * j] = x;
-      sm[wv][2 * j + 1] = y;
+      sm[wv][2 * J] = x;
+      sm[wv][2 * J + 1] = y;
     }
   }
   __syncthreads();
-  if (threadIdx.x < 2 * j + 2) {
+  if (threadIdx.x < 2 * J + 2) {
     double t = sm[0][threadIdx.x];
 #pragma unroll
     for (int k = 1; k < kRedThreads / 64; ++k) t += sm[k][threadIdx.x];
@@ -204,27 +226,27 @@ __global__ __launch_bounds__(kRedThreads) void k_dcgs_dots(const double2* __rest
   }
 }
 
-// Pass 2: q_j = (u - sum_i a_i Q_i) / beta ;  u <- (w - sum_i e_i Q_i - e_j q_j) / beta.
-template <int MAXV>
+// Pass 2: q_J = (u - sum_i a_i Q_i) / beta ;  u <- (w - sum_i e_i Q_i - e_J q_J) / beta.
+template <int J>
 __global__ __launch_bounds__(256) void k_dcgs_update(const double2* __restrict__ Q, long long ld2, DcgsCoef cf,
                                                     double2* u, const double2* __restrict__ w,
                                                     double2* __restrict__ qj, long long n2) {
   const long long stride = (long long)gridDim.x * blockDim.x;
-  const int j = cf.j;
   for (long long e = (long long)blockIdx.x * blockDim.x + threadIdx.x; e < n2; e += stride) {
-    double2 sa = u[e], se = w[e];
+    double2 sa = ldnt(u + e), se = ldnt(w + e);
+    double2 q[J > 0 ? J : 1];
 #pragma unroll
-    for (int i = 0; i < MAXV; ++i)
-      if (i < j) {
-        const double2 q = Q[i * ld2 + e];
-        sa.x = fma(-cf.a[i], q.x, sa.x);
-        sa.y = fma(-cf.a[i], q.y, sa.y);
-        se.x = fma(-cf.e[i], q.x, se.x);
-        se.y = fma(-cf.e[i], q.y, se.y);
-      }
+    for (int i = 0; i < J; ++i) q[i] = ldnt(Q + i * ld2 + e);
+#pragma unroll
+    for (int i = 0; i < J; ++i) {
+      sa.x = fma(-cf.a[i], q[i].x, sa.x);
+      sa.y = fma(-cf.a[i], q[i].y, sa.y);
+      se.x = fma(-cf.e[i], q[i].x, se.x);
+      se.y = fma(-cf.e[i], q[i].y, se.y);
+    }
     const double2 qn{sa.x * cf.inv_beta, sa.y * cf.inv_beta};
-    qj[e] = qn;
-    u[e] = double2{(se.x - cf.ej * qn.x) * cf.inv_beta, (se.y - cf.ej * qn.y) * cf.inv_beta};
+    stnt(qj + e, qn);
+    stnt(u + e, double2{(se.x - cf.ej * qn.x) * cf.inv_beta, (se.y - cf.ej * qn.y) * cf.inv_beta});
   }
 }
 
@@ -289,8 +311,20 @@ __global__ __launch_bounds__(kRedThreads) void k_diffnorm(const double* __restri
 // ---- host launchers --------------------------------------------------------
 static inline unsigned grid_for(long long n) {
   long long g = (n + 255) / 256;
-  if (g > 4096) g = 4096;
+  if (g > 65536) g = 65536;
   return (unsigned)(g < 1 ? 1 : g);
+}
+
+hipError_t reduce_partials_n(const Ctx& c, int nb, int nv, double* out, hipStream_t st) {
+  ProfScope ps(c.prof, st, KK_REDUCE, 8.0 * nb * nv);
+  hipLaunchKernelGGL((k_reduce<false>), dim3(nv), dim3(kRedThreads), 0, st, c.partial, nb, out);
+  return hipGetLastError();
+}
+
+hipError_t reduce_flat(const Ctx& c, int nb, double* out, hipStream_t st) {
+  ProfScope ps(c.prof, st, KK_REDUCE, 8.0 * nb);
+  hipLaunchKernelGGL(k_reduce_flat, dim3(1), dim3(kRedThreads), 0, st, c.partial, nb, out);
+  return hipGetLastError();
 }
 
 hipError_t reduce_partials(const Ctx& c, int nv, double* out, bool is_max, hipStream_t st) {
@@ -354,43 +388,67 @@ hipError_t cgs_update_norm(const Ctx& c, const double* V, long long ld, int nv, 
 }
 
 
-template <int MAXV>
-static void dd_t(const Ctx& c, const double* Q, long long ld, int j, const double* u, const double* w, long long n,
+template <int J>
+static void dd_t(const Ctx& c, const double* Q, long long ld, const double* u, const double* w, long long n,
                  hipStream_t st) {
-  hipLaunchKernelGGL((k_dcgs_dots<MAXV>), dim3(kRedBlocks), dim3(kRedThreads), 0, st,
-                     reinterpret_cast<const double2*>(Q), ld / 2, j, reinterpret_cast<const double2*>(u),
-                     reinterpret_cast<const double2*>(w), n / 2, c.partial);
-}
-hipError_t dcgs_dots(const Ctx& c, const double* Q, long long ld, int j, const double* u, const double* w,
-                     long long n, double* out, hipStream_t st) {
-  {
-    ProfScope ps(c.prof, st, KK_CGS_DOTS, 8.0 * n * (j + (w ? 2 : 1)));
-    if (j <= 4) dd_t<4>(c, Q, ld, j, u, w, n, st);
-    else if (j <= 8) dd_t<8>(c, Q, ld, j, u, w, n, st);
-    else if (j <= 16) dd_t<16>(c, Q, ld, j, u, w, n, st);
-    else dd_t<31>(c, Q, ld, j, u, w, n, st);
-  }
-  return reduce_partials(c, 2 * j + 2, out, false, st);
+  auto Q2 = reinterpret_cast<const double2*>(Q);
+  auto u2 = reinterpret_cast<const double2*>(u);
+  auto w2 = reinterpret_cast<const double2*>(w);
+  const int nb = red_blocks(n / 2);
+  if (w)
+    hipLaunchKernelGGL((k_dcgs_dots<J, true>), dim3(nb), dim3(kRedThreads), 0, st, Q2, ld / 2, u2, w2, n / 2,
+                       c.partial);
+  else
+    hipLaunchKernelGGL((k_dcgs_dots<J, false>), dim3(nb), dim3(kRedThreads), 0, st, Q2, ld / 2, u2, w2,
+                       n / 2, c.partial);
 }
 
-template <int MAXV>
+template <int J>
 static void du_t(const Ctx& c, const double* Q, long long ld, const DcgsCoef& cf, double* u, const double* w,
                  double* qj, long long n, hipStream_t st) {
   const long long n2 = n / 2;
-  long long g = (n2 + 255) / 256;
-  if (g > 8192) g = 8192;
-  hipLaunchKernelGGL((k_dcgs_update<MAXV>), dim3((unsigned)g), dim3(256), 0, st,
-                     reinterpret_cast<const double2*>(Q), ld / 2, cf, reinterpret_cast<double2*>(u),
-                     reinterpret_cast<const double2*>(w), reinterpret_cast<double2*>(qj), n2);
+  long long g = (n2 + 255) / 256;  // one 16-byte element per thread
+  if (g > (1LL << 30)) g = 1LL << 30;
+  hipLaunchKernelGGL((k_dcgs_update<J>), dim3((unsigned)g), dim3(256), 0, st, reinterpret_cast<const double2*>(Q),
+                     ld / 2, cf, reinterpret_cast<double2*>(u), reinterpret_cast<const double2*>(w),
+                     reinterpret_cast<double2*>(qj), n2);
 }
+
+// Runtime J -> template instantiation J = 0..31.
+template <template <int> class F, int J = 0>
+struct JDispatch {
+  template <typename... A>
+  static void run(int j, A&&... args) {
+    if (j == J) F<J>::go(std::forward<A>(args)...);
+    else if constexpr (J < 31) JDispatch<F, J + 1>::run(j, std::forward<A>(args)...);
+  }
+};
+template <int J>
+struct DotsF {
+  template <typename... A>
+  static void go(A&&... a) { dd_t<J>(std::forward<A>(a)...); }
+};
+template <int J>
+struct UpdF {
+  template <typename... A>
+  static void go(A&&... a) { du_t<J>(std::forward<A>(a)...); }
+};
+
+hipError_t dcgs_dots(const Ctx& c, const double* Q, long long ld, int j, const double* u, const double* w,
+                     long long n, double* out, hipStream_t st) {
+  if (j < 0 || j > 31) return hipErrorInvalidValue;
+  {
+    ProfScope ps(c.prof, st, KK_CGS_DOTS, 8.0 * n * (j + (w ? 2 : 1)));
+    JDispatch<DotsF>::run(j, c, Q, ld, u, w, n, st);
+  }
+  return reduce_partials_n(c, red_blocks(n / 2), 2 * j + 2, out, st);
+}
+
 hipError_t dcgs_update(const Ctx& c, const double* Q, long long ld, const DcgsCoef& cf, double* u, const double* w,
                        double* qj, long long n, hipStream_t st) {
+  if (cf.j < 0 || cf.j > 31) return hipErrorInvalidValue;
   ProfScope ps(c.prof, st, KK_CGS_UPDATE_DOTS, 8.0 * n * (cf.j + 4));
-  if (cf.j <= 4) du_t<4>(c, Q, ld, cf, u, w, qj, n, st);
-  else if (cf.j <= 8) du_t<8>(c, Q, ld, cf, u, w, qj, n, st);
-  else if (cf.j <= 16) du_t<16>(c, Q, ld, cf, u, w, qj, n, st);
-  else if (cf.j <= 32) du_t<32>(c, Q, ld, cf, u, w, qj, n, st);
-  else du_t<64>(c, Q, ld, cf, u, w, qj, n, st);
+  JDispatch<UpdF>::run(cf.j, c, Q, ld, cf, u, w, qj, n, st);
   return hipGetLastError();
 }
 

@@ -76,6 +76,11 @@ struct PipeIO {
   long long ng;
   const T* aux_v;    // EPI_JT: forward velocity v (3 planes)
   const T* aux_r;    // EPI_JT: forward multiplier (1 plane)
+  // Residual form: when rhs is set, the pipeline writes out = rhs - (operator
+  // output) and each x-inverse block stores the partial sum of squares of its
+  // outputs at red[blockIdx.x].
+  const TOut* rhs = nullptr;
+  double* red = nullptr;
 };
 
 }  // namespace llg

@@ -28,26 +28,41 @@ struct XCfg {
 
 __device__ __forceinline__ int xphys(int pos) { return pos + (pos >> 4); }
 
+// Grid planes (inputs, magnetization, outputs) are streamed with non-temporal
+// hints: each is touched once per pipeline and is far larger than the caches.
+// The spectral buffer is accessed with ordinary (cacheable) loads and stores:
+// it is reused by the next pass, and in float32 (about 200 MB at 256^3) much
+// of it stays in the 256 MB Infinity Cache between passes.
+#ifndef LLG_PIPE_NT
+#define LLG_PIPE_NT 1
+#endif
+template <typename U>
+__device__ __forceinline__ U ld_s(const U* p) {
+#if LLG_PIPE_NT
+  return __builtin_nontemporal_load(p);
+#else
+  return *p;
+#endif
+}
+template <typename U>
+__device__ __forceinline__ void st_s(U* p, U v) {
+#if LLG_PIPE_NT
+  __builtin_nontemporal_store(v, p);
+#else
+  *p = v;
+#endif
+}
+
 template <typename U>
 __device__ __forceinline__ void load2(const U* __restrict__ p, U& a, U& b) {
-  if constexpr (sizeof(U) == 8) {
-    const double2 t = *reinterpret_cast<const double2*>(p);
-    a = t.x;
-    b = t.y;
-  } else {
-    const float2 t = *reinterpret_cast<const float2*>(p);
-    a = t.x;
-    b = t.y;
-  }
+  a = ld_s(p);
+  b = ld_s(p + 1);
 }
 
 template <typename U>
 __device__ __forceinline__ void store2(U* __restrict__ p, U a, U b) {
-  if constexpr (sizeof(U) == 8) {
-    *reinterpret_cast<double2*>(p) = double2{a, b};
-  } else {
-    *reinterpret_cast<float2*>(p) = float2{a, b};
-  }
+  st_s(p, a);
+  st_s(p + 1, b);
 }
 
 // ---------------------------------------------------------------------------
@@ -162,9 +177,9 @@ __device__ __forceinline__ void epilogue_node(const PipeIO<T, TIn, TOut>& io, lo
     o[2] = -c * F[2] + hs * h2;
     o[3] = T(0);
   } else {
-    const V3<T> m{io.m[j], io.m[ng + j], io.m[2 * ng + j]};
-    const V3<T> v{T(io.in[j]), T(io.in[ng + j]), T(io.in[2 * ng + j])};
-    const T r = T(io.in[3 * ng + j]);
+    const V3<T> m{ld_s(io.m + j), ld_s(io.m + ng + j), ld_s(io.m + 2 * ng + j)};
+    const V3<T> v{T(ld_s(io.in + j)), T(ld_s(io.in + ng + j)), T(ld_s(io.in + 2 * ng + j))};
+    const T r = T(ld_s(io.in + 3 * ng + j));
     if constexpr (EPI == EPI_APPLY) {
       V3<T> z;
       T zr;
@@ -229,13 +244,24 @@ __global__ __launch_bounds__(192) void k_xfwd(const TIn* __restrict__ in, const 
   const long long line0 = (long long)blockIdx.x * C::LX;
   constexpr int NX = 2 * NH;
 
-  for (int e = tid; e < C::LX * NH; e += C::NT) {
-    const int l = e / NH, xp = e % NH;
-    const long long line = line0 + l;
-    cx<T> u[3] = {{T(0), T(0)}, {T(0), T(0)}, {T(0), T(0)}};
-    if (line < nlines) prologue<T, TIn, PRO>(in, m, g.ng, line * NX + 2 * xp, na, u);
+  // Copy-in with the prologue.  Indices are clamped instead of guarded so that
+  // the global loads of all iterations are unconditional and can be in flight
+  // together; only the LDS writes are predicated.
+  constexpr int NPAIR = C::LX * NH;
+  constexpr int ITERS = (NPAIR + C::NT - 1) / C::NT;
 #pragma unroll
-    for (int f = 0; f < 3; ++f) lds[(f * C::LX + l) * C::SL + xphys(xp)] = u[f];
+  for (int it = 0; it < ITERS; ++it) {
+    const int e0 = tid + it * C::NT;
+    const int e = e0 < NPAIR ? e0 : NPAIR - 1;
+    const int l = e / NH, xp = e % NH;
+    const long long line = line0 + l < nlines ? line0 + l : nlines - 1;
+    cx<T> u[3];
+    prologue<T, TIn, PRO>(in, m, g.ng, line * NX + 2 * xp, na, u);
+    if (e0 < NPAIR) {
+      const bool live = line0 + l < nlines;
+#pragma unroll
+      for (int f = 0; f < 3; ++f) lds[(f * C::LX + l) * C::SL + xphys(xp)] = live ? u[f] : cx<T>{T(0), T(0)};
+    }
   }
   __syncthreads();
 
@@ -283,11 +309,21 @@ __global__ __launch_bounds__(192) void k_xinv(PipeIO<T, TIn, TOut> io, const cx<
   constexpr int NX = 2 * NH;
   constexpr int CS = 3 * (NH + 1);
 
-  for (int e = tid; e < C::LX * CS; e += C::NT) {
-    const int l = e / CS, col = e % CS;
-    const long long line = line0 + l;
-    const int f = col / (NH + 1), k = col % (NH + 1);
-    lds[(f * C::LX + l) * C::SL + xphys(k)] = line < nlines ? spec[line * g.rs + col] : cx<T>{T(0), T(0)};
+  {
+    constexpr int NV = C::LX * CS;
+    constexpr int ITERS = (NV + C::NT - 1) / C::NT;
+#pragma unroll
+    for (int it = 0; it < ITERS; ++it) {
+      const int e0 = tid + it * C::NT;
+      const int e = e0 < NV ? e0 : NV - 1;
+      const int l = e / CS, col = e % CS;
+      const long long line = line0 + l < nlines ? line0 + l : nlines - 1;
+      const cx<T> val = spec[line * g.rs + col];
+      if (e0 < NV) {
+        const int f = col / (NH + 1), k = col % (NH + 1);
+        lds[(f * C::LX + l) * C::SL + xphys(k)] = line0 + l < nlines ? val : cx<T>{T(0), T(0)};
+      }
+    }
   }
   __syncthreads();
 
@@ -312,10 +348,17 @@ __global__ __launch_bounds__(192) void k_xinv(PipeIO<T, TIn, TOut> io, const cx<
   for (int s = 0; s < C::P; ++s) acc(t + C::TPL * out_q<NH>(s)) = v[s];
   __syncthreads();
 
-  for (int e = tid; e < C::LX * NH; e += C::NT) {
+  // Epilogue with clamped (unconditional) loads, predicated stores.
+  double rsum = 0.0;
+  constexpr int NPAIR = C::LX * NH;
+  constexpr int ITERS = (NPAIR + C::NT - 1) / C::NT;
+#pragma unroll
+  for (int it = 0; it < ITERS; ++it) {
+    const int e0 = tid + it * C::NT;
+    const int e = e0 < NPAIR ? e0 : NPAIR - 1;
     const int l = e / NH, xp = e % NH;
-    const long long line = line0 + l;
-    if (line >= nlines) continue;
+    const bool live = e0 < NPAIR && line0 + l < nlines;
+    const long long line = line0 + l < nlines ? line0 + l : nlines - 1;
     const long long i = line * NX + 2 * xp;
     cx<T> fz[3];
 #pragma unroll
@@ -328,8 +371,34 @@ __global__ __launch_bounds__(192) void k_xinv(PipeIO<T, TIn, TOut> io, const cx<
       epilogue_node<T, TIn, TOut, EPI>(io, i + 1, F1, na, o1);
     }
     constexpr int NOUT = EPI == EPI_STORE3 ? 3 : 4;
+    if (io.rhs) {
 #pragma unroll
-    for (int f = 0; f < NOUT; ++f) store2(io.out + f * io.ng + i, TOut(o0[f]), TOut(o1[f]));
+      for (int f = 0; f < NOUT; ++f) {
+        TOut r0, r1;
+        load2(io.rhs + f * io.ng + i, r0, r1);
+        o0[f] = T(r0) - o0[f];
+        o1[f] = T(r1) - o1[f];
+        if (live) rsum += double(o0[f]) * double(o0[f]) + double(o1[f]) * double(o1[f]);
+      }
+    }
+    if (live) {
+#pragma unroll
+      for (int f = 0; f < NOUT; ++f) store2(io.out + f * io.ng + i, TOut(o0[f]), TOut(o1[f]));
+    }
+  }
+  if (io.rhs) {
+    // block partial of the residual norm (fixed order: deterministic)
+    __shared__ double rs[C::NT / 64];
+#pragma unroll
+    for (int off = 32; off > 0; off >>= 1) rsum += __shfl_xor(rsum, off, 64);
+    if ((tid & 63) == 0) rs[tid >> 6] = rsum;
+    __syncthreads();
+    if (tid == 0) {
+      double t = rs[0];
+#pragma unroll
+      for (int k = 1; k < C::NT / 64; ++k) t += rs[k];
+      io.red[blockIdx.x] = t;
+    }
   }
 }
 
@@ -360,7 +429,11 @@ __global__ __launch_bounds__(axis_w(N) * (N / plan_p(N))) void k_axis(cx<T>* __r
   cx<T>* base = spec + outer * so + (valid ? col : 0);
   cx<T> v[P];
 #pragma unroll
-  for (int q = 0; q < P; ++q) v[q] = valid ? base[(t + TPL * q) * sp] : cx<T>{T(0), T(0)};
+  for (int q = 0; q < P; ++q) v[q] = base[(t + TPL * q) * sp];
+  if (!valid) {
+#pragma unroll
+    for (int q = 0; q < P; ++q) v[q] = cx<T>{T(0), T(0)};
+  }
   cx<T>* col_lds = lds + c;
   auto acc = [col_lds](int pos) -> cx<T>& { return col_lds[pos * (W + 1)]; };
 
