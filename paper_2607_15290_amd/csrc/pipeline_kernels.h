@@ -103,40 +103,48 @@ __device__ __forceinline__ void shift_solve_t(V3<T> m, V3<T> w, T wr, T lam, V3<
 }
 
 // ---------------------------------------------------------------------------
-// Prologue: values of the three filtered fields at nodes i and i+1.
+// Prologue: values of the three filtered fields at nodes i and i+1, split into
+// a load phase (raw plane values) and a compute phase so that the loads of
+// several node pairs can be issued together.
 // ---------------------------------------------------------------------------
 template <typename T, typename TIn, int PRO>
-__device__ __forceinline__ void prologue(const TIn* __restrict__ in, const T* __restrict__ m, long long ng,
-                                         long long i, const NodalArgs& na, cx<T> (&u)[3]) {
+struct ProRaw {
+  static constexpr int NV = PRO == PRO_COPY3 ? 3 : 4;
+  static constexpr int NM = PRO == PRO_COPY3 ? 0 : 3;
+  TIn v[NV][2];
+  T m[NM > 0 ? NM : 1][2];
+};
+
+template <typename T, typename TIn, int PRO>
+__device__ __forceinline__ void prologue_load(const TIn* __restrict__ in, const T* __restrict__ m, long long ng,
+                                              long long i, ProRaw<T, TIn, PRO>& r) {
+  using R = ProRaw<T, TIn, PRO>;
+#pragma unroll
+  for (int f = 0; f < R::NV; ++f) load2(in + f * ng + i, r.v[f][0], r.v[f][1]);
+#pragma unroll
+  for (int f = 0; f < R::NM; ++f) load2(m + f * ng + i, r.m[f][0], r.m[f][1]);
+}
+
+template <typename T, typename TIn, int PRO>
+__device__ __forceinline__ void prologue_compute(const ProRaw<T, TIn, PRO>& r, const NodalArgs& na,
+                                                 cx<T> (&u)[3]) {
   if constexpr (PRO == PRO_COPY3) {
 #pragma unroll
-    for (int f = 0; f < 3; ++f) {
-      TIn a, b;
-      load2(in + f * ng + i, a, b);
-      u[f] = {T(a), T(b)};
-    }
+    for (int f = 0; f < 3; ++f) u[f] = {T(r.v[f][0]), T(r.v[f][1])};
   } else {
-    TIn va[4], vb[4];
-#pragma unroll
-    for (int f = 0; f < 4; ++f) load2(in + f * ng + i, va[f], vb[f]);
-    T ma[3], mb[3];
-#pragma unroll
-    for (int f = 0; f < 3; ++f) load2(m + f * ng + i, ma[f], mb[f]);
     const T lam = T(na.lam);
 #pragma unroll
     for (int h = 0; h < 2; ++h) {
-      const TIn* vv = h ? vb : va;
-      const T* mm = h ? mb : ma;
-      V3<T> mv{mm[0], mm[1], mm[2]};
-      V3<T> v{T(vv[0]), T(vv[1]), T(vv[2])};
-      const T r = T(vv[3]);
+      const V3<T> mv{r.m[0][h], r.m[1][h], r.m[2][h]};
+      const V3<T> v{T(r.v[0][h]), T(r.v[1][h]), T(r.v[2][h])};
+      const T rr = T(r.v[3][h]);
       V3<T> o;
       if constexpr (PRO == PRO_SMINUS) {
         const V3<T> c = cross3(mv, v);
-        o = {c.x + mv.x * r - lam * v.x, c.y + mv.y * r - lam * v.y, c.z + mv.z * r - lam * v.z};
+        o = {c.x + mv.x * rr - lam * v.x, c.y + mv.y * rr - lam * v.y, c.z + mv.z * rr - lam * v.z};
       } else {  // PRO_M2T
         T orr;
-        shift_solve_t(mv, v, r, lam, o, orr);
+        shift_solve_t(mv, v, rr, lam, o, orr);
       }
       if (h == 0) {
         u[0].x = o.x;
@@ -152,12 +160,57 @@ __device__ __forceinline__ void prologue(const TIn* __restrict__ in, const T* __
 }
 
 // ---------------------------------------------------------------------------
-// Epilogue at one node: F = filtered fields at this node; j = node index.
+// Epilogue on the node pair (i, i+1): load phase (16-byte pair loads of the
+// planes the mode needs) and compute phase.  F = filtered fields.
 // ---------------------------------------------------------------------------
 template <typename T, typename TIn, typename TOut, int EPI>
-__device__ __forceinline__ void epilogue_node(const PipeIO<T, TIn, TOut>& io, long long j, const T (&F)[3],
-                                              const NodalArgs& na, T (&o)[4]) {
+struct EpiRaw {
+  static constexpr bool NODAL = !(EPI == EPI_STORE3 || EPI == EPI_RHS);
+  TIn v[4][2];   // x or p planes (nodal modes)
+  T m[3][2];     // magnetization (nodal modes)
+  T av[3][2];    // forward velocity (EPI_JT)
+  T ar[2];       // forward multiplier (EPI_JT)
+  double hf[3][2];  // spatial field (EPI_RHS)
+  TOut rb[4][2];    // right-hand side (residual form)
+};
+
+template <typename T, typename TIn, typename TOut, int EPI>
+__device__ __forceinline__ void epilogue_load(const PipeIO<T, TIn, TOut>& io, const NodalArgs& na, long long i,
+                                              EpiRaw<T, TIn, TOut, EPI>& r) {
   const long long ng = io.ng;
+  if constexpr (EpiRaw<T, TIn, TOut, EPI>::NODAL) {
+    // EPI_APPLY needs only the multiplier plane of p
+#pragma unroll
+    for (int f = 0; f < 4; ++f) {
+      if (EPI != EPI_APPLY || f == 3) load2(io.in + f * ng + i, r.v[f][0], r.v[f][1]);
+      else r.v[f][0] = r.v[f][1] = TIn(0);
+    }
+#pragma unroll
+    for (int f = 0; f < 3; ++f) load2(io.m + f * ng + i, r.m[f][0], r.m[f][1]);
+    if constexpr (EPI == EPI_JT) {
+#pragma unroll
+      for (int f = 0; f < 3; ++f) load2(io.aux_v + f * ng + i, r.av[f][0], r.av[f][1]);
+      load2(io.aux_r + i, r.ar[0], r.ar[1]);
+    }
+  } else if constexpr (EPI == EPI_RHS) {
+    if (na.hfield) {
+#pragma unroll
+      for (int f = 0; f < 3; ++f) load2(na.hfield + f * ng + i, r.hf[f][0], r.hf[f][1]);
+    } else {
+#pragma unroll
+      for (int f = 0; f < 3; ++f) r.hf[f][0] = r.hf[f][1] = 0.0;
+    }
+  }
+  if (io.rhs) {
+    constexpr int NOUT = EPI == EPI_STORE3 ? 3 : 4;
+#pragma unroll
+    for (int f = 0; f < NOUT; ++f) load2(io.rhs + f * ng + i, r.rb[f][0], r.rb[f][1]);
+  }
+}
+
+template <typename T, typename TIn, typename TOut, int EPI>
+__device__ __forceinline__ void epilogue_compute(const EpiRaw<T, TIn, TOut, EPI>& r, int h, const T (&F)[3],
+                                                 const NodalArgs& na, T (&o)[4]) {
   const T lam = T(na.lam);
   if constexpr (EPI == EPI_STORE3) {
     o[0] = F[0];
@@ -165,25 +218,19 @@ __device__ __forceinline__ void epilogue_node(const PipeIO<T, TIn, TOut>& io, lo
     o[2] = F[2];
     o[3] = T(0);
   } else if constexpr (EPI == EPI_RHS) {
-    T h0 = T(na.hu0), h1 = T(na.hu1), h2 = T(na.hu2);
-    if (na.hfield) {
-      h0 += T(na.hfield[j]);
-      h1 += T(na.hfield[ng + j]);
-      h2 += T(na.hfield[2 * ng + j]);
-    }
     const T c = T(na.chat), hs = T(na.hs);
-    o[0] = -c * F[0] + hs * h0;
-    o[1] = -c * F[1] + hs * h1;
-    o[2] = -c * F[2] + hs * h2;
+    o[0] = -c * F[0] + hs * (T(na.hu0) + T(r.hf[0][h]));
+    o[1] = -c * F[1] + hs * (T(na.hu1) + T(r.hf[1][h]));
+    o[2] = -c * F[2] + hs * (T(na.hu2) + T(r.hf[2][h]));
     o[3] = T(0);
   } else {
-    const V3<T> m{ld_s(io.m + j), ld_s(io.m + ng + j), ld_s(io.m + 2 * ng + j)};
-    const V3<T> v{T(ld_s(io.in + j)), T(ld_s(io.in + ng + j)), T(ld_s(io.in + 2 * ng + j))};
-    const T r = T(ld_s(io.in + 3 * ng + j));
+    const V3<T> m{r.m[0][h], r.m[1][h], r.m[2][h]};
+    const V3<T> v{T(r.v[0][h]), T(r.v[1][h]), T(r.v[2][h])};
+    const T rr = T(r.v[3][h]);
     if constexpr (EPI == EPI_APPLY) {
       V3<T> z;
       T zr;
-      shift_solve(m, V3<T>{F[0], F[1], F[2]}, r / lam, lam, z, zr);
+      shift_solve(m, V3<T>{F[0], F[1], F[2]}, rr / lam, lam, z, zr);
       o[0] = z.x;
       o[1] = z.y;
       o[2] = z.z;
@@ -193,32 +240,32 @@ __device__ __forceinline__ void epilogue_node(const PipeIO<T, TIn, TOut>& io, lo
       o[0] = F[0];
       o[1] = F[1];
       o[2] = F[2];
-      o[3] = (lam * r - dot3(m, v)) * inv_d / lam;
+      o[3] = (lam * rr - dot3(m, v)) * inv_d / lam;
     } else if constexpr (EPI == EPI_MATVEC || EPI == EPI_MATVEC_T) {
       const V3<T> c = cross3(m, v);
       const T sg = EPI == EPI_MATVEC ? T(1) : T(-1);
-      o[0] = F[0] + sg * (c.x + m.x * r);
-      o[1] = F[1] + sg * (c.y + m.y * r);
-      o[2] = F[2] + sg * (c.z + m.z * r);
+      o[0] = F[0] + sg * (c.x + m.x * rr);
+      o[1] = F[1] + sg * (c.y + m.y * rr);
+      o[2] = F[2] + sg * (c.z + m.z * rr);
       o[3] = -sg * dot3(m, v);
     } else if constexpr (EPI == EPI_JT) {
       // J^T mu = (H mu_v - m^n x mu_v + (k/2) r_f mu_v - m^{n+1} mu_r, m_half . mu_v),
       // m = m^n, (v_f, r_f) the forward solution, m^{n+1} = m^n + k v_f,
-      // m_half = m^n + (k/2) v_f; here v = mu_v and r = mu_r.
+      // m_half = m^n + (k/2) v_f; here v = mu_v and rr = mu_r.
       const T hk = T(na.half_k);
-      const V3<T> vf{io.aux_v[j], io.aux_v[ng + j], io.aux_v[2 * ng + j]};
-      const T rf = io.aux_r[j];
+      const V3<T> vf{r.av[0][h], r.av[1][h], r.av[2][h]};
+      const T rf = r.ar[h];
       const V3<T> c = cross3(m, v);
       const V3<T> m1{m.x + T(2) * hk * vf.x, m.y + T(2) * hk * vf.y, m.z + T(2) * hk * vf.z};
       const V3<T> mh{m.x + hk * vf.x, m.y + hk * vf.y, m.z + hk * vf.z};
-      o[0] = F[0] - c.x + hk * rf * v.x - m1.x * r;
-      o[1] = F[1] - c.y + hk * rf * v.y - m1.y * r;
-      o[2] = F[2] - c.z + hk * rf * v.z - m1.z * r;
+      o[0] = F[0] - c.x + hk * rf * v.x - m1.x * rr;
+      o[1] = F[1] - c.y + hk * rf * v.y - m1.y * rr;
+      o[2] = F[2] - c.z + hk * rf * v.z - m1.z * rr;
       o[3] = dot3(mh, v);
     } else {  // EPI_FUSED
-      const T ur = -dot3(m, v) - lam * r;
+      const T ur = -dot3(m, v) - lam * rr;
       const V3<T> w{v.x + F[0], v.y + F[1], v.z + F[2]};
-      const T wr = r + ur / lam;
+      const T wr = rr + ur / lam;
       V3<T> z;
       T zr;
       shift_solve(m, w, wr, lam, z, zr);
@@ -249,18 +296,34 @@ __global__ __launch_bounds__(192) void k_xfwd(const TIn* __restrict__ in, const 
   // together; only the LDS writes are predicated.
   constexpr int NPAIR = C::LX * NH;
   constexpr int ITERS = (NPAIR + C::NT - 1) / C::NT;
+  constexpr int BATCH = 3;  // node pairs whose loads are in flight together
 #pragma unroll
-  for (int it = 0; it < ITERS; ++it) {
-    const int e0 = tid + it * C::NT;
-    const int e = e0 < NPAIR ? e0 : NPAIR - 1;
-    const int l = e / NH, xp = e % NH;
-    const long long line = line0 + l < nlines ? line0 + l : nlines - 1;
-    cx<T> u[3];
-    prologue<T, TIn, PRO>(in, m, g.ng, line * NX + 2 * xp, na, u);
-    if (e0 < NPAIR) {
-      const bool live = line0 + l < nlines;
+  for (int it0 = 0; it0 < ITERS; it0 += BATCH) {
+    ProRaw<T, TIn, PRO> raw[BATCH];
 #pragma unroll
-      for (int f = 0; f < 3; ++f) lds[(f * C::LX + l) * C::SL + xphys(xp)] = live ? u[f] : cx<T>{T(0), T(0)};
+    for (int b = 0; b < BATCH; ++b) {
+      if (it0 + b < ITERS) {
+        const int e0 = tid + (it0 + b) * C::NT;
+        const int e = e0 < NPAIR ? e0 : NPAIR - 1;
+        const int l = e / NH, xp = e % NH;
+        const long long line = line0 + l < nlines ? line0 + l : nlines - 1;
+        prologue_load<T, TIn, PRO>(in, m, g.ng, line * NX + 2 * xp, raw[b]);
+      }
+    }
+#pragma unroll
+    for (int b = 0; b < BATCH; ++b) {
+      if (it0 + b < ITERS) {
+        const int e0 = tid + (it0 + b) * C::NT;
+        const int e = e0 < NPAIR ? e0 : NPAIR - 1;
+        const int l = e / NH, xp = e % NH;
+        cx<T> u[3];
+        prologue_compute<T, TIn, PRO>(raw[b], na, u);
+        if (e0 < NPAIR) {
+          const bool live = line0 + l < nlines;
+#pragma unroll
+          for (int f = 0; f < 3; ++f) lds[(f * C::LX + l) * C::SL + xphys(xp)] = live ? u[f] : cx<T>{T(0), T(0)};
+        }
+      }
     }
   }
   __syncthreads();
@@ -348,13 +411,29 @@ __global__ __launch_bounds__(192) void k_xinv(PipeIO<T, TIn, TOut> io, const cx<
   for (int s = 0; s < C::P; ++s) acc(t + C::TPL * out_q<NH>(s)) = v[s];
   __syncthreads();
 
-  // Epilogue with clamped (unconditional) loads, predicated stores.
+  // Epilogue: clamped (unconditional) loads issued a batch of node pairs at
+  // a time, predicated stores.
   double rsum = 0.0;
   constexpr int NPAIR = C::LX * NH;
   constexpr int ITERS = (NPAIR + C::NT - 1) / C::NT;
+  constexpr int BATCH = 3;
 #pragma unroll
-  for (int it = 0; it < ITERS; ++it) {
-    const int e0 = tid + it * C::NT;
+  for (int it0 = 0; it0 < ITERS; it0 += BATCH) {
+  EpiRaw<T, TIn, TOut, EPI> raw[BATCH];
+#pragma unroll
+  for (int b = 0; b < BATCH; ++b) {
+    if (it0 + b < ITERS) {
+      const int e0 = tid + (it0 + b) * C::NT;
+      const int e = e0 < NPAIR ? e0 : NPAIR - 1;
+      const int l = e / NH, xp = e % NH;
+      const long long line = line0 + l < nlines ? line0 + l : nlines - 1;
+      epilogue_load<T, TIn, TOut, EPI>(io, na, line * NX + 2 * xp, raw[b]);
+    }
+  }
+#pragma unroll
+  for (int b = 0; b < BATCH; ++b) {
+    if (it0 + b >= ITERS) continue;
+    const int e0 = tid + (it0 + b) * C::NT;
     const int e = e0 < NPAIR ? e0 : NPAIR - 1;
     const int l = e / NH, xp = e % NH;
     const bool live = e0 < NPAIR && line0 + l < nlines;
@@ -366,18 +445,16 @@ __global__ __launch_bounds__(192) void k_xinv(PipeIO<T, TIn, TOut> io, const cx<
     T o0[4], o1[4];
     {
       const T F0[3] = {fz[0].x, fz[1].x, fz[2].x};
-      epilogue_node<T, TIn, TOut, EPI>(io, i, F0, na, o0);
+      epilogue_compute<T, TIn, TOut, EPI>(raw[b], 0, F0, na, o0);
       const T F1[3] = {fz[0].y, fz[1].y, fz[2].y};
-      epilogue_node<T, TIn, TOut, EPI>(io, i + 1, F1, na, o1);
+      epilogue_compute<T, TIn, TOut, EPI>(raw[b], 1, F1, na, o1);
     }
     constexpr int NOUT = EPI == EPI_STORE3 ? 3 : 4;
     if (io.rhs) {
 #pragma unroll
       for (int f = 0; f < NOUT; ++f) {
-        TOut r0, r1;
-        load2(io.rhs + f * io.ng + i, r0, r1);
-        o0[f] = T(r0) - o0[f];
-        o1[f] = T(r1) - o1[f];
+        o0[f] = T(raw[b].rb[f][0]) - o0[f];
+        o1[f] = T(raw[b].rb[f][1]) - o1[f];
         if (live) rsum += double(o0[f]) * double(o0[f]) + double(o1[f]) * double(o1[f]);
       }
     }
@@ -385,6 +462,7 @@ __global__ __launch_bounds__(192) void k_xinv(PipeIO<T, TIn, TOut> io, const cx<
 #pragma unroll
       for (int f = 0; f < NOUT; ++f) store2(io.out + f * io.ng + i, TOut(o0[f]), TOut(o1[f]));
     }
+  }
   }
   if (io.rhs) {
     // block partial of the residual norm (fixed order: deterministic)
