@@ -291,24 +291,24 @@ llg_status arnoldi_step(const Ctx& c, double* V, long long n4, int j, double* co
 }
 
 // One Krylov cycle with CGS2 whose re-orthogonalization is delayed by one
-// iteration (two streaming passes and one reduction per iteration).
+// iteration: two streaming passes over the basis and one host round trip per
+// iteration.
 //
-// U holds the start vector u_0 on entry (not normalized).  Iteration j:
-//   w = Op(u_j)                                   (speculative: Op of the
-//                                                  not yet re-orthogonalized u_j)
-//   pass 1: a = Q_j^T u_j, b = Q_j^T w, c = u_j.u_j, d = u_j.w
-//   beta = sqrt(c - a.a), q_j = (u_j - Q_j a) / beta;  column j-1 of H is
-//   h_{j-1} + a with subdiagonal beta (h_{j-1}: first projection of the
-//   previous iteration).  By the Arnoldi relation Op(Q_j a) = Q_{j+1} H a, so
-//   Op q_j = (w - Q_{j+1} g) / beta with g = H_{0:j+1,0:j} a, and the first
-//   projection of Op q_j onto Q_{j+1} follows from (a, b, d, g) alone:
-//   h_j[i] = (b_i - g_i)/beta (i < j), h_j[j] = ((d - a.b)/beta - g_j)/beta.
-//   pass 2: q_j = (u_j - Q_j a)/beta, u_{j+1} = (w - Q_{j+1} (g + beta h_j))/beta.
-// The cycle stops after finalizing column k-1 (the Givens residual estimate
-// is one iteration behind the speculative Op application).  With flexible =
-// true, Op also stores Ztilde_j = M^{-1} u_j and the returned coefficients
-// multiply Ztilde (q_j's preconditioned vector is (Ztilde_j - Z a)/beta, so
-// the Hessenberg solution is mapped through the triangular factor T).
+// U holds the start vector u_0 on entry (not normalized), c0 = ||u_0||^2.
+// Entering iteration j the host knows a = Q_j^T u_j and beta_j =
+// ||u_j - Q_j a|| (from the previous update pass), which finalizes column
+// j-1 of the Hessenberg matrix (h_{j-1} + a, subdiagonal beta_j) before any
+// further work, so a converged cycle launches nothing extra.  Then
+//   w = Op(u_j)                                  (u_j not yet re-orthogonalized)
+//   pass 1: b = Q_j^T w, d = u_j.w               (stays on the device)
+//   pass 2: q_j = (u_j - Q_j a)/beta_j,  u_{j+1} = (w - Q_j b - e_j q_j)/beta_j,
+//           e_j = (d - a.b)/beta_j  (the first projection of Op q_j, up to the
+//           factor 1/beta_j: Q_{j+1}^T Op q_j = ([b; e_j] - g)/beta_j with
+//           g = H a, the part of Op(Q_j a) given by the Arnoldi relation);
+//           pass 2 also forms Q_{j+1}^T u_{j+1} and ||u_{j+1}||^2.
+// With flexible = true, Op also stores Ztilde_j = M^{-1} u_j and the returned
+// coefficients multiply Ztilde (q_j's preconditioned vector is
+// (Ztilde_j - Z a)/beta_j, i.e. Z = Ztilde T^{-1} with T upper triangular).
 struct CycleResult {
   int k = 0;
   double beta0 = 0, gres = 0;
@@ -316,35 +316,24 @@ struct CycleResult {
 };
 
 llg_status cycle_dcgs2(const Ctx& c, const std::function<hipError_t(int, const double*, double*)>& op, double* Q,
-                       double* U, double* W, long long n4, int R, double eta, int maxiter, int& iters, bool flexible,
-                       CycleResult& out, hipStream_t st) {
+                       double* U, double* W, long long n4, double c0, int R, double eta, int maxiter, int& iters,
+                       bool flexible, CycleResult& out, hipStream_t st) {
   Hess hs(R);
   std::vector<double> Hraw(size_t(R + 1) * R, 0.0), T(size_t(R + 1) * (R + 1), 0.0);
-  std::vector<double> hprev, col(R + 2), vals(2 * kMaxDots), g(R + 2), hnew(R + 2);
+  std::vector<double> hprev, a, col(R + 2), g(R + 2), vals(2 * kMaxDots + 2);
   auto HR = [&](int i, int jj) -> double& { return Hraw[size_t(i) * R + jj]; };
   auto TT = [&](int i, int jj) -> double& { return T[size_t(i) * (R + 1) + jj]; };
+  if (!is_fin(c0)) return fail(LLG_ENAN, "non-finite Krylov start vector");
+  double beta = c0 > 0 ? std::sqrt(c0) : 0.0;
+  out.beta0 = beta;
+  hs.g[0] = beta;
   int k = 0;
-  for (int j = 0; j <= R; ++j) {
-    const bool need_w = j < R;
-    if (need_w) CHK(op(j, U, W));
-    CHK(dcgs_dots(c, Q, n4, j, U, need_w ? W : nullptr, n4, c.dots, st));
-    CHK_STATUS(fetch(c, c.dots, 2 * j + 2, st, vals.data()));
-    const double* a = vals.data();
-    const double* b = vals.data() + j;
-    const double cc = vals[2 * j], d = vals[2 * j + 1];
-    double aa = 0, ab = 0;
-    for (int i = 0; i < j; ++i) {
-      aa += a[i] * a[i];
-      ab += a[i] * b[i];
-    }
-    if (!is_fin(cc) || !is_fin(d) || !is_fin(aa)) return fail(LLG_ENAN, "non-finite Arnoldi inner products");
-    const double beta2 = cc - aa;
-    const double beta = beta2 > 0 ? std::sqrt(beta2) : 0.0;
-    if (j == 0) {
-      out.beta0 = beta;
-      hs.g[0] = beta;
-      if (beta == 0.0) break;
-    } else {
+  if (beta == 0.0) {
+    out.k = 0;
+    return LLG_OK;
+  }
+  for (int j = 0;; ++j) {
+    if (j > 0) {
       for (int i = 0; i < j; ++i) col[i] = hprev[i] + a[i];
       col[j] = beta;
       for (int i = 0; i <= j; ++i) HR(i, j - 1) = col[i];
@@ -355,24 +344,37 @@ llg_status cycle_dcgs2(const Ctx& c, const std::function<hipError_t(int, const d
     }
     for (int i = 0; i < j; ++i) TT(i, j) = a[i];
     TT(j, j) = beta;
-    // g = H_{0:j+1, 0:j} a
+    CHK(op(j, U, W));
+    CHK(dcgs_dots(c, Q, n4, j, U, W, n4, c.dots, st));
+    DcgsCoef cf{};
+    for (int i = 0; i < j; ++i) cf.a[i] = a[i];
+    cf.inv_beta = 1.0 / beta;
+    cf.j = j;
+    CHK(dcgs_update(c, Q, n4, cf, c.dots, U, W, Q + size_t(j) * n4, n4, c.dots2, st));
+    // one round trip: pass-1 results (b, d) and the next (a, c)
+    CHK(hipMemcpyAsync(c.host, c.dots, sizeof(double) * 2 * kMaxDots, hipMemcpyDeviceToHost, st));
+    CHK(hipStreamSynchronize(st));
+    std::memcpy(vals.data(), c.host, sizeof(double) * 2 * kMaxDots);
+    const double* b = vals.data();
+    const double d = vals[j];
+    const double* an = vals.data() + kMaxDots;
+    const double cn = vals[kMaxDots + j + 1];
+    double ab = 0, aa = 0;
+    for (int i = 0; i < j; ++i) ab += a[i] * b[i];
+    for (int i = 0; i <= j; ++i) aa += an[i] * an[i];
+    if (!is_fin(d) || !is_fin(cn) || !is_fin(aa)) return fail(LLG_ENAN, "non-finite Arnoldi inner products");
+    // first projection of Op q_j: h_j = ([b; e_j] - g) / beta, g = H_{0:j+1,0:j} a
     for (int r = 0; r <= j; ++r) {
       double sgm = 0;
       for (int i = std::max(0, r - 1); i < j; ++i) sgm += HR(r, i) * a[i];
       g[r] = sgm;
     }
-    for (int i = 0; i < j; ++i) hnew[i] = (b[i] - g[i]) / beta;
-    hnew[j] = ((d - ab) / beta - g[j]) / beta;
-    DcgsCoef cf{};
-    for (int i = 0; i < j; ++i) {
-      cf.a[i] = a[i];
-      cf.e[i] = g[i] + beta * hnew[i];
-    }
-    cf.ej = g[j] + beta * hnew[j];
-    cf.inv_beta = 1.0 / beta;
-    cf.j = j;
-    CHK(dcgs_update(c, Q, n4, cf, U, W, Q + size_t(j) * n4, n4, st));
-    hprev.assign(hnew.begin(), hnew.begin() + j + 1);
+    hprev.assign(j + 1, 0.0);
+    for (int i = 0; i < j; ++i) hprev[i] = (b[i] - g[i]) / beta;
+    hprev[j] = ((d - ab) / beta - g[j]) / beta;
+    a.assign(an, an + j + 1);
+    const double beta2 = cn - aa;
+    beta = beta2 > 0 ? std::sqrt(beta2) : 0.0;
   }
   out.k = k;
   hs.solve(k, out.y);
@@ -438,9 +440,12 @@ llg_status gmres_left(const Ctx& c, const ResidOp& RA, const Op& M, const Op& MA
       double* U = w.V + size_t(R) * n4;
       double* W = w.V + size_t(R + 1) * n4;
       CHK(M(w.r, U));
+      double un[2];
+      CHK(dot_and_norm(c, U, nullptr, n4, c.scal, st));
+      CHK_STATUS(fetch(c, c.scal, 2, st, un));
       CycleResult cr;
       auto op = [&](int, const double* u, double* wout) { return MA(u, wout); };
-      CHK_STATUS(cycle_dcgs2(c, op, Q, U, W, n4, R, target / rho, o.maxiter, res.iters, false, cr, st));
+      CHK_STATUS(cycle_dcgs2(c, op, Q, U, W, n4, un[1], R, target / rho, o.maxiter, res.iters, false, cr, st));
       if (!is_fin(cr.beta0)) return fail(LLG_ENAN, "non-finite preconditioned residual");
       if (beta0 < 0) beta0 = cr.beta0;
       res.rel_prec = beta0 > 0 ? cr.gres / beta0 : 0.0;
@@ -543,8 +548,8 @@ llg_status gmres_ir(const Ctx& c, const llg_params* p, const double* m, const do
       };
       CycleResult cr;
       // u_0 = r (the residual buffer is consumed as the cycle's start vector)
-      CHK_STATUS(cycle_dcgs2(c, op, Q, w.r, W, n4, R, std::max(o.inner_rtol, target / rho), o.maxiter, res.iters,
-                             true, cr, st));
+      CHK_STATUS(cycle_dcgs2(c, op, Q, w.r, W, n4, rho * rho, R, std::max(o.inner_rtol, target / rho), o.maxiter,
+                             res.iters, true, cr, st));
       res.rel_prec = cr.gres / bnorm;
       if (cr.k == 0) break;
       CHK(lincomb(c, n4, cr.y, w.Z, n4, x, st));

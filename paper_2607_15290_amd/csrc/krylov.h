@@ -13,27 +13,26 @@ struct Coefs {
 // Coefficients of the second pass of CGS2 with delayed re-orthogonalization.
 struct DcgsCoef {
   double a[64];   // re-orthogonalization coefficients of u against Q_0..Q_{j-1}
-  double e[64];   // projection coefficients of w against Q_0..Q_{j-1}
-  double ej;      // coefficient of the new q_j in the projection of w
   double inv_beta;
   int j;
 };
 
-// out = [Q_i.u (i<j), Q_i.w (i<j), u.u, u.w]; with w null only Q_i.u and u.u
-// (out[2j] = u.u, out[2j+1] = 0).  j <= 31.
+// Pass 1: out = [Q_i.w (i < j), u.w].  j <= 31.
 hipError_t dcgs_dots(const Ctx& c, const double* Q, long long ld, int j, const double* u, const double* w,
                      long long n, double* out, hipStream_t st);
-// qj = (u - sum a_i Q_i)/beta ; u <- (w - sum e_i Q_i - ej qj)/beta
-hipError_t dcgs_update(const Ctx& c, const double* Q, long long ld, const DcgsCoef& cf, double* u, const double* w,
-                       double* qj, long long n, hipStream_t st);
+// Pass 2 (bd = pass-1 output on the device):
+//   qj = (u - sum a_i Q_i)/beta ; u <- (w - sum bd_i Q_i - e_j qj)/beta, e_j = (bd_j - a.bd)/beta
+//   out = [Q_i.u (i < j), qj.u, u.u] for the new u.
+hipError_t dcgs_update(const Ctx& c, const double* Q, long long ld, const DcgsCoef& cf, const double* bd, double* u,
+                       const double* w, double* qj, long long n, double* out, hipStream_t st);
 
 hipError_t reduce_partials(const Ctx& c, int nv, double* out, bool is_max, hipStream_t st);
 // sum over the first nb block partials (stride kMaxDots) of nv values
 hipError_t reduce_partials_n(const Ctx& c, int nb, int nv, double* out, hipStream_t st);
-// Blocks of a delayed-CGS2 dot pass over n2 16-byte elements: about four
-// elements per thread, at most kRedBlocksMax; depends only on n2.
+// Blocks of a delayed-CGS2 pass over n2 16-byte elements: two elements per
+// thread, at most kRedBlocksMax; depends only on n2 (deterministic order).
 inline int red_blocks(long long n2) {
-  long long g = (n2 + 4 * kRedThreads - 1) / (4 * kRedThreads);
+  long long g = (n2 + 2 * kRedThreads - 1) / (2 * kRedThreads);
   if (g > kRedBlocksMax) g = kRedBlocksMax;
   return int(g < 1 ? 1 : g);
 }

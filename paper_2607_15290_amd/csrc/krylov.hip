@@ -99,6 +99,32 @@ __global__ __launch_bounds__(kRedThreads) void k_reduce_flat(const double* __res
   }
 }
 
+// out[i] = sum_b partial[i * nb + b]: value-major partials, one block of 1024
+// threads per value, four independent accumulators per thread (fixed order).
+__global__ __launch_bounds__(1024) void k_reduce_vmajor(const double* __restrict__ partial, int nb,
+                                                       double* __restrict__ out) {
+  const double* p = partial + (long long)blockIdx.x * nb;
+  double s0 = 0.0, s1 = 0.0, s2 = 0.0, s3 = 0.0;
+  int b = threadIdx.x;
+  for (; b + 3 * 1024 < nb; b += 4 * 1024) {
+    s0 += p[b];
+    s1 += p[b + 1024];
+    s2 += p[b + 2048];
+    s3 += p[b + 3072];
+  }
+  for (; b < nb; b += 1024) s0 += p[b];
+  double s = (s0 + s1) + (s2 + s3);
+  __shared__ double sm[1024 / 64];
+  s = wave_sum(s);
+  if ((threadIdx.x & 63) == 0) sm[threadIdx.x >> 6] = s;
+  __syncthreads();
+  if (threadIdx.x == 0) {
+    double t = sm[0];
+    for (int w = 1; w < 1024 / 64; ++w) t += sm[w];
+    out[blockIdx.x] = t;
+  }
+}
+
 // ---- CGS2 passes ----------------------------------------------------------
 template <int MAXV>
 __global__ __launch_bounds__(kRedThreads) void k_mdot(const double* __restrict__ V, long long ld, int nv,
@@ -169,84 +195,106 @@ __global__ __launch_bounds__(kRedThreads) void k_update_norm(const double* __res
 // ---- CGS2 with delayed re-orthogonalization (two passes per iteration) -------
 // Both passes are instantiated for the exact number J of basis vectors, so
 // every basis load of a thread is unconditional and the loads of one element
-// are all in flight together.
+// are all in flight together; loads and stores are non-temporal.
 //
-// Pass 1: out = [Q_i.u (i < J), Q_i.w (i < J), u.u, u.w]  (HAS_W = false: only
-// Q_i.u and u.u).  Streams Q_0..Q_{J-1}, u and w once.
-template <int J, bool HAS_W>
+// Pass 1: out = [Q_i.w (i < J), u.w], value-major partials.
+template <int J>
 __global__ __launch_bounds__(kRedThreads) void k_dcgs_dots(const double2* __restrict__ Q, long long ld2,
                                                           const double2* __restrict__ u,
                                                           const double2* __restrict__ w, long long n2,
                                                           double* __restrict__ partial) {
   constexpr int NA = J > 0 ? J : 1;
-  double au[NA], aw[NA];
+  double aw[NA];
 #pragma unroll
-  for (int i = 0; i < NA; ++i) au[i] = aw[i] = 0.0;
-  double cuu = 0.0, cuw = 0.0;
+  for (int i = 0; i < NA; ++i) aw[i] = 0.0;
+  double cuw = 0.0;
   const long long stride = (long long)gridDim.x * blockDim.x;
   for (long long e = (long long)blockIdx.x * blockDim.x + threadIdx.x; e < n2; e += stride) {
-    const double2 uu = ldnt(u + e);
-    double2 ww{0.0, 0.0};
-    if constexpr (HAS_W) ww = ldnt(w + e);
+    const double2 uu = ldnt(u + e), ww = ldnt(w + e);
     double2 q[NA];
 #pragma unroll
     for (int i = 0; i < J; ++i) q[i] = ldnt(Q + i * ld2 + e);
-    cuu = fma(uu.x, uu.x, fma(uu.y, uu.y, cuu));
-    if constexpr (HAS_W) cuw = fma(uu.x, ww.x, fma(uu.y, ww.y, cuw));
+    cuw = fma(uu.x, ww.x, fma(uu.y, ww.y, cuw));
 #pragma unroll
-    for (int i = 0; i < J; ++i) {
-      au[i] = fma(q[i].x, uu.x, fma(q[i].y, uu.y, au[i]));
-      if constexpr (HAS_W) aw[i] = fma(q[i].x, ww.x, fma(q[i].y, ww.y, aw[i]));
-    }
+    for (int i = 0; i < J; ++i) aw[i] = fma(q[i].x, ww.x, fma(q[i].y, ww.y, aw[i]));
   }
-  __shared__ double sm[kRedThreads / 64][2 * J + 2];
+  __shared__ double sm[kRedThreads / 64][J + 1];
   const int lane = threadIdx.x & 63, wv = threadIdx.x >> 6;
 #pragma unroll
   for (int i = 0; i < J; ++i) {
-    const double x = wave_sum(au[i]);
-    const double y = HAS_W ? wave_sum(aw[i]) : 0.0;
-    if (lane == 0) {
-      sm[wv][i] = x;
-      sm[wv][J + i] = y;
-    }
+    const double y = wave_sum(aw[i]);
+    if (lane == 0) sm[wv][i] = y;
   }
   {
-    const double x = wave_sum(cuu), y = HAS_W ? wave_sum(cuw) : 0.0;
-    if (lane == 0) {
-      sm[wv][2 * J] = x;
-      sm[wv][2 * J + 1] = y;
-    }
+    const double y = wave_sum(cuw);
+    if (lane == 0) sm[wv][J] = y;
   }
   __syncthreads();
-  if (threadIdx.x < 2 * J + 2) {
+  if (threadIdx.x < J + 1) {
     double t = sm[0][threadIdx.x];
 #pragma unroll
     for (int k = 1; k < kRedThreads / 64; ++k) t += sm[k][threadIdx.x];
-    partial[blockIdx.x * kMaxDots + threadIdx.x] = t;
+    partial[(long long)threadIdx.x * gridDim.x + blockIdx.x] = t;
   }
 }
 
-// Pass 2: q_J = (u - sum_i a_i Q_i) / beta ;  u <- (w - sum_i e_i Q_i - e_J q_J) / beta.
+// Pass 2: with (b, d) = pass-1 results (device), a and beta from the host:
+//   q_J = (u - sum_i a_i Q_i) / beta
+//   u  <- (w - sum_i b_i Q_i - e_J q_J) / beta,   e_J = (d - a.b) / beta
+// and, for the next iteration, out = [Q_i.u_new (i < J), q_J.u_new, u_new.u_new].
 template <int J>
-__global__ __launch_bounds__(256) void k_dcgs_update(const double2* __restrict__ Q, long long ld2, DcgsCoef cf,
-                                                    double2* u, const double2* __restrict__ w,
-                                                    double2* __restrict__ qj, long long n2) {
+__global__ __launch_bounds__(kRedThreads) void k_dcgs_update(const double2* __restrict__ Q, long long ld2,
+                                                            DcgsCoef cf, const double* __restrict__ bd,
+                                                            double2* u, const double2* __restrict__ w,
+                                                            double2* __restrict__ qj, long long n2,
+                                                            double* __restrict__ partial) {
+  constexpr int NA = J > 0 ? J : 1;
+  double bb[NA];
+  double ab = 0.0;
+#pragma unroll
+  for (int i = 0; i < J; ++i) {
+    bb[i] = bd[i];
+    ab = fma(cf.a[i], bb[i], ab);
+  }
+  const double ej = (bd[J] - ab) * cf.inv_beta;
+  double acc[J + 2];
+#pragma unroll
+  for (int i = 0; i < J + 2; ++i) acc[i] = 0.0;
   const long long stride = (long long)gridDim.x * blockDim.x;
   for (long long e = (long long)blockIdx.x * blockDim.x + threadIdx.x; e < n2; e += stride) {
     double2 sa = ldnt(u + e), se = ldnt(w + e);
-    double2 q[J > 0 ? J : 1];
+    double2 q[NA];
 #pragma unroll
     for (int i = 0; i < J; ++i) q[i] = ldnt(Q + i * ld2 + e);
 #pragma unroll
     for (int i = 0; i < J; ++i) {
       sa.x = fma(-cf.a[i], q[i].x, sa.x);
       sa.y = fma(-cf.a[i], q[i].y, sa.y);
-      se.x = fma(-cf.e[i], q[i].x, se.x);
-      se.y = fma(-cf.e[i], q[i].y, se.y);
+      se.x = fma(-bb[i], q[i].x, se.x);
+      se.y = fma(-bb[i], q[i].y, se.y);
     }
     const double2 qn{sa.x * cf.inv_beta, sa.y * cf.inv_beta};
+    const double2 un{(se.x - ej * qn.x) * cf.inv_beta, (se.y - ej * qn.y) * cf.inv_beta};
     stnt(qj + e, qn);
-    stnt(u + e, double2{(se.x - cf.ej * qn.x) * cf.inv_beta, (se.y - cf.ej * qn.y) * cf.inv_beta});
+    stnt(u + e, un);
+#pragma unroll
+    for (int i = 0; i < J; ++i) acc[i] = fma(q[i].x, un.x, fma(q[i].y, un.y, acc[i]));
+    acc[J] = fma(qn.x, un.x, fma(qn.y, un.y, acc[J]));
+    acc[J + 1] = fma(un.x, un.x, fma(un.y, un.y, acc[J + 1]));
+  }
+  __shared__ double sm[kRedThreads / 64][J + 2];
+  const int lane = threadIdx.x & 63, wv = threadIdx.x >> 6;
+#pragma unroll
+  for (int i = 0; i < J + 2; ++i) {
+    const double y = wave_sum(acc[i]);
+    if (lane == 0) sm[wv][i] = y;
+  }
+  __syncthreads();
+  if (threadIdx.x < J + 2) {
+    double t = sm[0][threadIdx.x];
+#pragma unroll
+    for (int k = 1; k < kRedThreads / 64; ++k) t += sm[k][threadIdx.x];
+    partial[(long long)threadIdx.x * gridDim.x + blockIdx.x] = t;
   }
 }
 
@@ -265,13 +313,18 @@ __global__ void k_axpby(long long n, double a, const double* __restrict__ x, dou
     out[e] = a * x[e] + b * y[e];
 }
 
-template <typename TV>
-__global__ void k_lincomb(long long n, Coefs cf, const TV* __restrict__ V, long long ld,
-                          double* __restrict__ x) {
+// x += sum_i c_i V_i, instantiated for the exact count K so the K basis loads
+// of an element are issued together.
+template <typename TV, int K>
+__global__ void k_lincomb(long long n, Coefs cf, const TV* __restrict__ V, long long ld, double* __restrict__ x) {
   const long long stride = (long long)gridDim.x * blockDim.x;
   for (long long e = (long long)blockIdx.x * blockDim.x + threadIdx.x; e < n; e += stride) {
+    TV vv[K > 0 ? K : 1];
+#pragma unroll
+    for (int i = 0; i < K; ++i) vv[i] = __builtin_nontemporal_load(V + i * ld + e);
     double s = x[e];
-    for (int i = 0; i < cf.n; ++i) s = fma(cf.c[i], double(V[i * ld + e]), s);
+#pragma unroll
+    for (int i = 0; i < K; ++i) s = fma(cf.c[i], double(vv[i]), s);
     x[e] = s;
   }
 }
@@ -317,7 +370,7 @@ static inline unsigned grid_for(long long n) {
 
 hipError_t reduce_partials_n(const Ctx& c, int nb, int nv, double* out, hipStream_t st) {
   ProfScope ps(c.prof, st, KK_REDUCE, 8.0 * nb * nv);
-  hipLaunchKernelGGL((k_reduce<false>), dim3(nv), dim3(kRedThreads), 0, st, c.partial, nb, out);
+  hipLaunchKernelGGL(k_reduce_vmajor, dim3(nv), dim3(1024), 0, st, c.partial, nb, out);
   return hipGetLastError();
 }
 
@@ -391,27 +444,17 @@ hipError_t cgs_update_norm(const Ctx& c, const double* V, long long ld, int nv, 
 template <int J>
 static void dd_t(const Ctx& c, const double* Q, long long ld, const double* u, const double* w, long long n,
                  hipStream_t st) {
-  auto Q2 = reinterpret_cast<const double2*>(Q);
-  auto u2 = reinterpret_cast<const double2*>(u);
-  auto w2 = reinterpret_cast<const double2*>(w);
-  const int nb = red_blocks(n / 2);
-  if (w)
-    hipLaunchKernelGGL((k_dcgs_dots<J, true>), dim3(nb), dim3(kRedThreads), 0, st, Q2, ld / 2, u2, w2, n / 2,
-                       c.partial);
-  else
-    hipLaunchKernelGGL((k_dcgs_dots<J, false>), dim3(nb), dim3(kRedThreads), 0, st, Q2, ld / 2, u2, w2,
-                       n / 2, c.partial);
+  hipLaunchKernelGGL((k_dcgs_dots<J>), dim3(red_blocks(n / 2)), dim3(kRedThreads), 0, st,
+                     reinterpret_cast<const double2*>(Q), ld / 2, reinterpret_cast<const double2*>(u),
+                     reinterpret_cast<const double2*>(w), n / 2, c.partial);
 }
 
 template <int J>
-static void du_t(const Ctx& c, const double* Q, long long ld, const DcgsCoef& cf, double* u, const double* w,
-                 double* qj, long long n, hipStream_t st) {
-  const long long n2 = n / 2;
-  long long g = (n2 + 255) / 256;  // one 16-byte element per thread
-  if (g > (1LL << 30)) g = 1LL << 30;
-  hipLaunchKernelGGL((k_dcgs_update<J>), dim3((unsigned)g), dim3(256), 0, st, reinterpret_cast<const double2*>(Q),
-                     ld / 2, cf, reinterpret_cast<double2*>(u), reinterpret_cast<const double2*>(w),
-                     reinterpret_cast<double2*>(qj), n2);
+static void du_t(const Ctx& c, const double* Q, long long ld, const DcgsCoef& cf, const double* bd, double* u,
+                 const double* w, double* qj, long long n, hipStream_t st) {
+  hipLaunchKernelGGL((k_dcgs_update<J>), dim3(red_blocks(n / 2)), dim3(kRedThreads), 0, st,
+                     reinterpret_cast<const double2*>(Q), ld / 2, cf, bd, reinterpret_cast<double2*>(u),
+                     reinterpret_cast<const double2*>(w), reinterpret_cast<double2*>(qj), n / 2, c.partial);
 }
 
 // Runtime J -> template instantiation J = 0..31.
@@ -438,18 +481,20 @@ hipError_t dcgs_dots(const Ctx& c, const double* Q, long long ld, int j, const d
                      long long n, double* out, hipStream_t st) {
   if (j < 0 || j > 31) return hipErrorInvalidValue;
   {
-    ProfScope ps(c.prof, st, KK_CGS_DOTS, 8.0 * n * (j + (w ? 2 : 1)));
+    ProfScope ps(c.prof, st, KK_CGS_DOTS, 8.0 * n * (j + 2));
     JDispatch<DotsF>::run(j, c, Q, ld, u, w, n, st);
   }
-  return reduce_partials_n(c, red_blocks(n / 2), 2 * j + 2, out, st);
+  return reduce_partials_n(c, red_blocks(n / 2), j + 1, out, st);
 }
 
-hipError_t dcgs_update(const Ctx& c, const double* Q, long long ld, const DcgsCoef& cf, double* u, const double* w,
-                       double* qj, long long n, hipStream_t st) {
+hipError_t dcgs_update(const Ctx& c, const double* Q, long long ld, const DcgsCoef& cf, const double* bd, double* u,
+                       const double* w, double* qj, long long n, double* out, hipStream_t st) {
   if (cf.j < 0 || cf.j > 31) return hipErrorInvalidValue;
-  ProfScope ps(c.prof, st, KK_CGS_UPDATE_DOTS, 8.0 * n * (cf.j + 4));
-  JDispatch<UpdF>::run(cf.j, c, Q, ld, cf, u, w, qj, n, st);
-  return hipGetLastError();
+  {
+    ProfScope ps(c.prof, st, KK_CGS_UPDATE_DOTS, 8.0 * n * (cf.j + 4));
+    JDispatch<UpdF>::run(cf.j, c, Q, ld, cf, bd, u, w, qj, n, st);
+  }
+  return reduce_partials_n(c, red_blocks(n / 2), cf.j + 2, out, st);
 }
 
 hipError_t scale_invnorm(const Ctx& c, double* y, const double* x, const double* nrm2, long long n, hipStream_t st) {
@@ -465,16 +510,46 @@ hipError_t axpby(const Ctx& c, long long n, double a, const double* x, double b,
   return hipGetLastError();
 }
 
+template <typename TV, int K>
+struct LincombF {
+  static void go(const Ctx& c, long long n, const Coefs& cf, const TV* V, long long ld, double* x, hipStream_t st) {
+    (void)c;
+    long long g = (n + 255) / 256;
+    if (g > 65536) g = 65536;
+    hipLaunchKernelGGL((k_lincomb<TV, K>), dim3((unsigned)g), dim3(256), 0, st, n, cf, V, ld, x);
+  }
+};
+template <typename TV, int K = 1>
+static void lincomb_dispatch(int k, const Ctx& c, long long n, const Coefs& cf, const TV* V, long long ld, double* x,
+                             hipStream_t st) {
+  if (k == K) LincombF<TV, K>::go(c, n, cf, V, ld, x, st);
+  else if constexpr (K < 32) lincomb_dispatch<TV, K + 1>(k, c, n, cf, V, ld, x, st);
+}
+
 hipError_t lincomb(const Ctx& c, long long n, const Coefs& cf, const double* V, long long ld, double* x,
                    hipStream_t st) {
-  ProfScope ps(c.prof, st, KK_LINCOMB, double(n) * (8.0 * cf.n + 16.0));
-  hipLaunchKernelGGL((k_lincomb<double>), dim3(grid_for(n)), dim3(256), 0, st, n, cf, V, ld, x);
+  if (cf.n < 1) return hipSuccess;
+  if (cf.n > 64) return hipErrorInvalidValue;
+  ProfScope ps(c.prof, st, KK_LINCOMB, double(n) * (8.0 * cf.n + 16.0 * ((cf.n + 31) / 32)));
+  for (int i0 = 0; i0 < cf.n; i0 += 32) {  // chunks of at most 32 vectors
+    Coefs part{};
+    part.n = cf.n - i0 < 32 ? cf.n - i0 : 32;
+    for (int i = 0; i < part.n; ++i) part.c[i] = cf.c[i0 + i];
+    lincomb_dispatch<double>(part.n, c, n, part, V + (long long)i0 * ld, ld, x, st);
+  }
   return hipGetLastError();
 }
 hipError_t lincomb(const Ctx& c, long long n, const Coefs& cf, const float* V, long long ld, double* x,
                    hipStream_t st) {
-  ProfScope ps(c.prof, st, KK_LINCOMB, double(n) * (4.0 * cf.n + 16.0));
-  hipLaunchKernelGGL((k_lincomb<float>), dim3(grid_for(n)), dim3(256), 0, st, n, cf, V, ld, x);
+  if (cf.n < 1) return hipSuccess;
+  if (cf.n > 64) return hipErrorInvalidValue;
+  ProfScope ps(c.prof, st, KK_LINCOMB, double(n) * (4.0 * cf.n + 16.0 * ((cf.n + 31) / 32)));
+  for (int i0 = 0; i0 < cf.n; i0 += 32) {  // chunks of at most 32 vectors
+    Coefs part{};
+    part.n = cf.n - i0 < 32 ? cf.n - i0 : 32;
+    for (int i = 0; i < part.n; ++i) part.c[i] = cf.c[i0 + i];
+    lincomb_dispatch<float>(part.n, c, n, part, V + (long long)i0 * ld, ld, x, st);
+  }
   return hipGetLastError();
 }
 

@@ -24,7 +24,7 @@ void set_error(const std::string& msg);
 // Number of blocks used by every streaming reduction (fixed per context so the
 // reduction order, and hence every reduced value, is bitwise reproducible).
 constexpr int kRedBlocks = 1024;
-constexpr int kRedBlocksMax = 16384;  // partial buffer rows (large dot passes)
+constexpr int kRedBlocksMax = 65536;  // partial buffer rows (large dot passes)
 constexpr int kRedThreads = 256;
 constexpr int kMaxDots = 64;
 
