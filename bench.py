@@ -49,6 +49,8 @@ def parse():
     ap.add_argument("--no-fp64", action="store_true", help="skip the plain FP64 comparison run")
     ap.add_argument("--inner-rtol", type=float, default=1e-5)
     ap.add_argument("--op-reps", type=int, default=20)
+    ap.add_argument("--copy-calibration", action="store_true",
+                    help="only run a plain 1 GiB device copy 5 times (counter calibration) and exit")
     ap.add_argument("--orth", default="dcgs2", choices=["dcgs2", "cgs2"],
                     help="Arnoldi orthogonalization: CGS2 with delayed re-orthogonalization, or 3-pass CGS2")
     return ap.parse_args()
@@ -139,6 +141,27 @@ def op_bandwidth(P, ctx, prm, m0_dev, reps):
     return out
 
 
+def measured_traffic(kernel_kind, bytes_per_launch):
+    """HBM bytes per launch of ``kernel_kind`` from the committed hardware-counter
+    summary (profiles/traffic_3d256_midpoint.md), scaled to this run's
+    algorithmic bytes per launch; None when the summary has no entry for the
+    kernel or the kernel source changed since the counters were taken."""
+    import hashlib
+    path = os.path.join(ROOT, "profiles", "traffic_3d256_midpoint.md")
+    if not os.path.exists(path):
+        return None
+    for line in open(path):
+        parts = line.split()
+        if len(parts) == 5 and parts[0] == "bench-traffic:" and parts[1] == kernel_kind:
+            src = os.path.join(ROOT, "paper_2607_15290_amd", "csrc", parts[3])
+            if not os.path.exists(src):
+                return None
+            if hashlib.sha256(open(src, "rb").read()).hexdigest()[:16] != parts[4]:
+                return None
+            return float(parts[2]) * bytes_per_launch
+    return None
+
+
 def cpu_baseline(spec, m0_np, gpu_iters_per_solve):
     """FP64 oracle on the host, bounded sample: one application of the
     preconditioned operator M^{-1} A (one matvec and one FFT-HSS apply, the
@@ -175,6 +198,14 @@ def main():
     import paper_2607_15290_amd as P
 
     assert torch.cuda.is_available(), "bench.py needs a GPU"
+    if args.copy_calibration:
+        a = torch.ones(1 << 27, dtype=torch.float64, device="cuda:0")  # 1 GiB
+        b = torch.empty_like(a)
+        for _ in range(5):
+            b.copy_(a)
+        torch.cuda.synchronize()
+        print(json.dumps({"copy_bytes_read": a.numel() * 8, "copy_bytes_written": b.numel() * 8, "copies": 5}))
+        return
     log("generating workload 4 (3D midpoint)")
     spec = W.make(4, n=args.n)
     n = spec["n"]
@@ -210,10 +241,13 @@ def main():
     dom_name, dom = max(prof.items(), key=lambda kv: kv[1]["total_ms"])
     achieved = dom["bytes"] / (dom["total_ms"] * 1e-3) / 1e9
     avg_us = 1e3 * dom["total_ms"] / dom["launches"]
+    bpl = dom["bytes"] / dom["launches"]
+    traffic = measured_traffic(dom_name, bpl)
     roofline = dict(bound="hbm", achieved=round(achieved, 1), peak=HBM_PEAK_GBS, unit="GB/s",
-                    frac=round(achieved / HBM_PEAK_GBS, 4), traffic=None, kernel=dom_name,
-                    avg_launch_us=round(avg_us, 2), launches=dom["launches"],
-                    bytes_per_launch=dom["bytes"] / dom["launches"])
+                    frac=round(achieved / HBM_PEAK_GBS, 4),
+                    traffic=round(traffic) if traffic is not None else None, traffic_unit="HBM bytes per launch",
+                    kernel=dom_name, avg_launch_us=round(avg_us, 2), launches=dom["launches"],
+                    bytes_per_launch=round(bpl))
     kernels = {k: dict(launches=v["launches"], total_ms=round(v["total_ms"], 3),
                        GBs=round(v["bytes"] / (v["total_ms"] * 1e-3) / 1e9, 1) if v["total_ms"] > 0 else None)
                for k, v in sorted(prof.items(), key=lambda kv: -kv[1]["total_ms"])}

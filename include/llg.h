@@ -83,6 +83,9 @@ typedef struct {
   double rtol;       /* accept when ||b - A x||_2 <= rtol ||b||_2 */
   double inner_rtol; /* relative tolerance of each inner FGMRES cycle (FP32_IR) */
   int prec;          /* llg_precision */
+  int precond;       /* 0 = split FFT-HSS (the method), 1 = symmetric part
+                        (lambda I + calH)^{-1} only, 2 = none: the comparison
+                        preconditioners of Sec. 4.1 (float64 only) */
   int orth;          /* Arnoldi orthogonalization: 0 = CGS2 with the
                         re-orthogonalization delayed by one iteration (two
                         streaming passes, restart <= 31; default), 1 = CGS2 in

@@ -26,7 +26,7 @@ class LLGParams(ctypes.Structure):
 class LLGSolverOpts(ctypes.Structure):
     _fields_ = [("restart", ctypes.c_int), ("maxiter", ctypes.c_int), ("max_outer", ctypes.c_int),
                 ("use_x0", ctypes.c_int), ("rtol", ctypes.c_double), ("inner_rtol", ctypes.c_double),
-                ("prec", ctypes.c_int), ("orth", ctypes.c_int)]
+                ("prec", ctypes.c_int), ("precond", ctypes.c_int), ("orth", ctypes.c_int)]
 
 
 class LLGSolverStats(ctypes.Structure):

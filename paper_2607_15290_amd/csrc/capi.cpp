@@ -70,6 +70,8 @@ llg_status check_opts(const llg_solver_opts* o) {
   if (!is_fin(o->rtol) || o->rtol <= 0 || o->rtol >= 1) return fail(LLG_EARG, "rtol must be in (0, 1)");
   if (o->prec != LLG_FP64 && o->prec != LLG_FP32_IR) return fail(LLG_EARG, "unknown precision");
   if (o->orth != 0 && o->orth != 1) return fail(LLG_EARG, "orth must be 0 (delayed CGS2) or 1 (CGS2)");
+  if (o->precond < 0 || o->precond > 2) return fail(LLG_EARG, "precond must be 0, 1 or 2");
+  if (o->precond != 0 && o->prec != LLG_FP64) return fail(LLG_EARG, "comparison preconditioners run in float64");
   if (o->orth == 0 && o->restart > 31) return fail(LLG_EARG, "delayed CGS2 supports restart <= 31");
   if (o->prec == LLG_FP32_IR) {
     if (o->max_outer < 1) return fail(LLG_EARG, "max_outer must be >= 1");
@@ -601,6 +603,24 @@ llg_status solve(const Ctx& c, const llg_params* p, const double* m, const doubl
   CHK_STATUS(check_m(c, m, st));
   if (o.prec == LLG_FP32_IR) return gmres_ir(c, p, m, b, x, o, w, res, st);
   const ResidOp RA = resid_op(c, EPI_MATVEC, sym_for(c, p->alpha, hcoef(p), false), nodal_for(p), m, st);
+  if (o.precond == 1) {  // symmetric part (lambda I + calH)^{-1}
+    const SymArgs sa = sym_for(c, p->alpha + p->shift, hcoef(p), true);
+    Op M = [&](const double* in, double* out) {
+      return pipe_d(c, PRO_COPY3, EPI_APPLY_SYM, sa, nodal_for(p), in, m, out, st);
+    };
+    Op MA = [&](const double* in, double* out) {
+      return pipe_d(c, PRO_SMINUS, EPI_FUSED_SYM, sa, nodal_for(p), in, m, out, st);
+    };
+    return gmres_left(c, RA, M, MA, b, x, o, w, res, st);
+  }
+  if (o.precond == 2) {  // no preconditioner
+    const long long n4 = 4 * c.ng;
+    Op M = [&](const double* in, double* out) {
+      return hipMemcpyAsync(out, in, sizeof(double) * n4, hipMemcpyDeviceToDevice, st);
+    };
+    Op MA = [&](const double* in, double* out) { return op_matvec(c, p, m, in, out, false, st); };
+    return gmres_left(c, RA, M, MA, b, x, o, w, res, st);
+  }
   Op M = [&](const double* in, double* out) { return op_apply(c, p, m, in, out, false, st); };
   Op MA = [&](const double* in, double* out) { return op_fused(c, p, m, in, out, st); };
   return gmres_left(c, RA, M, MA, b, x, o, w, res, st);

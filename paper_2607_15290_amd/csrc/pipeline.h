@@ -63,6 +63,8 @@ enum EpiMode : int {
   EPI_FUSED = 5,     // out = M2^{-1} (x + (F, (-m.v - lambda r) / lambda))
   EPI_RHS = 6,       // out = (-C_hat F + (1+alpha^2) h, 0)
   EPI_JT = 7,        // out = J^T mu of the midpoint residual (adjoint), F = H mu_v
+  EPI_APPLY_SYM = 8, // out = (F, p_r / lambda): (lambda I + calH)^{-1} p alone
+  EPI_FUSED_SYM = 9, // out = x + (F, (-m.v - lambda r) / lambda): (lambda I + calH)^{-1} A x
 };
 
 // Pointers of one pipeline call.  "in" planes feed the prologue (and are

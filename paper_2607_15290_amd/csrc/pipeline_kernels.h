@@ -179,14 +179,20 @@ __device__ __forceinline__ void epilogue_load(const PipeIO<T, TIn, TOut>& io, co
                                               EpiRaw<T, TIn, TOut, EPI>& r) {
   const long long ng = io.ng;
   if constexpr (EpiRaw<T, TIn, TOut, EPI>::NODAL) {
-    // EPI_APPLY needs only the multiplier plane of p
+    // the apply modes need only the multiplier plane of p
+    constexpr bool ONLY_R = EPI == EPI_APPLY || EPI == EPI_APPLY_SYM;
 #pragma unroll
     for (int f = 0; f < 4; ++f) {
-      if (EPI != EPI_APPLY || f == 3) load2(io.in + f * ng + i, r.v[f][0], r.v[f][1]);
+      if (!ONLY_R || f == 3) load2(io.in + f * ng + i, r.v[f][0], r.v[f][1]);
       else r.v[f][0] = r.v[f][1] = TIn(0);
     }
+    if constexpr (EPI != EPI_APPLY_SYM) {
 #pragma unroll
-    for (int f = 0; f < 3; ++f) load2(io.m + f * ng + i, r.m[f][0], r.m[f][1]);
+      for (int f = 0; f < 3; ++f) load2(io.m + f * ng + i, r.m[f][0], r.m[f][1]);
+    } else {
+#pragma unroll
+      for (int f = 0; f < 3; ++f) r.m[f][0] = r.m[f][1] = T(0);
+    }
     if constexpr (EPI == EPI_JT) {
 #pragma unroll
       for (int f = 0; f < 3; ++f) load2(io.aux_v + f * ng + i, r.av[f][0], r.av[f][1]);
@@ -262,6 +268,17 @@ __device__ __forceinline__ void epilogue_compute(const EpiRaw<T, TIn, TOut, EPI>
       o[1] = F[1] - c.y + hk * rf * v.y - m1.y * rr;
       o[2] = F[2] - c.z + hk * rf * v.z - m1.z * rr;
       o[3] = dot3(mh, v);
+    } else if constexpr (EPI == EPI_APPLY_SYM) {
+      o[0] = F[0];
+      o[1] = F[1];
+      o[2] = F[2];
+      o[3] = rr / lam;
+    } else if constexpr (EPI == EPI_FUSED_SYM) {
+      const T ur = -dot3(m, v) - lam * rr;
+      o[0] = v.x + F[0];
+      o[1] = v.y + F[1];
+      o[2] = v.z + F[2];
+      o[3] = rr + ur / lam;
     } else {  // EPI_FUSED
       const T ur = -dot3(m, v) - lam * rr;
       const V3<T> w{v.x + F[0], v.y + F[1], v.z + F[2]};

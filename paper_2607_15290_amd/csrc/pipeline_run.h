@@ -49,6 +49,7 @@ void launch_xinv(const Ctx& c, const NodalArgs& na, const PipeIO<T, TIn, TOut>& 
     if (EPI == EPI_STORE3) node_b = 3.0 * sizeof(TOut);
     else if (EPI == EPI_RHS) node_b = 4.0 * sizeof(TOut) + (na.hfield ? 24.0 : 0.0);
     else if (EPI == EPI_APPLY) node_b = 1.0 * sizeof(TIn) + 3.0 * sizeof(T) + 4.0 * sizeof(TOut);
+    else if (EPI == EPI_APPLY_SYM) node_b = 1.0 * sizeof(TIn) + 4.0 * sizeof(TOut);
     else if (EPI == EPI_JT) node_b = 4.0 * sizeof(TIn) + 7.0 * sizeof(T) + 4.0 * sizeof(TOut);
     else node_b = 4.0 * sizeof(TIn) + 3.0 * sizeof(T) + 4.0 * sizeof(TOut);
     if (io.rhs) node_b += 4.0 * sizeof(TOut);
@@ -85,6 +86,8 @@ hipError_t run_nh(const Ctx& c, int pro, int epi, const SymArgs& sym, const Noda
     case EPI_FUSED: launch_xinv<T, TIn, TOut, NH, EPI_FUSED>(c, na, io, st); break;
     case EPI_RHS: launch_xinv<T, TIn, TOut, NH, EPI_RHS>(c, na, io, st); break;
     case EPI_JT: launch_xinv<T, TIn, TOut, NH, EPI_JT>(c, na, io, st); break;
+    case EPI_APPLY_SYM: launch_xinv<T, TIn, TOut, NH, EPI_APPLY_SYM>(c, na, io, st); break;
+    case EPI_FUSED_SYM: launch_xinv<T, TIn, TOut, NH, EPI_FUSED_SYM>(c, na, io, st); break;
     default: return hipErrorInvalidValue;
   }
   return hipGetLastError();

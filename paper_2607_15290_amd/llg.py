@@ -57,11 +57,13 @@ class Params:
 
 
 ORTH = {"dcgs2": 0, "cgs2": 1, 0: 0, 1: 1}
+PRECOND = {"fft_hss": 0, "symmetric": 1, "none": 2, 0: 0, 1: 1, 2: 2}
 
 
-def _opts(restart, maxiter, rtol, prec, inner_rtol, max_outer, use_x0, orth="dcgs2"):
+def _opts(restart, maxiter, rtol, prec, inner_rtol, max_outer, use_x0, orth="dcgs2", precond="fft_hss"):
     o = L.LLGSolverOpts()
     o.orth = ORTH[orth]
+    o.precond = PRECOND[precond]
     o.restart, o.maxiter, o.max_outer, o.use_x0 = int(restart), int(maxiter), int(max_outer), int(use_x0)
     o.rtol, o.inner_rtol = float(rtol), float(inner_rtol)
     o.prec = _PREC[prec]
@@ -164,12 +166,12 @@ def fft_hss_apply_f32(ctx, params, m, p, z=None, transpose=False):
 
 
 def gmres_solve(ctx, params, m, b, x=None, use_x0=False, restart=30, rtol=1e-10, maxiter=3000, prec="fp64",
-                inner_rtol=1e-5, max_outer=20, check=True, orth="dcgs2"):
+                inner_rtol=1e-5, max_outer=20, check=True, orth="dcgs2", precond="fft_hss"):
     """Solve A(m) x = b; returns (x, stats).  See gmres_solve in include/llg.h."""
     if x is None:
         x = ctx.new(4)
         use_x0 = False
-    o = _opts(restart, maxiter, rtol, prec, inner_rtol, max_outer, use_x0, orth)
+    o = _opts(restart, maxiter, rtol, prec, inner_rtol, max_outer, use_x0, orth, precond)
     st = L.LLGSolverStats()
     work = ctx.workspace(restart, prec)
     pr = params.c_struct()
