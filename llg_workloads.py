@@ -176,3 +176,15 @@ def make(wid, n=None, seed=None):
     spec.update(n=n, nx=n, ny=n, nz=nz, h=1.0 / n, dt=dt, m0=m0, h_field=h_field,
                 seed_used=used, theta=1.0 if spec["scheme"] == "euler" else 0.5)
     return spec
+
+
+def gaussian_rhs(n, seed, dim=2):
+    """Random-right-hand-side study input: a Gaussian velocity right-hand side
+    (numpy.random.default_rng(seed).standard_normal over the 3 planes, SoA),
+    scaled to unit 2-norm, with a zero multiplier plane.  Shape (4, [nz,] ny, nx)
+    with nz = 1 in 2D."""
+    shape = _shape(n, dim)
+    f = np.random.default_rng(seed).standard_normal((3,) + shape)
+    b = np.zeros((4,) + shape)
+    b[:3] = f / np.linalg.norm(f)
+    return b

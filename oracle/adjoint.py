@@ -3,18 +3,22 @@
 Write u = (v, r) and m_half = m^n + (k/2) v.  The converged step solves the
 residual of eq. "C-N" (Sec. 3.3) with the lower-order field h:
 
-    R_v = alpha v + m_half x v + C_hat (-Delta_N) m_half + m_half r - (1+alpha^2) h
+    R_v = alpha v + m_half x v + C_hat (-Delta_N) m_half + m_half r
+          - (1+alpha^2) (L_low m_half + h)
     R_r = -m_half . v
 
-and sets m^{n+1} = m^n + k v.  Differentiating (m_half x v = m^n x v):
+(L_low: the linear, symmetric part of the lower-order field, oracle.fields)
+and sets m^{n+1} = m^n + k v.  Differentiating (m_half x v = m^n x v), with
+K_low = (k/2)(1 + alpha^2) L_low:
 
-    J = dR/du = [[alpha I + [m^n]_x + (k/2) C_hat (-Delta_N) + (k/2) r I, m_half],
-                 [-(m_half + (k/2) v)^T,                                   0     ]].
+    J = dR/du = [[alpha I + [m^n]_x + (k/2) C_hat (-Delta_N) + (k/2) r I - K_low, m_half],
+                 [-(m_half + (k/2) v)^T,                                           0     ]].
 
 For a loss L(m^{n+1}) with gbar = dL/dm^{n+1}, let mu = J^{-T} (k gbar, 0).  Then
 dL/dh = (1 + alpha^2) mu_v and
 
-    dL/dm^n = gbar - [v x mu_v + C_hat (-Delta_N) mu_v + r mu_v - v mu_r].
+    dL/dm^n = gbar - [v x mu_v + C_hat (-Delta_N) mu_v + r mu_v - v mu_r
+                      - (1 + alpha^2) L_low mu_v].
 
 The transposed solve is preconditioned with the transposed split FFT-HSS
 operator built on m_half.
@@ -25,7 +29,7 @@ from dataclasses import replace
 import numpy as np
 
 from . import dense as dense_mod
-from . import fourier, nodal, operators
+from . import fields, fourier, nodal, operators
 from .gmres import gmres
 
 
@@ -37,7 +41,8 @@ def jacobian_transpose_apply(g, prm, m_n, v, r, mu):
     mv, mr = mu[:3], mu[3]
     out = np.empty_like(mu)
     out[:3] = (fourier.h_apply(g, mv, prm.alpha, 0.5 * k * prm.c_hat)
-               - nodal.cross(m_n, mv) + 0.5 * k * r * mv - m_next * mr)
+               - nodal.cross(m_n, mv) + 0.5 * k * r * mv - m_next * mr
+               - 0.5 * k * (1.0 + prm.alpha ** 2) * fields.low_linear(g, prm, mv))
     out[3] = nodal.dot(m_half, mv)
     return out
 
@@ -49,7 +54,8 @@ def jacobian_apply(g, prm, m_n, v, r, du):
     dv, dr = du[:3], du[3]
     out = np.empty_like(du)
     out[:3] = (fourier.h_apply(g, dv, prm.alpha, 0.5 * k * prm.c_hat)
-               + nodal.cross(m_n, dv) + 0.5 * k * r * dv + m_half * dr)
+               + nodal.cross(m_n, dv) + 0.5 * k * r * dv + m_half * dr
+               - 0.5 * k * (1.0 + prm.alpha ** 2) * fields.low_linear(g, prm, dv))
     out[3] = -nodal.dot(m_half + 0.5 * k * v, dv)
     return out
 
@@ -75,5 +81,5 @@ def step_adjoint(g, prm, m_n, v, r, gbar, rtol=1e-12, restart=30, dense=False):
     hbar_field = (1.0 + prm.alpha ** 2) * muv
     hbar_uniform = hbar_field.reshape(3, -1).sum(axis=1)
     gbar_n = gbar - (nodal.cross(v, muv) + prm.c_hat * fourier.neg_laplacian(g, muv)
-                     + r * muv - v * mur)
+                     + r * muv - v * mur - (1.0 + prm.alpha ** 2) * fields.low_linear(g, prm, muv))
     return gbar_n, hbar_field, hbar_uniform, mu, info

@@ -35,6 +35,44 @@ def neg_laplacian_matrix(g):
     return D.real
 
 
+def low_linear_matrix(g, prm):
+    """Dense L_low (3 N_g x 3 N_g, component-major): demag * D_dem + 2 K e e^T,
+    with D_dem = -F^{-1} diag(xi~_c xi~_d / |xi|^2) F (zero at xi = 0), xi~ the
+    derivative wave vector whose Nyquist entries are zero."""
+    n = g.ng
+    F = grid_dft(g)
+
+    def axis(nn, length, nyq_zero):
+        k = wavenumbers(nn).astype(np.float64)
+        if nyq_zero and nn % 2 == 0:
+            k[nn // 2] = 0.0
+        return 2 * np.pi * k / length if nn > 1 else np.zeros(1)
+
+    def grid3(nyq_zero):
+        kz = axis(g.nz, g.lengths[0], nyq_zero)
+        ky = axis(g.ny, g.lengths[1], nyq_zero)
+        kx = axis(g.nx, g.lengths[2], nyq_zero)
+        shp = (len(kz), len(ky), len(kx))
+        return [np.broadcast_to(kx[None, None, :], shp).ravel(),
+                np.broadcast_to(ky[None, :, None], shp).ravel(),
+                np.broadcast_to(kz[:, None, None], shp).ravel()]
+
+    xi = grid3(False)
+    xt = grid3(True)
+    s = xi[0] ** 2 + xi[1] ** 2 + xi[2] ** 2
+    inv = np.where(s > 0, 1.0 / np.where(s > 0, s, 1.0), 0.0)
+    e = np.asarray(prm.aniso_axis, dtype=np.float64)
+    L = np.zeros((3 * n, 3 * n))
+    for c in range(3):
+        for d in range(3):
+            blk = 2.0 * prm.aniso_k * e[c] * e[d] * np.eye(n)
+            if prm.demag != 0.0:
+                sym = xt[c] * xt[d] * inv
+                blk = blk - prm.demag * ((np.conj(F).T @ (sym[:, None] * F)) / n).real
+            L[c * n:(c + 1) * n, d * n:(d + 1) * n] = blk
+    return L
+
+
 def block_indices(g):
     n = g.ng
     return [np.arange(c * n, (c + 1) * n) for c in range(4)]
@@ -92,6 +130,7 @@ def midpoint_jacobian(g, prm, m_n, v, r):
     Hb = prm.alpha * np.eye(n) + 0.5 * k * prm.c_hat * D
     for c in range(3):
         J[c * n:(c + 1) * n, c * n:(c + 1) * n] = Hb + 0.5 * k * np.diag(rr)
+    J[:3 * n, :3 * n] -= 0.5 * k * (1.0 + prm.alpha ** 2) * low_linear_matrix(g, prm)
     for i in range(n):
         L = nodal.lambda_matrix(mn[:, i])
         rows = np.arange(3) * n + i

@@ -27,7 +27,10 @@ class Params:
     alpha: damping; cexc: normalized exchange coefficient (1 in the paper's
     runs); dt: time step k; theta: 1 (Euler) or 1/2 (midpoint); shift: the HSS
     shift lambda; h_uniform: uniform applied field; h_field: optional spatial
-    applied field of shape (3, nz, ny, nx).
+    applied field of shape (3, nz, ny, nx); demag: coefficient of the
+    periodic demagnetizing field (0 off, 1 for the normalized field of the
+    magnetostatic problem); aniso_k, aniso_axis: uniaxial anisotropy
+    coefficient K and easy axis e (field 2 K e (e.m)).
     """
     alpha: float = 0.2
     cexc: float = 1.0
@@ -36,6 +39,9 @@ class Params:
     shift: float = 0.5
     h_uniform: tuple = (0.0, 0.0, 0.0)
     h_field: np.ndarray = field(default=None, repr=False)
+    demag: float = 0.0
+    aniso_k: float = 0.0
+    aniso_axis: tuple = (0.0, 0.0, 1.0)
 
     @property
     def c_hat(self):

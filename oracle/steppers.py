@@ -7,31 +7,35 @@
 * Projection-free midpoint scheme (Sec. 3.3, eqs. "C-N" and "hatm"): Picard
   iteration on the frozen midpoint m_hat^p = m^n + (k/2) v^{p-1} (p = 0 uses
   the previous step's velocity, zero on the first step), each iterate one
-  saddle solve with theta = 1/2 and the same right-hand side; after
-  convergence m^{n+1} = m^n + k v.
-* Discrete energy g_N(m) = (u, v)_N-weighted sum of cexc/2 m.(-Delta_N m) -
-  m.h_ext, the quadratic-affine energy of exchange + Zeeman, and the
-  dissipation identity with its inexact-solve correction (Proposition
-  "Nodal constraint and discrete energy law", Remark "Effect of an inexact
-  midpoint solve").
+  saddle solve with theta = 1/2 on the frozen midpoint; after convergence
+  m^{n+1} = m^n + k v.
+* Discrete energy g_N(m) = (u, v)_N-weighted sum of cexc/2 m.(-Delta_N m)
+  plus the lower-order densities (demagnetizing, anisotropy, Zeeman; see
+  oracle.fields), a quadratic-affine energy, and the dissipation identity
+  with its inexact-solve correction (Proposition "Nodal constraint and
+  discrete energy law", Remark "Effect of an inexact midpoint solve").
 
-The applied field enters only as h_low = h_ext (uniform plus optional spatial
-part), or as an explicit forcing F = (1 + alpha^2) h_low(t) supplied by the
-caller (manufactured solutions).
+The lower-order field h_low(m) = L_low m + h_ext (oracle.fields) is explicit
+in the Euler step (evaluated at m^n) and frozen at the Picard midpoint m_hat^p
+in the midpoint step, so the right-hand side is rebuilt at every Picard
+iteration.  A caller may add an explicit forcing F = (1 + alpha^2) h(t)
+(manufactured solutions).
 """
 
 from dataclasses import replace
 
 import numpy as np
 
-from . import fourier, nodal, operators
+from . import fields, fourier, nodal, operators
 from .gmres import gmres
 
 
-def rhs(g, prm, m, forcing=None):
-    """b = (f, 0) with f = C_hat Delta_N m + (1 + alpha^2) h_ext (+ forcing)."""
+def rhs(g, prm, m, forcing=None, m_low=None):
+    """b = (f, 0) with f = C_hat Delta_N m + (1 + alpha^2) h_low(m_low)
+    (+ forcing); m_low defaults to m."""
     b = np.zeros((4,) + g.shape)
-    b[:3] = -prm.c_hat * fourier.neg_laplacian(g, m) + (1.0 + prm.alpha ** 2) * prm.h_ext(g.shape)
+    b[:3] = (-prm.c_hat * fourier.neg_laplacian(g, m)
+             + (1.0 + prm.alpha ** 2) * fields.h_low(g, prm, m if m_low is None else m_low))
     if forcing is not None:
         b[:3] += forcing
     return b
@@ -58,13 +62,18 @@ def euler_step(g, prm, m, forcing=None, restart=30, rtol=1e-10):
 
 
 def midpoint_step(g, prm, m, v_prev=None, lam_prev=None, forcing=None, restart=30,
-                  rtol=1e-10, picard_tol=1e-10, picard_max=50):
+                  rtol=1e-10, picard_tol=1e-10, picard_max=50, picard_norm="midpoint"):
     """One projection-free midpoint step (theta = 1/2) with Picard iteration.
 
     v_prev / lam_prev: velocity and multiplier of the previous step (the p = 0
     frozen midpoint and the GMRES initial guess); None on the first step.
-    Convergence: ||v^p - v^{p-1}||_2 <= picard_tol ||v^p||_2 with v^{-1} =
-    v_prev.  Returns (m_new, v, r, info)."""
+    Convergence (v^{-1} = v_prev):
+      picard_norm "midpoint": ||m_hat^{p+1} - m_hat^p||_2 <= picard_tol ||m_hat^{p+1}||_2,
+          i.e. (k/2) ||v^p - v^{p-1}|| <= picard_tol ||m^n + (k/2) v^p||, the
+          change of the fixed-point iterate of Proposition "Local convergence
+          of the midpoint Picard iteration";
+      picard_norm "velocity": ||v^p - v^{p-1}||_2 <= picard_tol ||v^p||_2.
+    Returns (m_new, v, r, info)."""
     prm2 = replace(prm, theta=0.5)
     k = prm.dt
     b = rhs(g, prm2, m, forcing)
@@ -79,16 +88,22 @@ def midpoint_step(g, prm, m, v_prev=None, lam_prev=None, forcing=None, restart=3
     x = None
     for _ in range(picard_max):
         m_hat = m + 0.5 * k * v_old
+        if fields.has_low(prm):
+            b = rhs(g, prm2, m, forcing, m_low=m_hat)
         x, linfo = solve_saddle(g, prm2, m_hat, b, x0=x0, restart=restart, rtol=rtol)
         info["picard_iters"] += 1
         info["lin_iters"].append(linfo["iters"])
         v = x[:3]
-        vn = np.linalg.norm(v)
-        change = np.linalg.norm(v - v_old)
-        info["picard_rel_change"] = change / vn if vn > 0 else change
+        if picard_norm == "midpoint":
+            change = 0.5 * k * np.linalg.norm(v - v_old)
+            ref = np.linalg.norm(m + 0.5 * k * v)
+        else:
+            change = np.linalg.norm(v - v_old)
+            ref = np.linalg.norm(v)
+        info["picard_rel_change"] = change / ref if ref > 0 else change
         v_old = v
         x0 = x
-        if change <= picard_tol * vn:
+        if change <= picard_tol * ref:
             info["converged"] = True
             break
     v = x[:3]
@@ -97,9 +112,11 @@ def midpoint_step(g, prm, m, v_prev=None, lam_prev=None, forcing=None, restart=3
 
 
 def energy(g, prm, m):
-    """g_N(m) = sum_i w [cexc/2 m_i.(-Delta_N m)_i - m_i.h_ext,i], w = |Omega|/N_g."""
+    """g_N(m) = sum_i w [cexc/2 m_i.(-Delta_N m)_i + lower-order densities],
+    w = |Omega|/N_g; the lower-order densities are -1/2 demag m.h_dem[m] +
+    K (1 - (e.m)^2) - m.h_ext (oracle.fields)."""
     lap = fourier.neg_laplacian(g, m)
-    dens = 0.5 * prm.cexc * nodal.dot(m, lap) - nodal.dot(m, prm.h_ext(g.shape))
+    dens = 0.5 * prm.cexc * nodal.dot(m, lap) + fields.low_energy_density(g, prm, m)
     return g.weight * float(dens.sum())
 
 
@@ -116,7 +133,7 @@ def midpoint_diagnostics(g, prm, m_old, m_new, v, r):
     w = g.weight
     mh = 0.5 * (m_old + m_new)
     res_v = (a * v + nodal.cross(mh, v) + prm.c_hat * fourier.neg_laplacian(g, mh)
-             + mh * r - (1.0 + a * a) * prm.h_ext(g.shape))
+             + mh * r - (1.0 + a * a) * fields.h_low(g, prm, mh))
     res_c = nodal.dot(v, mh)
     rho_v = w * float(nodal.dot(res_v, v).sum())
     chi_r = w * float((res_c * r).sum())

@@ -1,13 +1,17 @@
 """Pins of the oracle GMRES: the dense direct solve (Proposition 1 makes the
 solution unique), the uniform-state closed form derived from the tangent
 equation, the even-step residual bound of the Theorem "Full saddle two-step
-contraction", and the paper's iteration count for the smooth one-step system
-(Sec. 4.3, a soft pin)."""
+contraction", and the paper's printed iteration counts: the preconditioner
+comparison on the smooth one-step system (Sec. 4.3, exact), the shift sweep
+(Sec. 4.4, exact minimum and band) and the random right-hand-side mesh study
+(Sec. 4.5, soft)."""
 
 import json
 import os
 
 import numpy as np
+
+import llg_workloads
 import pytest
 
 from oracle import dense, gmres, manufactured, nodal, operators, steppers, theory
@@ -110,6 +114,63 @@ def test_smooth_rhs_iteration_counts_match_paper(n):
     assert counts["split"] == gold["split_2d"]
     assert counts["symmetric"] == gold["symmetric_2d"]
     assert counts["none"] == gold["unpreconditioned_2d"][str(n)]
+
+
+def _split_count(g, prm, m, b):
+    x, info = gmres.gmres(lambda x: operators.matvec(g, prm, m, x),
+                          lambda x: operators.hss_apply(g, prm, m, x), b, restart=50, rtol=1e-8, maxiter=5000)
+    assert info["converged"]
+    return info["iters"]
+
+
+def test_lambda_sweep_matches_paper():
+    """Sec. 4.4: the shift sweep 2^-3..2^4 on the smooth system.  The minimum
+    (10 iterations at lambda = 0.25), the 10..12 band on [0.25, 1] and the
+    N = 256 count at lambda = 16 (42) are reproduced exactly; the N = 64 count
+    at lambda = 16 is a soft pin (27 here, 32 printed)."""
+    gold = GOLD["lambda_sweep"]
+    counts = {}
+    for n, lams in [(64, [2.0 ** e for e in range(-3, 5)]), (256, [0.25, 16.0])]:
+        g = Grid(n, n, 1, lengths=(1.0, 2 * np.pi, 2 * np.pi))
+        for lam in lams:
+            prm = Params(alpha=0.2, dt=1e-2, theta=1.0, shift=lam)
+            m, _ = manufactured.grid_fields(g, 0.0, prm.alpha)
+            _, F = manufactured.grid_fields(g, prm.dt, prm.alpha)
+            counts[(n, lam)] = _split_count(g, prm, m, steppers.rhs(g, prm, m, forcing=F))
+    sweep64 = {lam: c for (n, lam), c in counts.items() if n == 64}
+    assert min(sweep64.values()) == gold["min_iters"]
+    assert min(sweep64, key=sweep64.get) == gold["argmin"]
+    for lam in gold["band_lambdas"]:
+        assert gold["band"][0] <= sweep64[lam] <= gold["band"][1]
+    # counts grow once lambda leaves the band
+    tail = [sweep64[2.0 ** e] for e in range(0, 5)]
+    assert tail == sorted(tail)
+    assert counts[(256, 0.25)] == gold["min_iters"]
+    assert counts[(256, 16.0)] == gold["lambda16"]["256"]
+    assert abs(sweep64[16.0] - gold["lambda16"]["64"]) <= 6
+
+
+def test_random_rhs_mesh_dependence():
+    """Sec. 4.5: Gaussian velocity right-hand sides.  The seeds are the
+    paper's but its generator is unstated, so the counts are soft pins
+    (within 6 %): bounded stiffness k N^2 = 10.24 keeps the count flat near
+    55, fixed k = 1e-2 makes it grow with N (checked up to N = 64 here; the
+    N = 256 value 608 is checked on the GPU)."""
+    gold = GOLD["random_rhs"]
+    tol = gold["soft_rel"]
+    med = {}
+    for regime, n in [("fixed", 32), ("fixed", 64), ("bounded", 64), ("bounded", 128)]:
+        g = Grid(n, n, 1, lengths=(1.0, 2 * np.pi, 2 * np.pi))
+        k = 1e-2 if regime == "fixed" else 10.24 / n ** 2
+        prm = Params(alpha=0.2, dt=k, theta=1.0, shift=0.5)
+        m, _ = manufactured.grid_fields(g, 0.0, prm.alpha)
+        c = sorted(_split_count(g, prm, m, llg_workloads.gaussian_rhs(n, s)) for s in gold["seeds"])
+        med[(regime, n)] = c[1]
+    lo, hi = gold["bounded_range"]
+    for n in (64, 128):
+        assert lo * (1 - tol) <= med[("bounded", n)] <= hi * (1 + tol)
+    assert abs(med[("fixed", 32)] - gold["fixed_k"]["32"]) <= tol * gold["fixed_k"]["32"]
+    assert med[("fixed", 64)] >= 1.8 * med[("fixed", 32)]
 
 
 def test_fgmres_ir_matches_gmres():
