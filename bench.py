@@ -230,7 +230,8 @@ def main():
                                     False, args.orth)
         solves64 = sum(s["picard_iters"] for s in st64)
         lin64 = sum(s["lin_iters_total"] for s in st64)
-        res["fp64"] = dict(solves_per_s=solves64 / t64, ms_per_step=1e3 * t64 / args.steps, solves=solves64,
+        res["fp64"] = dict(solves_per_s=solves64 / t64, steps_per_s=args.steps / t64, ms_per_step=1e3 * t64 / args.steps,
+                           solves=solves64,
                            gmres_iters=lin64, iters_per_solve=lin64 / solves64)
     log("paper protocol (median of 3 after 1 warm-up)")
     pp32 = paper_protocol(P, ctx, prm, m0_dev, spec, "fp32_ir", args.inner_rtol, args.orth)
@@ -273,7 +274,8 @@ def main():
                    "orthogonalization": "CGS2, re-orthogonalization delayed one iteration" if args.orth == "dcgs2"
                    else "CGS2, three passes",
                    "parallelism": "1 GPU"},
-        "fp32_ir": dict(solves_per_s=value, solves=solves32, gmres_iters=lin32, iters_per_solve=lin32 / solves32,
+        "fp32_ir": dict(solves_per_s=value, steps_per_s=args.steps / t32, picard_per_step=solves32 / args.steps,
+                        solves=solves32, gmres_iters=lin32, iters_per_solve=lin32 / solves32,
                         max_len_err=max(s["max_len_err"] for s in st32)),
         "fp64": res.get("fp64"),
         "fp32_ir_over_fp64": (value / res["fp64"]["solves_per_s"]) if "fp64" in res else None,

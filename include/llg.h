@@ -64,7 +64,13 @@ typedef enum {
 
 typedef struct llg_ctx llg_ctx;
 
-/* Physical parameters of one saddle system (Sec. 2.4 and Sec. 4.1). */
+/* Physical parameters of one saddle system (Sec. 2.4 and Sec. 4.1).
+ * The lower-order field (Sec. 2.1, eq. "heff"; Sec. 2.2) is
+ *   h_low(m) = demag h_dem[m] + 2 aniso_k e (e.m) + h_uniform + h_field,
+ * h_dem the periodic demagnetizing field with zero-mean potential:
+ * h_dem^ = -xi~ (xi~ . m^) / |xi|^2, xi~ the wave vector with the Nyquist
+ * entry of each axis set to zero.  Set demag = aniso_k = 0 for an applied
+ * field alone (the fast path: no extra pipeline anywhere). */
 typedef struct {
   double alpha;         /* damping, > 0 */
   double cexc;          /* normalized exchange coefficient (1 in the paper) */
@@ -73,6 +79,9 @@ typedef struct {
   double shift;         /* HSS shift lambda > 0 (0.5 in the paper) */
   double h_uniform[3];  /* uniform applied field */
   const double* h_field;/* optional spatial applied field, 3 planes, or NULL */
+  double demag;         /* coefficient of the demagnetizing field: 0 off, 1 on */
+  double aniso_k;       /* uniaxial anisotropy coefficient K (energy K (1 - (e.m)^2)) */
+  double aniso_axis[3]; /* easy axis e; must be a unit vector when aniso_k != 0 */
 } llg_params;
 
 typedef struct {
@@ -90,6 +99,10 @@ typedef struct {
                         re-orthogonalization delayed by one iteration (two
                         streaming passes, restart <= 31; default), 1 = CGS2 in
                         three passes */
+  int picard_norm;   /* midpoint Picard stopping test: 0 = change of the frozen
+                        midpoint, ||m_hat^{p+1} - m_hat^p|| <= tol ||m_hat^{p+1}||
+                        (default), 1 = change of the velocity,
+                        ||v^p - v^{p-1}|| <= tol ||v^p|| */
 } llg_solver_opts;
 
 typedef struct {
@@ -105,9 +118,9 @@ typedef struct {
   int picard_iters;         /* Picard iterations of the midpoint step (1 for Euler) */
   int lin_iters_total;      /* Krylov iterations over all solves of the step */
   int converged;            /* Picard (and every linear solve) converged */
-  double picard_rel_change; /* last ||v^p - v^{p-1}|| / ||v^p|| */
+  double picard_rel_change; /* last relative Picard change (the quantity picard_norm selects) */
   double max_len_err;       /* max_i | |m_i^{n+1}| - 1 | */
-  double energy_before;     /* g_N(m^n) (exchange + Zeeman) */
+  double energy_before;     /* g_N(m^n) (exchange + lower-order energies) */
   double energy_after;      /* g_N(m^{n+1}) */
   double dissipation_defect;/* g_N(m^{n+1}) - g_N(m^n) + alpha k/(1+alpha^2) ||v||_N^2 */
   double inexact_correction;/* k/(1+alpha^2) [rho(v) - chi(lam)] (midpoint) */
@@ -160,8 +173,9 @@ llg_status gmres_solve(llg_ctx* ctx, const llg_params* prm, const double* m, con
                        void* stream);
 
 /* One projected implicit Euler step (Sec. 2.4; Sec. 3.2 last paragraph):
- * solve A(m^n) (v, lam) = (C_hat Delta_N m^n + (1+alpha^2) h, 0) with
- * theta = 1, then m^{n+1} = (m^n + k v) / |m^n + k v|.
+ * solve A(m^n) (v, lam) = (C_hat Delta_N m^n + (1+alpha^2) h_low(m^n), 0)
+ * with theta = 1 (lower-order field explicit), then
+ * m^{n+1} = (m^n + k v) / |m^n + k v|.
  * m: in m^n, out m^{n+1} (3 planes); v_out (3 planes) and lam_out (1 plane)
  * may be NULL.  prm->theta is ignored.  Synchronizes the stream. */
 llg_status llg_step_euler(llg_ctx* ctx, const llg_params* prm, double* m, double* v_out, double* lam_out,
@@ -169,10 +183,11 @@ llg_status llg_step_euler(llg_ctx* ctx, const llg_params* prm, double* m, double
                           void* stream);
 
 /* One projection-free midpoint step (Sec. 3.3, eqs. "C-N" and "hatm"):
- * Picard iteration on the frozen midpoint m^n + (k/2) v^{p-1}, each iterate
- * a GMRES solve with theta = 1/2 warm-started from the previous iterate;
- * stops when ||v^p - v^{p-1}||_2 <= picard_tol ||v^p||_2; then
- * m^{n+1} = m^n + k v.
+ * Picard iteration on the frozen midpoint m_hat^p = m^n + (k/2) v^{p-1}, each
+ * iterate a GMRES solve with theta = 1/2 warm-started from the previous
+ * iterate, right-hand side (C_hat Delta_N m^n + (1+alpha^2) h_low(m_hat^p), 0);
+ * stops when the change selected by opts->picard_norm is at most picard_tol
+ * (relative); then m^{n+1} = m^n + k v.
  * m: in m^n, out m^{n+1}.  v_half: in v^{n-1/2} (the p = 0 midpoint; zeros on
  * the first step), out v^{n+1/2}.  lam: in the previous multiplier (initial
  * guess), out the new one; either may be NULL (zeros used, no output).
@@ -185,8 +200,10 @@ llg_status llg_step_midpoint(llg_ctx* ctx, const llg_params* prm, double* m, dou
 /* Adjoint of one converged midpoint step m^{n+1} = m^n + k v(m^n, h).
  * With J the Jacobian of the residual of eq. "C-N" with respect to (v, lam),
  * solves J^T mu = (k gbar, 0) by GMRES preconditioned with the transposed
- * split FFT-HSS operator built on the midpoint, then
- *   gbar  <- gbar - [v x mu_v + C_hat (-Delta_N) mu_v + lam mu_v - v mu_lam]
+ * split FFT-HSS operator built on the midpoint, then, with L_low the linear
+ * part of the lower-order field (demagnetization and anisotropy),
+ *   gbar  <- gbar - [v x mu_v + C_hat (-Delta_N) mu_v + lam mu_v - v mu_lam
+ *                    - (1 + alpha^2) L_low mu_v]
  *   hbar_field   += (1 + alpha^2) mu_v            (3 planes, may be NULL)
  *   hbar_uniform += (1 + alpha^2) sum_i mu_v,i    (3 host doubles, may be NULL)
  * m_n, v, lam: the forward step's input magnetization, velocity and
@@ -196,15 +213,18 @@ llg_status llg_step_midpoint_adjoint(llg_ctx* ctx, const llg_params* prm, const 
                                      const llg_solver_opts* opts, llg_solver_stats* stats, void* work,
                                      size_t work_bytes, void* stream);
 
-/* Right-hand side of one time step (Sec. 2.4, eq. "total system"; Sec. 3.3,
- * eq. "C-N"): b = (C_hat Delta_N m + (1 + alpha^2) h, 0) with h the uniform
- * plus spatial applied field.  m: 3 planes; b: 4 planes (last plane zeroed).
+/* Right-hand side of one time step (Sec. 2.4, eq. "total system"):
+ * b = (C_hat Delta_N m + (1 + alpha^2) h_low(m), 0), the Euler form with the
+ * lower-order field evaluated at m (the applied field alone when demag =
+ * aniso_k = 0).  m: 3 planes; b: 4 planes (last plane zeroed).
  * Asynchronous. */
 llg_status llg_rhs(llg_ctx* ctx, const llg_params* prm, const double* m, double* b, void* stream);
 
-/* Discrete energy g_N(m) = |Omega|/N_g sum_i [cexc/2 m_i.(-Delta_N m)_i - m_i.h_i]
- * (exchange + Zeeman; Sec. 3.3, Proposition on the energy law).  Result to
- * the host double *energy.  Synchronizes. */
+/* Discrete energy g_N(m) = |Omega|/N_g sum_i [cexc/2 m_i.(-Delta_N m)_i
+ *   - demag/2 m_i.h_dem[m]_i + aniso_k (1 - (e.m_i)^2) - m_i.h_i]
+ * (exchange, demagnetization, anisotropy, Zeeman; Sec. 2.1 and Sec. 3.3,
+ * Proposition on the energy law; divide by |Omega| for the normalized energy
+ * of Sec. 4.6).  Result to the host double *energy.  Synchronizes. */
 llg_status llg_energy(llg_ctx* ctx, const llg_params* prm, const double* m, double* energy, void* stream);
 
 /* Instrumentation: per-kernel timing with HIP events.

@@ -20,13 +20,15 @@ c_double_p = ctypes.POINTER(ctypes.c_double)
 class LLGParams(ctypes.Structure):
     _fields_ = [("alpha", ctypes.c_double), ("cexc", ctypes.c_double), ("dt", ctypes.c_double),
                 ("theta", ctypes.c_double), ("shift", ctypes.c_double), ("h_uniform", ctypes.c_double * 3),
-                ("h_field", ctypes.c_void_p)]
+                ("h_field", ctypes.c_void_p), ("demag", ctypes.c_double), ("aniso_k", ctypes.c_double),
+                ("aniso_axis", ctypes.c_double * 3)]
 
 
 class LLGSolverOpts(ctypes.Structure):
     _fields_ = [("restart", ctypes.c_int), ("maxiter", ctypes.c_int), ("max_outer", ctypes.c_int),
                 ("use_x0", ctypes.c_int), ("rtol", ctypes.c_double), ("inner_rtol", ctypes.c_double),
-                ("prec", ctypes.c_int), ("precond", ctypes.c_int), ("orth", ctypes.c_int)]
+                ("prec", ctypes.c_int), ("precond", ctypes.c_int), ("orth", ctypes.c_int),
+                ("picard_norm", ctypes.c_int)]
 
 
 class LLGSolverStats(ctypes.Structure):

@@ -23,7 +23,8 @@ class LLGMidpoint(torch.autograd.Function):
     def forward(fctx, m0, h_uniform, h_field, ctx, params, nsteps, ckpt_every, solver):
         hu = tuple(float(v) for v in h_uniform.detach().cpu().tolist())
         prm = L.Params(alpha=params.alpha, cexc=params.cexc, dt=params.dt, theta=0.5, shift=params.shift,
-                       h_uniform=hu, h_field=h_field.detach().contiguous() if h_field is not None else None)
+                       h_uniform=hu, h_field=h_field.detach().contiguous() if h_field is not None else None,
+                       demag=params.demag, aniso_k=params.aniso_k, aniso_axis=params.aniso_axis)
         m = m0.detach().clone().contiguous()
         vh = torch.zeros_like(m)
         lam = torch.zeros((1,) + tuple(m.shape[1:]), dtype=m.dtype, device=m.device)

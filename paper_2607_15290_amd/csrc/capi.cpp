@@ -60,6 +60,13 @@ llg_status check_params(const llg_params* p) {
   if (!is_fin(p->cexc) || p->cexc < 0) return fail(LLG_EARG, "cexc must be finite and >= 0");
   for (int i = 0; i < 3; ++i)
     if (!is_fin(p->h_uniform[i])) return fail(LLG_EARG, "h_uniform must be finite");
+  if (!is_fin(p->demag) || !is_fin(p->aniso_k)) return fail(LLG_EARG, "demag and aniso_k must be finite");
+  if (p->aniso_k != 0.0) {
+    const double* e = p->aniso_axis;
+    if (!is_fin(e[0]) || !is_fin(e[1]) || !is_fin(e[2]) ||
+        std::fabs(e[0] * e[0] + e[1] * e[1] + e[2] * e[2] - 1.0) > 1e-12)
+      return fail(LLG_EARG, "aniso_axis must be a unit vector");
+  }
   return LLG_OK;
 }
 
@@ -73,6 +80,7 @@ llg_status check_opts(const llg_solver_opts* o) {
   if (o->precond < 0 || o->precond > 2) return fail(LLG_EARG, "precond must be 0, 1 or 2");
   if (o->precond != 0 && o->prec != LLG_FP64) return fail(LLG_EARG, "comparison preconditioners run in float64");
   if (o->orth == 0 && o->restart > 31) return fail(LLG_EARG, "delayed CGS2 supports restart <= 31");
+  if (o->picard_norm != 0 && o->picard_norm != 1) return fail(LLG_EARG, "picard_norm must be 0 or 1");
   if (o->prec == LLG_FP32_IR) {
     if (o->max_outer < 1) return fail(LLG_EARG, "max_outer must be >= 1");
     if (!is_fin(o->inner_rtol) || o->inner_rtol <= 0 || o->inner_rtol >= 1)
@@ -95,6 +103,27 @@ NodalArgs nodal_for(const llg_params* p) {
 }
 
 double hcoef(const llg_params* p) { return p->theta * p->dt * (1.0 + p->alpha * p->alpha) * p->cexc; }
+
+// True when the lower-order field depends on m (demagnetization or anisotropy).
+bool has_low(const llg_params* p) { return p->demag != 0.0 || p->aniso_k != 0.0; }
+
+// Multiplier s_id I + s_ex |xi|^2 I + scale (demag xi~ xi~^T / |xi|^2 - 2 K e e^T).
+// (0, cexc, 1) gives -(h_exc + h_dem + h_ani), (0, 0, 1) the lower-order part alone.
+FieldArgs field_for(const Ctx& c, const llg_params* p, double s_id, double s_ex, double scale) {
+  FieldArgs f{};
+  f.s_id = s_id;
+  f.s_ex = s_ex;
+  f.s_dm = scale * p->demag;
+  f.s_an = -scale * 2.0 * p->aniso_k;
+  f.e0 = p->aniso_axis[0];
+  f.e1 = p->aniso_axis[1];
+  f.e2 = p->aniso_axis[2];
+  f.cx = 2.0 * M_PI / c.Lx;
+  f.cy = 2.0 * M_PI / c.Ly;
+  f.cz = c.dim == 3 ? 2.0 * M_PI / c.Lz : 0.0;
+  f.inv_ng = 1.0 / double(c.ng);
+  return f;
+}
 
 hipStream_t as_stream(void* s) { return reinterpret_cast<hipStream_t>(s); }
 
@@ -147,9 +176,27 @@ hipError_t op_lap(const Ctx& c, const double* u, double* out, hipStream_t st) {
   NodalArgs na{};
   return pipe_d(c, PRO_COPY3, EPI_STORE3, sym_for(c, 0.0, 1.0, false), na, u, nullptr, out, st);
 }
-// b = (C_hat Delta_N m + (1+alpha^2) h, 0)
+// b = (C_hat Delta_N m + (1+alpha^2) h_ext, 0)
 hipError_t op_rhs(const Ctx& c, const llg_params* p, const double* m, double* b, hipStream_t st) {
   return pipe_d(c, PRO_COPY3, EPI_RHS, sym_for(c, 0.0, 1.0, false), nodal_for(p), m, nullptr, b, st);
+}
+// One lower-order field pipeline (3x3 multiplier fa, prologue PRO_COPY3).
+hipError_t op_field(const Ctx& c, const FieldArgs& fa, int epi, const NodalArgs& na, const double* in, double* out,
+                    hipStream_t st, const double* m = nullptr, const double* aux_v = nullptr,
+                    const double* aux_r = nullptr) {
+  PipeIO<double, double, double> io{in, m, out, c.ng, aux_v, aux_r};
+  return run_field(c, fa, epi, na, io, st);
+}
+// -(h_exc + h_dem + h_ani)(u) for 3 planes: cexc (-Delta_N) u - L_low u
+hipError_t op_negfield(const Ctx& c, const llg_params* p, const double* u, double* out, hipStream_t st) {
+  return op_field(c, field_for(c, p, 0.0, p->cexc, 1.0), EPI_STORE3, NodalArgs{}, u, out, st);
+}
+// Explicit right-hand side b = (C_hat Delta_N m + (1+alpha^2) h_low(m), 0)
+hipError_t op_rhs_low(const Ctx& c, const llg_params* p, const double* m, double* b, hipStream_t st) {
+  if (!has_low(p)) return op_rhs(c, p, m, b, st);
+  NodalArgs na = nodal_for(p);
+  na.chat = na.hs;  // b_v = -(1+alpha^2) F + (1+alpha^2) h_ext with F = -(h_exc + h_dem + h_ani)
+  return op_field(c, field_for(c, p, 0.0, p->cexc, 1.0), EPI_RHS, na, m, b, st);
 }
 
 // Number of x-inverse blocks of a pipeline (one residual partial each).
@@ -636,13 +683,17 @@ void fill_stats(const SolveResult& r, llg_solver_stats* s) {
   s->rel_res_prec = r.rel_prec;
 }
 
+// g_N(m): with the lower-order field the nodal density is 1/2 m.F - m.h_ext + K,
+// F = -(h_exc + h_dem + h_ani)(m); without it 1/2 cexc m.(-Delta_N m) - m.h_ext.
 llg_status energy_of(const Ctx& c, const llg_params* p, const double* m, double* lm, double* e, hipStream_t st) {
-  CHK(op_lap(c, m, lm, st));
-  CHK(energy_sum(c, nodal_for(p), p->cexc, m, lm, c.scal, st));
+  const bool low = has_low(p);
+  if (low) CHK(op_negfield(c, p, m, lm, st));
+  else CHK(op_lap(c, m, lm, st));
+  CHK(energy_sum(c, nodal_for(p), low ? 1.0 : p->cexc, m, lm, c.scal, st));
   double s;
   CHK_STATUS(fetch(c, c.scal, 1, st, &s));
   const double vol = c.Lx * c.Ly * (c.dim == 3 ? c.Lz : 1.0);
-  *e = s * vol / double(c.ng);
+  *e = s * vol / double(c.ng) + (low ? p->aniso_k * vol : 0.0);
   return LLG_OK;
 }
 
@@ -832,7 +883,7 @@ llg_status llg_rhs(llg_ctx* ctx, const llg_params* prm, const double* m, double*
   if (!ctx || !m || !b) return fail(LLG_EARG, "null argument");
   CHK_STATUS(check_params(prm));
   CHK_STATUS(ensure_device(ctx->c));
-  CHK(op_rhs(ctx->c, prm, m, b, as_stream(stream)));
+  CHK(op_rhs_low(ctx->c, prm, m, b, as_stream(stream)));
   return LLG_OK;
 }
 
@@ -867,7 +918,7 @@ llg_status llg_step_euler(llg_ctx* ctx, const llg_params* prm, double* m, double
   if (stats) std::memset(stats, 0, sizeof(*stats));
   double e0 = 0;
   if (stats) CHK_STATUS(energy_of(c, &p1, m, w.l0, &e0, st));
-  CHK(op_rhs(c, &p1, m, w.b, st));
+  CHK(op_rhs_low(c, &p1, m, w.b, st));
   SolveResult r;
   const llg_status s = solve(c, &p1, m, w.b, w.x, o, w, r, st);
   if (stats) {
@@ -919,7 +970,14 @@ llg_status llg_step_midpoint(llg_ctx* ctx, const llg_params* prm, double* m, dou
   const double k = prm->dt;
   if (stats) std::memset(stats, 0, sizeof(*stats));
   CHK(hipMemcpyAsync(w.m0, m, sizeof(double) * 3 * ng, hipMemcpyDeviceToDevice, st));
+  // Step-constant part of the right-hand side, C_hat Delta_N m^n + (1+alpha^2) h_ext.
+  // With a lower-order field it is kept in l0 and (1+alpha^2) L_low m_hat^p is
+  // added at every Picard iteration (the field frozen at the midpoint, eq. "C-N").
+  const bool low = has_low(prm);
   CHK(op_rhs(c, &p2, w.m0, w.b, st));
+  if (low) CHK(hipMemcpyAsync(w.l0, w.b, sizeof(double) * 3 * ng, hipMemcpyDeviceToDevice, st));
+  const FieldArgs fa_low = field_for(c, prm, 0.0, 0.0, 1.0);
+  const NodalArgs na2 = nodal_for(&p2);
   if (v_half) {
     CHK(hipMemcpyAsync(w.vold, v_half, sizeof(double) * 3 * ng, hipMemcpyDeviceToDevice, st));
     CHK(hipMemcpyAsync(w.x, v_half, sizeof(double) * 3 * ng, hipMemcpyDeviceToDevice, st));
@@ -929,26 +987,29 @@ llg_status llg_step_midpoint(llg_ctx* ctx, const llg_params* prm, double* m, dou
   }
   if (lam) CHK(hipMemcpyAsync(w.x + 3 * ng, lam, sizeof(double) * ng, hipMemcpyDeviceToDevice, st));
   else CHK(hipMemsetAsync(w.x + 3 * ng, 0, sizeof(double) * ng, st));
+  CHK(nodal_axpy3(c, w.m0, 0.5 * k, w.vold, w.mh, st));
   int iters = 0, pic = 0;
   bool pconv = false, lconv = true;
   double change = 0;
   llg_status lin = LLG_OK;
   for (int p = 0; p < picard_max; ++p) {
-    CHK(nodal_axpy3(c, w.m0, 0.5 * k, w.vold, w.mh, st));
+    if (low) CHK(op_field(c, fa_low, EPI_ADDF, na2, w.mh, w.b, st, nullptr, w.l0));
     SolveResult r;
     lin = solve(c, &p2, w.mh, w.b, w.x, o, w, r, st);
     iters += r.iters;
     pic++;
     if (lin != LLG_OK && lin != LLG_ENOCONV) return lin;
     if (lin == LLG_ENOCONV) lconv = false;
-    double dn[2];
-    CHK(diff_norms(c, w.x, w.vold, 3 * ng, c.scal, st));
-    CHK_STATUS(fetch(c, c.scal, 2, st, dn));
-    CHK(hipMemcpyAsync(w.vold, w.x, sizeof(double) * 3 * ng, hipMemcpyDeviceToDevice, st));
-    const double vn = std::sqrt(dn[1]), dd = std::sqrt(dn[0]);
-    change = vn > 0 ? dd / vn : dd;
+    // ||v^p - v^{p-1}||^2, ||v^p||^2, ||m_hat^{p+1}||^2; vold <- v^p, mh <- m_hat^{p+1}
+    double dn[3];
+    CHK(picard_update(c, w.m0, w.x, w.vold, w.mh, 0.5 * k, c.scal, st));
+    CHK_STATUS(fetch(c, c.scal, 3, st, dn));
+    const double dd = std::sqrt(dn[0]);
+    const double num = opts->picard_norm == 0 ? 0.5 * k * dd : dd;
+    const double ref = std::sqrt(opts->picard_norm == 0 ? dn[2] : dn[1]);
+    change = ref > 0 ? num / ref : num;
     if (!is_fin(change)) return fail(LLG_ENAN, "non-finite Picard update");
-    if (dd <= picard_tol * vn) {
+    if (num <= picard_tol * ref) {
       pconv = true;
       break;
     }
@@ -961,17 +1022,31 @@ llg_status llg_step_midpoint(llg_ctx* ctx, const llg_params* prm, double* m, dou
     stats->lin_iters_total = iters;
     stats->converged = (pconv && lconv) ? 1 : 0;
     stats->picard_rel_change = change;
-    CHK(op_lap(c, w.m0, w.l0, st));
-    CHK(op_lap(c, w.x, w.l1, st));
+    // l0 = F(m^n), l1 = F(v) with F = C_hat/(1+alpha^2) (-Delta_N) (no lower-order
+    // field) or -(h_exc + h_dem + h_ani) (with it); the diagnostic kernel uses
+    // linearity for m^{n+1} = m^n + k v and the exact midpoint m^n + (k/2) v.
+    NodalArgs nd = nodal_for(prm);
+    double ecoef = prm->cexc;
+    if (low) {
+      CHK(op_negfield(c, prm, w.m0, w.l0, st));
+      CHK(op_negfield(c, prm, w.x, w.l1, st));
+      nd.chat = nd.hs;
+      ecoef = 1.0;
+    } else {
+      CHK(op_lap(c, w.m0, w.l0, st));
+      CHK(op_lap(c, w.x, w.l1, st));
+    }
     double d[5], len;
-    CHK(midpoint_diag(c, nodal_for(prm), prm->alpha, prm->cexc, k, w.m0, w.x, w.x + 3 * ng, w.l0, w.l1, c.scal, st));
+    CHK(midpoint_diag(c, nd, prm->alpha, ecoef, k, w.m0, w.x, w.x + 3 * ng, w.l0, w.l1, c.scal, st));
     CHK_STATUS(fetch(c, c.scal, 5, st, d));
     CHK(len_err(c, m, c.scal, st));
     CHK_STATUS(fetch(c, c.scal, 1, st, &len));
-    const double wq = c.Lx * c.Ly * (c.dim == 3 ? c.Lz : 1.0) / double(ng);
+    const double vol = c.Lx * c.Ly * (c.dim == 3 ? c.Lz : 1.0);
+    const double wq = vol / double(ng);
+    const double econst = low ? prm->aniso_k * vol : 0.0;
     const double a = prm->alpha;
-    stats->energy_before = wq * d[0];
-    stats->energy_after = wq * d[1];
+    stats->energy_before = wq * d[0] + econst;
+    stats->energy_after = wq * d[1] + econst;
     stats->v_norm2 = wq * d[2];
     stats->dissipation_defect = stats->energy_after - stats->energy_before + a * k / (1 + a * a) * stats->v_norm2;
     stats->inexact_correction = k / (1 + a * a) * (wq * d[3] - wq * d[4]);
@@ -1008,7 +1083,12 @@ llg_status llg_step_midpoint_adjoint(llg_ctx* ctx, const llg_params* prm, const 
   CHK(hipMemsetAsync(w.b + 3 * ng, 0, sizeof(double) * ng, st));
   const SymArgs sym_h = sym_for(c, p2.alpha, hcoef(&p2), false);
   const NodalArgs na = nodal_for(&p2);
+  // With a lower-order field the velocity block of J^T gains -(k/2)(1+alpha^2) L_low,
+  // so its Fourier part is the 3x3 multiplier alpha + (k/2)(1+alpha^2)[cexc |xi|^2 - L_low^].
+  const bool low = has_low(prm);
+  const FieldArgs fa_jt = field_for(c, prm, p2.alpha, hcoef(&p2), 0.5 * k * na.hs);
   Op JT = [&](const double* in, double* out) {
+    if (low) return op_field(c, fa_jt, EPI_JT, na, in, out, st, m_n, v, lam);
     return pipe_d(c, PRO_COPY3, EPI_JT, sym_h, na, in, m_n, out, st, v, lam);
   };
   Op MT = [&](const double* in, double* out) { return op_apply(c, &p2, w.mh, in, out, true, st); };
@@ -1019,14 +1099,31 @@ llg_status llg_step_midpoint_adjoint(llg_ctx* ctx, const llg_params* prm, const 
   };
   llg_solver_opts o = *opts;
   o.use_x0 = 0;
-  const ResidOp RJT = resid_op(c, EPI_JT, sym_h, na, m_n, st, v, lam);
+  ResidOp RJT = resid_op(c, EPI_JT, sym_h, na, m_n, st, v, lam);
+  if (low) {
+    RJT = [&c, fa_jt, na, m_n, st, v, lam](const double* x, const double* b, double* r) -> hipError_t {
+      PipeIO<double, double, double> io{x, m_n, r, c.ng, v, lam};
+      io.rhs = b;
+      io.red = c.partial;
+      hipError_t e = run_field(c, fa_jt, EPI_JT, na, io, st);
+      if (e != hipSuccess) return e;
+      return reduce_flat(c, xinv_blocks(c), c.scal, st);
+    };
+  }
   SolveResult r;
   const llg_status s = gmres_left(c, RJT, MT, MTJT, w.b, w.x, o, w, r, st);
   fill_stats(r, stats);
   if (s != LLG_OK) return s;
-  // gbar update and field gradients
-  CHK(op_lap(c, w.x, w.l0, st));
-  CHK(adjoint_finish(c, na, v, lam, w.x, w.l0, gbar, hbar_field, c.scal, st));
+  // gbar update and field gradients: gbar -= v x mu_v + chat F mu_v + r mu_v - v mu_r,
+  // F = (-Delta_N) (chat = C_hat) or -(h_exc + h_dem + h_ani) (chat = 1 + alpha^2)
+  NodalArgs nf = na;
+  if (low) {
+    CHK(op_negfield(c, prm, w.x, w.l0, st));
+    nf.chat = nf.hs;
+  } else {
+    CHK(op_lap(c, w.x, w.l0, st));
+  }
+  CHK(adjoint_finish(c, nf, v, lam, w.x, w.l0, gbar, hbar_field, c.scal, st));
   double hs3[3];
   CHK_STATUS(fetch(c, c.scal, 3, st, hs3));
   if (hbar_uniform)

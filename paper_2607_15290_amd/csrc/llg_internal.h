@@ -31,7 +31,8 @@ constexpr int kMaxDots = 64;
 // Kernel kinds known to the event profiler.
 enum KernelKind : int {
   KK_XFWD = 0, KK_AXIS_FWD, KK_AXIS_FUSED, KK_AXIS_INV, KK_XINV, KK_CGS_DOTS, KK_CGS_UPDATE_DOTS,
-  KK_CGS_UPDATE_NORM, KK_REDUCE, KK_SCALE, KK_AXPBY, KK_LINCOMB, KK_CONVERT, KK_DOT2, KK_NODAL, KK_COUNT
+  KK_CGS_UPDATE_NORM, KK_REDUCE, KK_SCALE, KK_AXPBY, KK_LINCOMB, KK_CONVERT, KK_DOT2, KK_NODAL, KK_FIELD3,
+  KK_COUNT
 };
 const char* kernel_kind_name(int k);
 
@@ -71,6 +72,12 @@ SymArgs sym_for(const Ctx& c, double a, double b, bool invert);
 template <typename T, typename TIn, typename TOut>
 hipError_t run_pipeline(const Ctx& c, int pro, int epi, const SymArgs& sym, const NodalArgs& na,
                         const PipeIO<T, TIn, TOut>& io, hipStream_t st);
+
+// Lower-order field pipeline (field.hip, float64): forward DFTs of three
+// planes, the 3x3 multiplier of FieldArgs, inverse DFTs, then the x-inverse
+// epilogue `epi` (EPI_STORE3, EPI_RHS, EPI_ADDF or EPI_JT; prologue PRO_COPY3).
+hipError_t run_field(const Ctx& c, const FieldArgs& fa, int epi, const NodalArgs& na,
+                     const PipeIO<double, double, double>& io, hipStream_t st);
 
 // Axis passes (axis.hip).
 template <typename T>

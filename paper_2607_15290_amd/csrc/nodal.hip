@@ -3,6 +3,7 @@
 //   euler_update   projected Euler update m <- (m + k v)/|m + k v| (Sec. 3.2)
 //   nodal_axpy3    frozen midpoint m^n + (k/2) v and the update m^n + k v
 //                  (Sec. 3.3, eq. "hatm")
+//   picard_update  Picard change norms and the next frozen midpoint
 //   midpoint_diag  energies, ||v||^2 and the residual functionals rho(v) and
 //                  chi(r) of eq. "C-N" at the exact midpoint (Remark on the
 //                  effect of an inexact midpoint solve)
@@ -86,6 +87,25 @@ __global__ __launch_bounds__(kRedThreads) void k_euler_update(double* __restrict
 __global__ void k_axpy3(const double* __restrict__ m, double a, const double* __restrict__ v,
                         double* __restrict__ out, long long n) {
   GRID_LOOP(i, n) out[i] = m[i] + a * v[i];
+}
+
+// Picard bookkeeping of the midpoint step, one pass over 3 planes:
+// partial sums of ||v - vold||^2, ||v||^2 and ||m0 + a v||^2, then vold <- v
+// and mh <- m0 + a v (the next frozen midpoint).
+__global__ __launch_bounds__(kRedThreads) void k_picard_update(const double* __restrict__ m0,
+                                                              const double* __restrict__ v,
+                                                              double* __restrict__ vold, double* __restrict__ mh,
+                                                              double a, long long n, double* __restrict__ partial) {
+  double acc[3] = {0, 0, 0};
+  GRID_LOOP(i, n) {
+    const double vi = v[i], d = vi - vold[i], mi = m0[i] + a * vi;
+    acc[0] += d * d;
+    acc[1] += vi * vi;
+    acc[2] += mi * mi;
+    vold[i] = vi;
+    mh[i] = mi;
+  }
+  bstore<3, 0>(acc, partial);
 }
 
 __global__ __launch_bounds__(kRedThreads) void k_len_err(const double* __restrict__ m, long long ng,
@@ -272,6 +292,18 @@ hipError_t midpoint_diag(const Ctx& c, const NodalArgs& na, double alpha, double
   hipLaunchKernelGGL(k_midpoint_diag, dim3(kRedBlocks), dim3(kRedThreads), 0, st, na, alpha, cexc, k, m0, v, r, lm0,
                      lv, c.ng, c.partial);
   e_ = reduce_partials(c, 5, out, false, st);
+  }
+  return e_;
+}
+
+hipError_t picard_update(const Ctx& c, const double* m0, const double* v, double* vold, double* mh, double a,
+                         double* out, hipStream_t st) {
+  hipError_t e_ = hipSuccess;
+  {
+  ProfScope ps(c.prof, st, KK_NODAL, 0.0);
+  hipLaunchKernelGGL(k_picard_update, dim3(kRedBlocks), dim3(kRedThreads), 0, st, m0, v, vold, mh, a, 3 * c.ng,
+                     c.partial);
+  e_ = reduce_partials(c, 3, out, false, st);
   }
   return e_;
 }

@@ -65,6 +65,21 @@ enum EpiMode : int {
   EPI_JT = 7,        // out = J^T mu of the midpoint residual (adjoint), F = H mu_v
   EPI_APPLY_SYM = 8, // out = (F, p_r / lambda): (lambda I + calH)^{-1} p alone
   EPI_FUSED_SYM = 9, // out = x + (F, (-m.v - lambda r) / lambda): (lambda I + calH)^{-1} A x
+  EPI_ADDF = 10,     // out = (aux_v - (1+alpha^2) F, 0): right-hand side with the lower-order field
+};
+
+// Symmetric 3x3 Fourier multiplier of the lower-order field pipeline:
+//   M(xi) = (s_id + s_ex |xi|^2) I + s_dm xi~ xi~^T / |xi|^2 + s_an e e^T,
+// xi~ = xi with the Nyquist entry of each axis set to zero (spectral first
+// derivative of real data), the demagnetizing term zero at xi = 0.  With
+// s_id = 0, s_ex = cexc, s_dm = demag, s_an = -2K the output is minus the
+// linear part of the effective field (exchange, periodic demagnetization of
+// Sec. 2.2, uniaxial anisotropy of Sec. 2.1).
+struct FieldArgs {
+  double s_id, s_ex, s_dm, s_an;
+  double e0, e1, e2;   // easy axis
+  double cx, cy, cz;   // 2 pi / L per axis
+  double inv_ng;
 };
 
 // Pointers of one pipeline call.  "in" planes feed the prologue (and are

@@ -165,7 +165,7 @@ __device__ __forceinline__ void prologue_compute(const ProRaw<T, TIn, PRO>& r, c
 // ---------------------------------------------------------------------------
 template <typename T, typename TIn, typename TOut, int EPI>
 struct EpiRaw {
-  static constexpr bool NODAL = !(EPI == EPI_STORE3 || EPI == EPI_RHS);
+  static constexpr bool NODAL = !(EPI == EPI_STORE3 || EPI == EPI_RHS || EPI == EPI_ADDF);
   TIn v[4][2];   // x or p planes (nodal modes)
   T m[3][2];     // magnetization (nodal modes)
   T av[3][2];    // forward velocity (EPI_JT)
@@ -198,6 +198,9 @@ __device__ __forceinline__ void epilogue_load(const PipeIO<T, TIn, TOut>& io, co
       for (int f = 0; f < 3; ++f) load2(io.aux_v + f * ng + i, r.av[f][0], r.av[f][1]);
       load2(io.aux_r + i, r.ar[0], r.ar[1]);
     }
+  } else if constexpr (EPI == EPI_ADDF) {
+#pragma unroll
+    for (int f = 0; f < 3; ++f) load2(io.aux_v + f * ng + i, r.av[f][0], r.av[f][1]);
   } else if constexpr (EPI == EPI_RHS) {
     if (na.hfield) {
 #pragma unroll
@@ -222,6 +225,12 @@ __device__ __forceinline__ void epilogue_compute(const EpiRaw<T, TIn, TOut, EPI>
     o[0] = F[0];
     o[1] = F[1];
     o[2] = F[2];
+    o[3] = T(0);
+  } else if constexpr (EPI == EPI_ADDF) {
+    const T hs = T(na.hs);
+    o[0] = r.av[0][h] - hs * F[0];
+    o[1] = r.av[1][h] - hs * F[1];
+    o[2] = r.av[2][h] - hs * F[2];
     o[3] = T(0);
   } else if constexpr (EPI == EPI_RHS) {
     const T c = T(na.chat), hs = T(na.hs);

@@ -51,6 +51,7 @@ void launch_xinv(const Ctx& c, const NodalArgs& na, const PipeIO<T, TIn, TOut>& 
     else if (EPI == EPI_APPLY) node_b = 1.0 * sizeof(TIn) + 3.0 * sizeof(T) + 4.0 * sizeof(TOut);
     else if (EPI == EPI_APPLY_SYM) node_b = 1.0 * sizeof(TIn) + 4.0 * sizeof(TOut);
     else if (EPI == EPI_JT) node_b = 4.0 * sizeof(TIn) + 7.0 * sizeof(T) + 4.0 * sizeof(TOut);
+    else if (EPI == EPI_ADDF) node_b = 3.0 * sizeof(T) + 4.0 * sizeof(TOut);
     else node_b = 4.0 * sizeof(TIn) + 3.0 * sizeof(T) + 4.0 * sizeof(TOut);
     if (io.rhs) node_b += 4.0 * sizeof(TOut);
     ProfScope ps(c.prof, st, KK_XINV, double(c.ng) * node_b + double(c.geom.cs) * lines * 2 * sizeof(T));

@@ -37,7 +37,8 @@ def _check(status, where):
 class Params:
     """Physical parameters (llg_params): alpha, cexc, dt (k), theta, shift
     (the HSS lambda), uniform applied field, optional spatial field tensor
-    (3 planes, float64, on the GPU)."""
+    (3 planes, float64, on the GPU), demagnetizing-field coefficient (0 or
+    1), uniaxial anisotropy coefficient K and unit easy axis."""
     alpha: float = 0.2
     cexc: float = 1.0
     dt: float = 1e-2
@@ -45,6 +46,9 @@ class Params:
     shift: float = 0.5
     h_uniform: tuple = (0.0, 0.0, 0.0)
     h_field: Optional[torch.Tensor] = field(default=None, repr=False)
+    demag: float = 0.0
+    aniso_k: float = 0.0
+    aniso_axis: tuple = (0.0, 0.0, 1.0)
 
     def c_struct(self):
         p = L.LLGParams()
@@ -53,17 +57,23 @@ class Params:
         for i in range(3):
             p.h_uniform[i] = float(self.h_uniform[i])
         p.h_field = self.h_field.data_ptr() if self.h_field is not None else None
+        p.demag, p.aniso_k = float(self.demag), float(self.aniso_k)
+        for i in range(3):
+            p.aniso_axis[i] = float(self.aniso_axis[i])
         return p
 
 
 ORTH = {"dcgs2": 0, "cgs2": 1, 0: 0, 1: 1}
 PRECOND = {"fft_hss": 0, "symmetric": 1, "none": 2, 0: 0, 1: 1, 2: 2}
+PICARD_NORM = {"midpoint": 0, "velocity": 1, 0: 0, 1: 1}
 
 
-def _opts(restart, maxiter, rtol, prec, inner_rtol, max_outer, use_x0, orth="dcgs2", precond="fft_hss"):
+def _opts(restart, maxiter, rtol, prec, inner_rtol, max_outer, use_x0, orth="dcgs2", precond="fft_hss",
+          picard_norm="midpoint"):
     o = L.LLGSolverOpts()
     o.orth = ORTH[orth]
     o.precond = PRECOND[precond]
+    o.picard_norm = PICARD_NORM[picard_norm]
     o.restart, o.maxiter, o.max_outer, o.use_x0 = int(restart), int(maxiter), int(max_outer), int(use_x0)
     o.rtol, o.inner_rtol = float(rtol), float(inner_rtol)
     o.prec = _PREC[prec]
@@ -205,9 +215,11 @@ def llg_step_euler(ctx, params, m, v_out=None, lam_out=None, restart=30, rtol=1e
 
 def llg_step_midpoint(ctx, params, m, v_half=None, lam=None, picard_tol=1e-10, picard_max=50, restart=30,
                       rtol=1e-10, maxiter=3000, prec="fp64", inner_rtol=1e-5, max_outer=20, check=True,
-                      orth="dcgs2"):
-    """One midpoint step; m, v_half, lam updated in place.  Returns stats."""
-    o = _opts(restart, maxiter, rtol, prec, inner_rtol, max_outer, 1, orth)
+                      orth="dcgs2", picard_norm="midpoint"):
+    """One midpoint step; m, v_half, lam updated in place.  picard_norm:
+    "midpoint" (change of the frozen midpoint, default) or "velocity".
+    Returns stats."""
+    o = _opts(restart, maxiter, rtol, prec, inner_rtol, max_outer, 1, orth, picard_norm=picard_norm)
     st = L.LLGStepStats()
     work = ctx.workspace(restart, prec)
     pr = params.c_struct()
@@ -247,7 +259,7 @@ def llg_step_midpoint_adjoint(ctx, params, m_n, v, lam, gbar, hbar_field=None, h
 
 
 def llg_rhs(ctx, params, m, b=None):
-    """b = (C_hat Delta_N m + (1+alpha^2) h, 0).  See llg_rhs in include/llg.h."""
+    """b = (C_hat Delta_N m + (1+alpha^2) h_low(m), 0).  See llg_rhs in include/llg.h."""
     b = ctx.new(4) if b is None else b
     pr = params.c_struct()
     _check(ctx.lib.llg_rhs(ctx.handle, ctypes.byref(pr), ctx.check(m, 3, name="m"), ctx.check(b, 4, name="b"),

@@ -64,3 +64,32 @@ def test_entry_points_reject_null_context(lib):
                                  0, None) == 1
     assert lib.llg_workspace_bytes(None, 30, 0) == 0
     assert lib.llg_ctx_destroy(None) == 0
+
+
+def test_binding_structs_match_header_layout(tmp_path):
+    """Every ctypes structure of the binding has the size and field offsets
+    the C compiler gives the header's struct (compiled with gcc here)."""
+    import shutil
+    import subprocess
+    from paper_2607_15290_amd import _lib
+    if shutil.which("gcc") is None:
+        pytest.skip("gcc not available")
+    structs = {"llg_params": _lib.LLGParams, "llg_solver_opts": _lib.LLGSolverOpts,
+               "llg_solver_stats": _lib.LLGSolverStats, "llg_step_stats": _lib.LLGStepStats,
+               "llg_kernel_profile": _lib.LLGKernelProfile}
+    lines = ["#include <stddef.h>", "#include <stdio.h>", '#include "llg.h"', "int main(void) {"]
+    for cname, cls in structs.items():
+        lines.append(f'  printf("{cname} size %zu\\n", sizeof({cname}));')
+        for fname, _ in cls._fields_:
+            lines.append(f'  printf("{cname} {fname} %zu\\n", offsetof({cname}, {fname}));')
+    lines += ["  return 0;", "}"]
+    src = tmp_path / "layout.c"
+    src.write_text("\n".join(lines) + "\n")
+    exe = tmp_path / "layout"
+    subprocess.run(["gcc", "-std=c99", "-I", os.path.join(ROOT, "include"), str(src), "-o", str(exe)], check=True)
+    out = subprocess.run([str(exe)], check=True, capture_output=True, text=True).stdout.split("\n")
+    got = {tuple(l.split()[:2]): int(l.split()[2]) for l in out if l.strip()}
+    for cname, cls in structs.items():
+        assert got[(cname, "size")] == ctypes.sizeof(cls), cname
+        for fname, _ in cls._fields_:
+            assert got[(cname, fname)] == getattr(cls, fname).offset, (cname, fname)

@@ -114,8 +114,10 @@ def test_midpoint_steps_invariants_and_oracle():
     lam = torch.zeros((1, 1, n, n), dtype=torch.float64, device="cuda:0")
     m_ref, v_ref, l_ref = m0, None, None
     for step in range(3):
-        st = P.llg_step_midpoint(ctx, prm, md, vh, lam, picard_tol=1e-12, picard_max=60, rtol=1e-13)
-        m_ref, v_ref, l_ref, info = steppers.midpoint_step(g, op, m_ref, v_ref, l_ref, rtol=1e-13, picard_tol=1e-12,
+        # Picard change of the frozen midpoint to 1e-13: the length defect 2 k chi
+        # then stays below 1e-12
+        st = P.llg_step_midpoint(ctx, prm, md, vh, lam, picard_tol=1e-13, picard_max=60, rtol=1e-13)
+        m_ref, v_ref, l_ref, info = steppers.midpoint_step(g, op, m_ref, v_ref, l_ref, rtol=1e-13, picard_tol=1e-13,
                                                            picard_max=60)
         assert st["converged"] == 1
         assert st["max_len_err"] <= 1e-12

@@ -44,8 +44,13 @@ def test_workload2_midpoint_512():
             # both sides converge Picard and GMRES to 1e-10
             assert np.max(np.abs(host(m) - m_ref)) <= 1e-10
             assert rel(host(vh), v_ref) <= 1e-8
+            len_ref = steppers.midpoint_diagnostics(g, op, spec["m0"], m_ref, v_ref, l_ref)["max_len_err"]
+            assert st["max_len_err"] <= 2 * len_ref + 1e-12
         assert st["converged"] == 1
-        assert st["max_len_err"] <= 1e-9
+        # The Picard test stops on the change of the frozen midpoint, (k/2)||dv||
+        # <= 1e-10 ||m_hat||; the length defect 2 k m^{n+1/2}.v then carries a
+        # k^2 |dv| |v| term of about 1e-9 at this stiffness.
+        assert st["max_len_err"] <= 5e-9
         scale = abs(st["energy_before"])
         assert abs(st["dissipation_defect"] - st["inexact_correction"]) <= 1e-13 * scale
         if e_prev is not None:
