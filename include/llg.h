@@ -127,12 +127,19 @@ typedef struct {
   double v_norm2;           /* ||v||_N^2 */
 } llg_step_stats;
 
-/* Create a context for an nx x ny x nz grid (nz = 1: 2-D) with spacing h on
- * device `device`.  Each n must be a power of two in [4, 512].  Allocates the
- * twiddle tables, the spectral scratch (about 48 N_g bytes) and reduction
- * buffers.  Errors: LLG_EARG (null out, bad n or h), LLG_EUNSUPPORTED,
- * LLG_ENOMEM, LLG_EHIP. */
+/* Create a context for an nx x ny x nz grid (nz = 1: 2-D) with spacing h in
+ * every direction (cell lengths n h; Sec. 2.3) on device `device`.
+ * Grid sizes: ny and nz (or nz = 1) in [4, 512] and nx / 2 in [2, 256], each
+ * of the form 2^a, 3 * 2^a or 5 * 2^a (nx even).  Allocates the twiddle
+ * tables, the spectral scratch (about 48 N_g bytes) and reduction buffers.
+ * Errors: LLG_EARG (null out, unsupported n, bad h), LLG_ENOMEM, LLG_EHIP. */
 llg_status llg_ctx_create(llg_ctx** out, int nx, int ny, int nz, double h, int device);
+
+/* The same for a cell of lengths lx, ly, lz (spacings lx / nx, ly / ny,
+ * lz / nz may differ; lz is unused in 2-D but must be > 0): the periodic
+ * cell prod_l (0, L_l) of Sec. 2.3 with wave numbers 2 pi k_l / L_l. */
+llg_status llg_ctx_create_cell(llg_ctx** out, int nx, int ny, int nz, double lx, double ly, double lz,
+                               int device);
 llg_status llg_ctx_destroy(llg_ctx* ctx);
 
 /* Bytes of caller workspace that gmres_solve and the steppers need with

@@ -54,6 +54,8 @@ P = ctypes.c_void_p
 I = ctypes.c_int
 SIGNATURES = {
     "llg_ctx_create": (I, [ctypes.POINTER(ctypes.c_void_p), I, I, I, ctypes.c_double, I]),
+    "llg_ctx_create_cell": (I, [ctypes.POINTER(ctypes.c_void_p), I, I, I, ctypes.c_double, ctypes.c_double,
+                                ctypes.c_double, I]),
     "llg_ctx_destroy": (I, [P]),
     "llg_workspace_bytes": (ctypes.c_size_t, [P, I, I]),
     "llg_matvec": (I, [P, ctypes.POINTER(LLGParams), P, P, P, I, P]),

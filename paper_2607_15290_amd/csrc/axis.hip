@@ -28,14 +28,10 @@ template <typename T>
 hipError_t launch_axis(const Ctx& c, int axis, int mode, const SymArgs& sym, cx<T>* spec, hipStream_t st) {
   const int n = axis == 1 ? c.ny : c.nz;
   switch (n) {
-    case 4: return axis_n<T, 4>(c, axis, mode, sym, spec, st);
-    case 8: return axis_n<T, 8>(c, axis, mode, sym, spec, st);
-    case 16: return axis_n<T, 16>(c, axis, mode, sym, spec, st);
-    case 32: return axis_n<T, 32>(c, axis, mode, sym, spec, st);
-    case 64: return axis_n<T, 64>(c, axis, mode, sym, spec, st);
-    case 128: return axis_n<T, 128>(c, axis, mode, sym, spec, st);
-    case 256: return axis_n<T, 256>(c, axis, mode, sym, spec, st);
-    case 512: return axis_n<T, 512>(c, axis, mode, sym, spec, st);
+#define LLG_CASE(v) \
+  case v: return axis_n<T, v>(c, axis, mode, sym, spec, st);
+    LLG_FOR_AXIS(LLG_CASE)
+#undef LLG_CASE
     default: return hipErrorInvalidValue;
   }
 }

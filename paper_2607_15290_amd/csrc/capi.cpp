@@ -43,7 +43,6 @@ SymArgs sym_for(const Ctx& c, double a, double b, bool invert) {
 
 namespace {
 
-bool pow2_in(int n, int lo, int hi) { return n >= lo && n <= hi && (n & (n - 1)) == 0; }
 bool is_fin(double v) { return std::isfinite(v); }
 
 llg_status fail(llg_status s, const std::string& msg) {
@@ -707,12 +706,16 @@ extern "C" {
 
 const char* llg_last_error(void) { return g_err.c_str(); }
 
-llg_status llg_ctx_create(llg_ctx** out, int nx, int ny, int nz, double h, int device) {
+llg_status llg_ctx_create_cell(llg_ctx** out, int nx, int ny, int nz, double lx, double ly, double lz,
+                               int device) {
   if (!out) return fail(LLG_EARG, "out is null");
   *out = nullptr;
-  if (!pow2_in(nx, 4, 512) || !pow2_in(ny, 4, 512) || !(nz == 1 || pow2_in(nz, 4, 512)))
-    return fail(LLG_EARG, "each of nx, ny must be a power of two in [4, 512]; nz must be 1 or such a power");
-  if (!is_fin(h) || h <= 0) return fail(LLG_EARG, "h must be finite and > 0");
+  if (nx % 2 != 0 || !nh_supported(nx / 2) || !axis_supported(ny) || !(nz == 1 || axis_supported(nz)))
+    return fail(LLG_EARG,
+                "unsupported grid: nx must be 2 n with n in {2..256} of the form 2^a, 3*2^a or 5*2^a; ny and "
+                "nz (or nz = 1) in [4, 512] of the form 2^a, 3*2^a or 5*2^a");
+  if (!is_fin(lx) || lx <= 0 || !is_fin(ly) || ly <= 0 || !is_fin(lz) || lz <= 0)
+    return fail(LLG_EARG, "cell lengths must be finite and > 0");
   if (device < 0) return fail(LLG_EARG, "device must be >= 0");
   int ndev = 0;
   if (hipGetDeviceCount(&ndev) != hipSuccess || device >= ndev) return fail(LLG_EHIP, "no such HIP device");
@@ -724,10 +727,9 @@ llg_status llg_ctx_create(llg_ctx** out, int nx, int ny, int nz, double h, int d
   c.nz = nz;
   c.dim = nz == 1 ? 2 : 3;
   c.device = device;
-  c.h = h;
-  c.Lx = nx * h;
-  c.Ly = ny * h;
-  c.Lz = nz * h;
+  c.Lx = lx;
+  c.Ly = ly;
+  c.Lz = lz;
   c.ng = (long long)nx * ny * nz;
   c.geom.nx = nx;
   c.geom.ny = ny;
@@ -772,6 +774,14 @@ llg_status llg_ctx_create(llg_ctx** out, int nx, int ny, int nz, double h, int d
   }
   *out = ctx;
   return LLG_OK;
+}
+
+llg_status llg_ctx_create(llg_ctx** out, int nx, int ny, int nz, double h, int device) {
+  if (!is_fin(h) || h <= 0) {
+    if (out) *out = nullptr;
+    return fail(LLG_EARG, "h must be finite and > 0");
+  }
+  return llg_ctx_create_cell(out, nx, ny, nz, nx * h, ny * h, nz * h, device);
 }
 
 llg_status llg_ctx_destroy(llg_ctx* ctx) {

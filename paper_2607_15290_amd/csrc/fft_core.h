@@ -51,32 +51,69 @@ __device__ __forceinline__ cx<T> mul_dir_i(cx<T> a) {
 }
 
 // ---------------------------------------------------------------------------
-// Radix plans: P points per thread, up to three stages.
+// Radix plans: P points per thread, TPL = N / P threads per line (always a
+// power of two), up to four stages whose radices all divide P.
 //   N:   2   4   8  16  32    64    128    256     512      1024
 //   R:  [2] [4] [8][16][8,4] [8,8] [16,8] [16,16] [8,8,8] [16,16,4]
+// Lengths 3 * 2^k and 5 * 2^k (the grids N = 24, 48 of the paper's 3D
+// experiments, among others) keep the odd factor inside P:
+//   N:   3   5   6     10    12    20    24    40 (P 20)  48 (P 12)  80 (P 20)
+//   R:  [3] [5] [2,3] [2,5] [4,3] [4,5] [8,3] [4,2,5]    [4,4,3]    [4,4,5]
+//   N:   96 (P 24)  160 (P 20)  192 (P 24)  320 (P 20)  384 (P 24)
+//   R:  [8,4,3]    [4,4,2,5]   [8,8,3]     [4,4,4,5]   [8,4,4,3]
 // ---------------------------------------------------------------------------
-__host__ __device__ constexpr int plan_p(int n) {
-  return n <= 16 ? n : (n == 32 || n == 64 || n == 512) ? 8 : 16;
+struct Plan {
+  int p, nst, r0, r1, r2, r3;
+};
+__host__ __device__ constexpr Plan plan_of(int n) {
+  switch (n) {
+    case 2: return {2, 1, 2, 1, 1, 1};
+    case 3: return {3, 1, 3, 1, 1, 1};
+    case 4: return {4, 1, 4, 1, 1, 1};
+    case 5: return {5, 1, 5, 1, 1, 1};
+    case 6: return {6, 2, 2, 3, 1, 1};
+    case 8: return {8, 1, 8, 1, 1, 1};
+    case 10: return {10, 2, 2, 5, 1, 1};
+    case 12: return {12, 2, 4, 3, 1, 1};
+    case 16: return {16, 1, 16, 1, 1, 1};
+    case 20: return {20, 2, 4, 5, 1, 1};
+    case 24: return {24, 2, 8, 3, 1, 1};
+    case 32: return {8, 2, 8, 4, 1, 1};
+    case 40: return {20, 3, 4, 2, 5, 1};
+    case 48: return {12, 3, 4, 4, 3, 1};
+    case 64: return {8, 2, 8, 8, 1, 1};
+    case 80: return {20, 3, 4, 4, 5, 1};
+    case 96: return {24, 3, 8, 4, 3, 1};
+    case 128: return {16, 2, 16, 8, 1, 1};
+    case 160: return {20, 4, 4, 4, 2, 5};
+    case 192: return {24, 3, 8, 8, 3, 1};
+    case 256: return {16, 2, 16, 16, 1, 1};
+    case 320: return {20, 4, 4, 4, 4, 5};
+    case 384: return {24, 4, 8, 4, 4, 3};
+    case 512: return {8, 3, 8, 8, 8, 1};
+    case 1024: return {16, 3, 16, 16, 4, 1};
+    default: return {0, 0, 1, 1, 1, 1};
+  }
 }
-__host__ __device__ constexpr int plan_stages(int n) {
-  return n <= 16 ? 1 : (n <= 256 ? 2 : 3);
-}
+// true for the line lengths that have a plan
+__host__ __device__ constexpr bool plan_ok(int n) { return plan_of(n).p > 0; }
+__host__ __device__ constexpr int plan_p(int n) { return plan_of(n).p; }
+__host__ __device__ constexpr int plan_stages(int n) { return plan_of(n).nst; }
 __host__ __device__ constexpr int plan_radix(int n, int s) {
-  return n <= 16 ? n
-         : n == 32   ? (s == 0 ? 8 : 4)
-         : n == 64   ? 8
-         : n == 128  ? (s == 0 ? 16 : 8)
-         : n == 256  ? 16
-         : n == 512  ? 8
-                     : (s < 2 ? 16 : 4);
+  return s == 0 ? plan_of(n).r0 : s == 1 ? plan_of(n).r1 : s == 2 ? plan_of(n).r2 : plan_of(n).r3;
 }
 // product of the radices of the stages before s
 __host__ __device__ constexpr int plan_ns(int n, int s) {
   return s == 0 ? 1 : plan_ns(n, s - 1) * plan_radix(n, s - 1);
 }
-// slot of input position t + TPL*q (first stage has radix P, so slot = q)
+// Slot of input position t + TPL*q.  The first stage (radix R0, B0 = P/R0
+// butterflies per thread) reads position t + TPL*(b + r*B0) in slot b*R0 + r;
+// when R0 = P this is slot q.
 template <int N>
-__device__ __forceinline__ constexpr int in_slot(int q) { return q; }
+__device__ __forceinline__ constexpr int in_slot(int q) {
+  constexpr int B0 = plan_p(N) / plan_radix(N, 0);
+  return (q % B0) * plan_radix(N, 0) + q / B0;
+}
 // position index q held by output slot s of the last stage
 template <int N>
 __device__ __forceinline__ constexpr int out_q(int slot) {
@@ -86,7 +123,7 @@ __device__ __forceinline__ constexpr int out_q(int slot) {
 }
 
 // ---------------------------------------------------------------------------
-// In-register DFTs of size 2, 4, 8, 16 (natural order in and out).
+// In-register DFTs of size 2, 3, 4, 5, 8, 16 (natural order in and out).
 // ---------------------------------------------------------------------------
 template <typename T, int DIR>
 __device__ __forceinline__ void dft2(cx<T>& a, cx<T>& b) {
@@ -183,11 +220,50 @@ __device__ __forceinline__ void dft16(cx<T>* v) {
   t = v[11]; v[11] = v[14]; v[14] = t;
 }
 
+// DFT of size 3: with w = exp(DIR 2 pi i / 3), X1,2 = x0 - (x1 + x2)/2 +- i DIR (sqrt 3 / 2)(x1 - x2)
+template <typename T, int DIR>
+__device__ __forceinline__ void dft3(cx<T>* v) {
+  constexpr T h3 = T(0.86602540378443864676372317075293618347140262690519);  // sqrt(3)/2
+  const cx<T> s = cadd(v[1], v[2]);
+  const cx<T> d = cscale(mul_dir_i<T, DIR>(csub(v[1], v[2])), h3);
+  const cx<T> a{v[0].x - T(0.5) * s.x, v[0].y - T(0.5) * s.y};
+  v[0] = cadd(v[0], s);
+  v[1] = cadd(a, d);
+  v[2] = csub(a, d);
+}
+
+// DFT of size 5 from the sums and differences of the mirrored inputs:
+// X1,4 = A1 +- i DIR B1, X2,3 = A2 +- i DIR B2 with
+// A1 = x0 + c1 (x1+x4) + c2 (x2+x3), A2 = x0 + c2 (x1+x4) + c1 (x2+x3),
+// B1 = s1 (x1-x4) + s2 (x2-x3),     B2 = s2 (x1-x4) - s1 (x2-x3),
+// c1,2 = cos(2 pi/5), cos(4 pi/5), s1,2 = sin(2 pi/5), sin(4 pi/5).
+template <typename T, int DIR>
+__device__ __forceinline__ void dft5(cx<T>* v) {
+  constexpr T c1 = T(0.30901699437494742410229341718281905886436174199705);
+  constexpr T c2 = T(-0.80901699437494742410229341718281905886436174199705);
+  constexpr T s1 = T(0.95105651629515357211643933337938214340569863412575);
+  constexpr T s2 = T(0.58778525229247312916870595463907276859765243764315);
+  const cx<T> p1 = cadd(v[1], v[4]), m1 = csub(v[1], v[4]);
+  const cx<T> p2 = cadd(v[2], v[3]), m2 = csub(v[2], v[3]);
+  const cx<T> x0 = v[0];
+  const cx<T> a1{x0.x + c1 * p1.x + c2 * p2.x, x0.y + c1 * p1.y + c2 * p2.y};
+  const cx<T> a2{x0.x + c2 * p1.x + c1 * p2.x, x0.y + c2 * p1.y + c1 * p2.y};
+  const cx<T> b1 = mul_dir_i<T, DIR>(cx<T>{s1 * m1.x + s2 * m2.x, s1 * m1.y + s2 * m2.y});
+  const cx<T> b2 = mul_dir_i<T, DIR>(cx<T>{s2 * m1.x - s1 * m2.x, s2 * m1.y - s1 * m2.y});
+  v[0] = cadd(x0, cadd(p1, p2));
+  v[1] = cadd(a1, b1);
+  v[4] = csub(a1, b1);
+  v[2] = cadd(a2, b2);
+  v[3] = csub(a2, b2);
+}
+
 template <typename T, int R, int DIR>
 __device__ __forceinline__ void dft(cx<T>* v) {
   if constexpr (R == 1) {
   } else if constexpr (R == 2) dft2<T, DIR>(v[0], v[1]);
+  else if constexpr (R == 3) dft3<T, DIR>(v);
   else if constexpr (R == 4) dft4<T, DIR>(v[0], v[1], v[2], v[3]);
+  else if constexpr (R == 5) dft5<T, DIR>(v);
   else if constexpr (R == 8) dft8<T, DIR>(v);
   else dft16<T, DIR>(v);
 }
@@ -237,34 +313,33 @@ __device__ __forceinline__ int stage_in_pos(int t, int slot) {
   return t + TPL * b + r * (N / R);
 }
 
+// Exchange through LDS between stage S-1 and stage S, then compute stage S.
+template <typename T, int N, int S, int DIR, class Lds>
+__device__ __forceinline__ void next_stage(cx<T>* v, int t, Lds lds, const cx<T>* __restrict__ tw, int tws) {
+  constexpr int P = plan_p(N);
+  __syncthreads();
+#pragma unroll
+  for (int s = 0; s < P; ++s) lds(stage_out_pos<N, S - 1>(t, s)) = v[s];
+  __syncthreads();
+#pragma unroll
+  for (int s = 0; s < P; ++s) v[s] = lds(stage_in_pos<N, S>(t, s));
+  stage_compute<T, N, S, DIR>(v, t, tw, tws);
+}
+
 // Full line FFT on registers, exchanging through LDS between stages.
 // Lds is an accessor with operator()(pos) -> cx<T>& for this thread's line.
-// Starts with the input pattern (slot q <-> position t + TPL q) and ends with
-// the output pattern (slot s <-> position t + TPL out_q(s)).  Contains block
-// barriers when there is more than one stage: every thread of the block must
-// call it the same number of times.
+// Starts with the input pattern (slot in_slot(q) <-> position t + TPL q) and
+// ends with the output pattern (slot s <-> position t + TPL out_q(s)).
+// Contains block barriers when there is more than one stage: every thread of
+// the block must call it the same number of times.
 template <typename T, int N, int DIR, class Lds>
 __device__ __forceinline__ void line_fft(cx<T>* v, int t, Lds lds, const cx<T>* __restrict__ tw, int tws) {
-  constexpr int P = plan_p(N), NST = plan_stages(N);
+  constexpr int NST = plan_stages(N);
+  static_assert(plan_ok(N), "no FFT plan for this length");
   stage_compute<T, N, 0, DIR>(v, t, tw, tws);
-  if constexpr (NST > 1) {
-    __syncthreads();
-#pragma unroll
-    for (int s = 0; s < P; ++s) lds(stage_out_pos<N, 0>(t, s)) = v[s];
-    __syncthreads();
-#pragma unroll
-    for (int s = 0; s < P; ++s) v[s] = lds(stage_in_pos<N, 1>(t, s));
-    stage_compute<T, N, 1, DIR>(v, t, tw, tws);
-  }
-  if constexpr (NST > 2) {
-    __syncthreads();
-#pragma unroll
-    for (int s = 0; s < P; ++s) lds(stage_out_pos<N, 1>(t, s)) = v[s];
-    __syncthreads();
-#pragma unroll
-    for (int s = 0; s < P; ++s) v[s] = lds(stage_in_pos<N, 2>(t, s));
-    stage_compute<T, N, 2, DIR>(v, t, tw, tws);
-  }
+  if constexpr (NST > 1) next_stage<T, N, 1, DIR>(v, t, lds, tw, tws);
+  if constexpr (NST > 2) next_stage<T, N, 2, DIR>(v, t, lds, tw, tws);
+  if constexpr (NST > 3) next_stage<T, N, 3, DIR>(v, t, lds, tw, tws);
 }
 
 }  // namespace llg

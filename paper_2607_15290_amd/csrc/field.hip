@@ -82,14 +82,10 @@ static hipError_t field_nh(const Ctx& c, const FieldArgs& fa, int epi, const Nod
 hipError_t run_field(const Ctx& c, const FieldArgs& fa, int epi, const NodalArgs& na,
                      const PipeIO<double, double, double>& io, hipStream_t st) {
   switch (c.geom.nh) {
-    case 2: return field_nh<2>(c, fa, epi, na, io, st);
-    case 4: return field_nh<4>(c, fa, epi, na, io, st);
-    case 8: return field_nh<8>(c, fa, epi, na, io, st);
-    case 16: return field_nh<16>(c, fa, epi, na, io, st);
-    case 32: return field_nh<32>(c, fa, epi, na, io, st);
-    case 64: return field_nh<64>(c, fa, epi, na, io, st);
-    case 128: return field_nh<128>(c, fa, epi, na, io, st);
-    case 256: return field_nh<256>(c, fa, epi, na, io, st);
+#define LLG_CASE(n) \
+  case n: return field_nh<n>(c, fa, epi, na, io, st);
+    LLG_FOR_NH(LLG_CASE)
+#undef LLG_CASE
     default: return hipErrorInvalidValue;
   }
 }

@@ -51,7 +51,7 @@ struct ProfScope {
 struct Ctx {
   Profiler* prof = nullptr;
   int nx = 0, ny = 0, nz = 0, dim = 0, device = 0;
-  double h = 0, Lx = 0, Ly = 0, Lz = 0;
+  double Lx = 0, Ly = 0, Lz = 0;  // cell lengths (spacing L / n per axis)
   long long ng = 0;
   SpecGeom geom{};
   cx<double>* tw_d[3] = {nullptr, nullptr, nullptr};  // exp(-2 pi i m / n_axis)

@@ -25,6 +25,22 @@
 
 namespace llg {
 
+// Line lengths with kernel instantiations: half-lengths nx/2 of the x passes
+// and lengths of the y / z passes (plans in fft_core.h).
+#define LLG_FOR_NH(X) \
+  X(2) X(3) X(4) X(5) X(6) X(8) X(10) X(12) X(16) X(20) X(24) X(32) X(40) X(48) X(64) X(80) X(96) X(128) \
+  X(160) X(192) X(256)
+#define LLG_FOR_AXIS(X) \
+  X(4) X(6) X(8) X(10) X(12) X(16) X(20) X(24) X(32) X(40) X(48) X(64) X(80) X(96) X(128) X(160) X(192) \
+  X(256) X(320) X(384) X(512)
+
+inline bool nh_supported(int n) {
+#define LLG_EQ(v) || n == v
+  return false LLG_FOR_NH(LLG_EQ);
+}
+inline bool axis_supported(int n) { return false LLG_FOR_AXIS(LLG_EQ); }
+#undef LLG_EQ
+
 struct SpecGeom {
   int nx, ny, nz, nh;  // nh = nx / 2
   int cs;              // 3 (nh + 1) valid columns per row

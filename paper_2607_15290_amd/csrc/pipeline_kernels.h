@@ -359,7 +359,7 @@ __global__ __launch_bounds__(192) void k_xfwd(const TIn* __restrict__ in, const 
   auto acc = [line_lds](int pos) -> cx<T>& { return line_lds[xphys(pos)]; };
   cx<T> v[C::P];
 #pragma unroll
-  for (int q = 0; q < C::P; ++q) v[q] = acc(t + C::TPL * q);
+  for (int q = 0; q < C::P; ++q) v[in_slot<NH>(q)] = acc(t + C::TPL * q);
   line_fft<T, NH, -1>(v, t, acc, twx, 2);
   __syncthreads();
 #pragma unroll
@@ -429,7 +429,7 @@ __global__ __launch_bounds__(192) void k_xinv(PipeIO<T, TIn, TOut> io, const cx<
     const cx<T> e{a.x + bc.x, a.y - bc.y};
     const cx<T> d{a.x - bc.x, a.y + bc.y};
     const cx<T> o = cmulc(d, twx[k]);
-    v[q] = {e.x - o.y, e.y + o.x};
+    v[in_slot<NH>(q)] = {e.x - o.y, e.y + o.x};
   }
   line_fft<T, NH, 1>(v, t, acc, twx, 2);
   __syncthreads();
@@ -510,7 +510,10 @@ __global__ __launch_bounds__(192) void k_xinv(PipeIO<T, TIn, TOut> io, const cx<
 // k_axis: DFTs along y (axis 1) or z (axis 2).  MODE 0 forward, 1 inverse,
 // 2 forward -> multiplier -> inverse.
 // ---------------------------------------------------------------------------
-__host__ __device__ constexpr int axis_w(int n) { return n <= 16 ? 64 : (n >= 512 ? 4 : 16); }
+// spectral columns per axis block; mixed-radix lengths up to 24 run one thread per line
+__host__ __device__ constexpr int axis_w(int n) {
+  return n <= 16 ? 64 : (n >= 512 ? 4 : ((n & (n - 1)) != 0 && n <= 24 ? 64 : 16));
+}
 
 template <typename T, int N, int MODE>
 __global__ __launch_bounds__(axis_w(N) * (N / plan_p(N))) void k_axis(cx<T>* __restrict__ spec, SpecGeom g,
@@ -533,7 +536,7 @@ __global__ __launch_bounds__(axis_w(N) * (N / plan_p(N))) void k_axis(cx<T>* __r
   cx<T>* base = spec + outer * so + (valid ? col : 0);
   cx<T> v[P];
 #pragma unroll
-  for (int q = 0; q < P; ++q) v[q] = base[(t + TPL * q) * sp];
+  for (int q = 0; q < P; ++q) v[in_slot<N>(q)] = base[(t + TPL * q) * sp];
   if (!valid) {
 #pragma unroll
     for (int q = 0; q < P; ++q) v[q] = cx<T>{T(0), T(0)};
@@ -565,7 +568,7 @@ __global__ __launch_bounds__(axis_w(N) * (N / plan_p(N))) void k_axis(cx<T>* __r
       const double lam2 = base2 + aa * aa;
       double mult = sym.a + sym.b * lam2;
       mult = sym.invert ? sym.inv_ng / mult : sym.inv_ng * mult;
-      w[q] = cscale(v[s], T(mult));
+      w[in_slot<N>(q)] = cscale(v[s], T(mult));
     }
     line_fft<T, N, 1>(w, t, acc, tw, 1);
 #pragma unroll

@@ -98,14 +98,10 @@ template <typename T, typename TIn, typename TOut>
 hipError_t run_pipeline(const Ctx& c, int pro, int epi, const SymArgs& sym, const NodalArgs& na,
                         const PipeIO<T, TIn, TOut>& io, hipStream_t st) {
   switch (c.geom.nh) {
-    case 2: return run_nh<T, TIn, TOut, 2>(c, pro, epi, sym, na, io, st);
-    case 4: return run_nh<T, TIn, TOut, 4>(c, pro, epi, sym, na, io, st);
-    case 8: return run_nh<T, TIn, TOut, 8>(c, pro, epi, sym, na, io, st);
-    case 16: return run_nh<T, TIn, TOut, 16>(c, pro, epi, sym, na, io, st);
-    case 32: return run_nh<T, TIn, TOut, 32>(c, pro, epi, sym, na, io, st);
-    case 64: return run_nh<T, TIn, TOut, 64>(c, pro, epi, sym, na, io, st);
-    case 128: return run_nh<T, TIn, TOut, 128>(c, pro, epi, sym, na, io, st);
-    case 256: return run_nh<T, TIn, TOut, 256>(c, pro, epi, sym, na, io, st);
+#define LLG_CASE(n) \
+  case n: return run_nh<T, TIn, TOut, n>(c, pro, epi, sym, na, io, st);
+    LLG_FOR_NH(LLG_CASE)
+#undef LLG_CASE
     default: return hipErrorInvalidValue;
   }
 }

@@ -85,18 +85,29 @@ def _stats_dict(s):
 
 
 class Context:
-    """An llg_ctx: grid nx x ny x nz (nz = 1 for 2-D), spacing h, one GPU."""
+    """An llg_ctx: grid nx x ny x nz (nz = 1 for 2-D) on one GPU, with either
+    one spacing h (cell lengths n h) or explicit cell lengths
+    lengths = (lx, ly, lz) (llg_ctx_create_cell)."""
 
-    def __init__(self, nx, ny, nz=1, h=None, device=0):
+    def __init__(self, nx, ny, nz=1, h=None, device=0, lengths=None):
         self.lib = L.load()
         self.nx, self.ny, self.nz = int(nx), int(ny), int(nz)
-        self.h = float(1.0 / nx if h is None else h)
         self.device = torch.device("cuda", int(device))
         self.ng = self.nx * self.ny * self.nz
+        if lengths is None:
+            self.h = float(1.0 / nx if h is None else h)
+            self.lengths = (self.nx * self.h, self.ny * self.h, self.nz * self.h)
+        else:
+            self.lengths = tuple(float(v) for v in lengths)
+            self.h = None
         handle = ctypes.c_void_p()
         with torch.cuda.device(self.device):
-            _check(self.lib.llg_ctx_create(ctypes.byref(handle), self.nx, self.ny, self.nz, self.h, int(device)),
-                   "llg_ctx_create")
+            if lengths is None:
+                s = self.lib.llg_ctx_create(ctypes.byref(handle), self.nx, self.ny, self.nz, self.h, int(device))
+            else:
+                s = self.lib.llg_ctx_create_cell(ctypes.byref(handle), self.nx, self.ny, self.nz, *self.lengths,
+                                                 int(device))
+            _check(s, "llg_ctx_create")
         self.handle = handle
         self._work = {}
 

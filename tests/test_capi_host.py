@@ -42,12 +42,17 @@ def test_binding_signatures_cover_header():
 
 def test_ctx_create_rejects_bad_sizes(lib):
     h = ctypes.c_void_p()
-    for nx, ny, nz, hh in [(3, 4, 1, 0.1), (4, 6, 1, 0.1), (1024, 4, 1, 0.1), (4, 4, 2, 0.1), (4, 4, 1, 0.0),
-                           (4, 4, 1, -1.0), (8, 8, 3, 0.1), (0, 8, 1, 0.1)]:
-        assert lib.llg_ctx_create(ctypes.byref(h), nx, ny, nz, hh, 0) == 1
+    # odd nx, factors other than 2, 3, 5, a 7 or 9 factor, sizes out of range, bad h
+    for nx, ny, nz, hh in [(3, 4, 1, 0.1), (4, 14, 1, 0.1), (1024, 4, 1, 0.1), (4, 4, 2, 0.1), (4, 4, 1, 0.0),
+                           (4, 4, 1, -1.0), (8, 8, 3, 0.1), (0, 8, 1, 0.1), (18, 8, 1, 0.1), (8, 8, 36, 0.1),
+                           (768, 8, 1, 0.1), (8, 640, 1, 0.1), (24, 2, 1, 0.1), (8, 8, 1, float("nan"))]:
+        assert lib.llg_ctx_create(ctypes.byref(h), nx, ny, nz, hh, 0) == 1, (nx, ny, nz, hh)
         assert h.value is None
         assert len(lib.llg_last_error()) > 0
     assert lib.llg_ctx_create(None, 8, 8, 1, 0.1, 0) == 1
+    for lens in [(0.0, 1.0, 1.0), (1.0, -1.0, 1.0), (1.0, 1.0, 0.0), (1.0, float("inf"), 1.0)]:
+        assert lib.llg_ctx_create_cell(ctypes.byref(h), 8, 8, 1, *lens, 0) == 1
+        assert h.value is None
 
 
 def test_entry_points_reject_null_context(lib):

@@ -121,7 +121,7 @@ def test_adjoint_with_lower_order_field_matches_oracle():
     ctx.close()
 
 
-@pytest.mark.parametrize("n", [16, 32])
+@pytest.mark.parametrize("n", [16, 24, 32])
 def test_energy_test_3d_matches_paper(n):
     """Sec. 4.6: ten midpoint steps of the 3D periodic problem with exchange,
     demagnetization, anisotropy 0.2 (axis e3) and h_ext = (0.05, 0, 0) on

@@ -103,14 +103,15 @@ def _run_energy_test(n):
     return energies, lens, pics, its, gaps
 
 
-@pytest.mark.parametrize("n", [16, 32])
+@pytest.mark.parametrize("n", [16, 24, 32])
 def test_energy_test_matches_paper(n):
     energies, lens, pics, its, gaps = _run_energy_test(n)
     half_ulp = 0.5 * 10.0 ** -E3["printed_decimals"]
     assert abs(energies[-1] - E3["energy_final"][str(n)]) <= half_ulp
     assert all(b < a for a, b in zip(energies, energies[1:]))
+    # printed to three significant digits: 1.68e-10 (N = 24) .. 1.87e-10
     lo, hi = E3["len_err_range"]
-    assert lo <= max(lens) <= hi
+    assert lo - 0.005e-10 <= max(lens) <= hi + 0.005e-10
     assert pics == [E3["picard_per_step"]] * len(pics)
     # GMRES iterations per solve: printed 7.84..8.88 over N = 16, 24, 32
     lo, hi = E3["gmres_per_solve_range"]
