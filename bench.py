@@ -13,7 +13,9 @@ GMRES(30).  During the headline timed region the library brackets each kernel
 with HIP events (llg_profile_enable) to give the roofline of the dominant
 kernel.  Also reported: the paper's protocol (median of 3 solves after one
 warm-up on the first Picard system), standalone fft_hss_apply / llg_matvec
-bandwidth, and the FP64 CPU oracle timed on a bounded sample.
+bandwidth, the preconditioner comparison of the paper (split FFT-HSS,
+symmetric part, none) on its largest grids, and the FP64 CPU oracle timed on
+a bounded sample.
 
 Prints one JSON line on stdout; progress goes to stderr.
 """
@@ -48,6 +50,7 @@ def parse():
     ap.add_argument("--no-cpu-baseline", action="store_true")
     ap.add_argument("--no-fp64", action="store_true", help="skip the plain FP64 comparison run")
     ap.add_argument("--inner-rtol", type=float, default=1e-5)
+    ap.add_argument("--no-comparison", action="store_true", help="skip the preconditioner comparison")
     ap.add_argument("--op-reps", type=int, default=20)
     ap.add_argument("--copy-calibration", action="store_true",
                     help="only run a plain 1 GiB device copy 5 times (counter calibration) and exit")
@@ -162,6 +165,45 @@ def measured_traffic(kernel_kind, bytes_per_launch):
     return None
 
 
+def precond_comparison(P, torch, W):
+    """Sec. 4.3 on the GPU: one Euler system (k = 1e-2, alpha = 0.2, lambda =
+    0.5, smooth manufactured right-hand side, GMRES(50), rtol 1e-8) on the
+    largest grids of the paper's comparison, 256^2 and 48^3, solved with the
+    split FFT-HSS preconditioner, the symmetric part alone and no
+    preconditioner; median of 3 solves after one warm-up.  The paper's CPU
+    timings of the same systems are quoted beside the GPU's."""
+    out = {}
+    alpha, k = 0.2, 1e-2
+    paper = {"2d_256": (0.236, 15.45), "3d_48": (0.684, 3.20)}
+    for key, dim, n in (("2d_256", 2, 256), ("3d_48", 3, 48)):
+        nz = 1 if dim == 2 else n
+        m, _ = W.manufactured(n, dim, 0.0, alpha)
+        _, F = W.manufactured(n, dim, k, alpha)
+        ctx = P.Context(n, n, nz, 2 * np.pi / n, 0)
+        md = torch.from_numpy(np.ascontiguousarray(m)).to("cuda:0")
+        hf = torch.from_numpy(np.ascontiguousarray(F / (1 + alpha ** 2))).to("cuda:0")
+        prm_b = P.Params(alpha=alpha, cexc=1.0, dt=k, theta=1.0, shift=0.5, h_field=hf)
+        b = P.llg_rhs(ctx, prm_b, md)
+        prm = P.Params(alpha=alpha, cexc=1.0, dt=k, theta=1.0, shift=0.5)
+        res = {}
+        for pc in ("fft_hss", "symmetric", "none"):
+            _, st = P.gmres_solve(ctx, prm, md, b, restart=50, rtol=1e-8, orth="cgs2", precond=pc)
+            times = []
+            for _ in range(3):
+                torch.cuda.synchronize()
+                t0 = time.perf_counter()
+                _, st = P.gmres_solve(ctx, prm, md, b, restart=50, rtol=1e-8, orth="cgs2", precond=pc)
+                torch.cuda.synchronize()
+                times.append(time.perf_counter() - t0)
+            res[pc] = dict(iters=st["iters"], median_ms=round(1e3 * statistics.median(times), 3),
+                           rel_res_true=st["rel_res_true"])
+        res["speedup_split_vs_none"] = round(res["none"]["median_ms"] / res["fft_hss"]["median_ms"], 2)
+        res["paper_cpu_split_s"], res["paper_speedup_split_vs_none"] = paper[key]
+        out[key] = res
+        ctx.close()
+    return out
+
+
 def cpu_baseline(spec, m0_np, gpu_iters_per_solve):
     """FP64 oracle on the host, bounded sample: one application of the
     preconditioned operator M^{-1} A (one matvec and one FFT-HSS apply, the
@@ -233,6 +275,10 @@ def main():
         res["fp64"] = dict(solves_per_s=solves64 / t64, steps_per_s=args.steps / t64, ms_per_step=1e3 * t64 / args.steps,
                            solves=solves64,
                            gmres_iters=lin64, iters_per_solve=lin64 / solves64)
+    comparison = None
+    if not args.no_comparison:
+        log("preconditioner comparison (256^2 and 48^3)")
+        comparison = precond_comparison(P, torch, W)
     log("paper protocol (median of 3 after 1 warm-up)")
     pp32 = paper_protocol(P, ctx, prm, m0_dev, spec, "fp32_ir", args.inner_rtol, args.orth)
     pp64 = (paper_protocol(P, ctx, prm, m0_dev, spec, "fp64", args.inner_rtol, args.orth)
@@ -280,6 +326,7 @@ def main():
         "fp64": res.get("fp64"),
         "fp32_ir_over_fp64": (value / res["fp64"]["solves_per_s"]) if "fp64" in res else None,
         "paper_protocol": {"fp32_ir": pp32, "fp64": pp64},
+        "precond_comparison": comparison,
         "ops": ops,
         "roofline": roofline,
         "kernels": kernels,

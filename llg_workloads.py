@@ -188,3 +188,37 @@ def gaussian_rhs(n, seed, dim=2):
     b = np.zeros((4,) + shape)
     b[:3] = f / np.linalg.norm(f)
     return b
+
+
+def manufactured(n, dim, t, alpha, cexc=1.0):
+    """Problem data of the manufactured-solution runs (temporal convergence
+    and preconditioner comparison) on (0, 2 pi)^dim with n nodes per axis:
+    the unit field m_e(x, t) and its source term F (entering as the applied
+    field F / (1 + alpha^2)), sampled at the nodes, shapes (3, nz, ny, nx).
+
+    2D: a = t + x, b = t + y; 3D: a = t + x + z, b = t + y + z;
+    m_e = (sin a cos b, cos a cos b, sin b),
+    F = alpha d_t m_e + m_e x d_t m_e - (1 + alpha^2) cexc Delta m_e."""
+    ax = 2.0 * np.pi * np.arange(n) / n
+    if dim == 2:
+        yy, xx = np.meshgrid(ax, ax, indexing="ij")
+        a, b = (t + xx)[None], (t + yy)[None]
+    else:
+        zz, yy, xx = np.meshgrid(ax, ax, ax, indexing="ij")
+        a, b = t + xx + zz, t + yy + zz
+    sa, ca, sb, cb = np.sin(a), np.cos(a), np.sin(b), np.cos(b)
+    zero = np.zeros_like(a)
+    m = np.stack([sa * cb, ca * cb, sb])
+    m_a = np.stack([ca * cb, -sa * cb, zero])
+    m_b = np.stack([-sa * sb, -ca * sb, cb])
+    m_aa = np.stack([-sa * cb, -ca * cb, zero])
+    m_ab = np.stack([-ca * sb, sa * sb, zero])
+    m_bb = -m
+    if dim == 2:
+        dt_m, lap = m_a + m_b, m_aa + m_bb
+    else:
+        dt_m, lap = m_a + m_b, 2.0 * (m_aa + m_bb + m_ab)
+    cr = np.stack([m[1] * dt_m[2] - m[2] * dt_m[1], m[2] * dt_m[0] - m[0] * dt_m[2],
+                   m[0] * dt_m[1] - m[1] * dt_m[0]])
+    F = alpha * dt_m + cr - (1.0 + alpha ** 2) * cexc * lap
+    return m, F

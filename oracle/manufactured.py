@@ -13,6 +13,16 @@ Reading: the forcing that reproduces the printed errors of Sec. 4.2 to every
 printed digit is the unprojected one, F = alpha d_t m_e + m_e x d_t m_e -
 (1+alpha^2) cexc Delta m_e (``project=False``, the default); the projected
 variant keeps the orders but changes the error constants.
+
+Three dimensions (reading; the paper names no 3D field for its 3D
+preconditioner comparison, Sec. 4.3): on (0, 2 pi)^3 the same family with
+a = t + x + z, b = t + y + z, i.e. m_e = (sin a cos b, cos a cos b, sin b),
+whose t = 0 value is the initial field of the 3D energy test (Sec. 4.6).
+With it the comparison counts printed for N = 16..48 are reproduced exactly.
+With u_a, u_b the partial derivatives in a and b:
+    d_t m = m_a + m_b,  Delta m = 2 m_aa + 2 m_bb + 2 m_ab,
+    m_a = (cos a cos b, -sin a cos b, 0),  m_b = (-sin a sin b, -cos a sin b, cos b),
+    m_aa = -(m_1, m_2, 0),  m_bb = -m,  m_ab = (-cos a sin b, sin a sin b, 0).
 """
 
 import numpy as np
@@ -46,10 +56,46 @@ def forcing(x, y, t, alpha, cexc=1.0, project=False):
     return alpha * mt + nodal.cross(m, mt) - (1.0 + alpha ** 2) * cexc * lap
 
 
+def _ab3(x, y, z, t):
+    return t + x + z, t + y + z
+
+
+def m_exact_3d(x, y, z, t):
+    a, b = _ab3(x, y, z, t)
+    return np.stack([np.sin(a) * np.cos(b), np.cos(a) * np.cos(b), np.sin(b)])
+
+
+def dt_m_exact_3d(x, y, z, t):
+    a, b = _ab3(x, y, z, t)
+    ma = np.stack([np.cos(a) * np.cos(b), -np.sin(a) * np.cos(b), np.zeros_like(a)])
+    mb = np.stack([-np.sin(a) * np.sin(b), -np.cos(a) * np.sin(b), np.cos(b)])
+    return ma + mb
+
+
+def lap_m_exact_3d(x, y, z, t):
+    a, b = _ab3(x, y, z, t)
+    m = m_exact_3d(x, y, z, t)
+    maa = np.stack([-m[0], -m[1], np.zeros_like(a)])
+    mab = np.stack([-np.cos(a) * np.sin(b), np.sin(a) * np.sin(b), np.zeros_like(a)])
+    return 2.0 * maa - 2.0 * m + 2.0 * mab
+
+
+def forcing_3d(x, y, z, t, alpha, cexc=1.0, project=False):
+    m = m_exact_3d(x, y, z, t)
+    mt = dt_m_exact_3d(x, y, z, t)
+    lap = lap_m_exact_3d(x, y, z, t)
+    if project:
+        lap = lap - nodal.dot(m, lap) * m
+    return alpha * mt + nodal.cross(m, mt) - (1.0 + alpha ** 2) * cexc * lap
+
+
 def grid_fields(g, t, alpha, cexc=1.0, project=False):
-    """(m_e, F) sampled on a 2D grid (nz = 1), shaped (3, 1, ny, nx)."""
-    _, yy, xx = g.coords()
-    return (m_exact(xx, yy, t), forcing(xx, yy, t, alpha, cexc, project))
+    """(m_e, F) sampled on the grid, shaped (3, nz, ny, nx): the 2D field when
+    nz = 1, the 3D family otherwise."""
+    zz, yy, xx = g.coords()
+    if g.dim == 2:
+        return (m_exact(xx, yy, t), forcing(xx, yy, t, alpha, cexc, project))
+    return (m_exact_3d(xx, yy, zz, t), forcing_3d(xx, yy, zz, t, alpha, cexc, project))
 
 
 def run(g, alpha, dt, t_end, scheme, shift=0.5, restart=50, rtol=1e-10, picard_tol=1e-10,

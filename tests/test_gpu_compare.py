@@ -135,3 +135,42 @@ def test_random_rhs_mesh_study(regime, n):
         else:
             assert abs(med - gold["fixed_k"]["256"]) <= tol * gold["fixed_k"]["256"]
     ctx.close()
+
+
+@pytest.mark.parametrize("n", [16, 24, 32, 48])
+def test_comparison_counts_3d(n):
+    """Sec. 4.3 in 3D on (0, 2 pi)^3 (3D manufactured family): split 13,
+    symmetric part 26 on every grid; unpreconditioned 24 at N = 16 and 58 at
+    N = 48 as printed, and the oracle's count in between."""
+    gold = GOLD["smooth_rhs_iterations"]
+    announce(f"preconditioner comparison 3D N={n}")
+    h = 2 * math.pi / n
+    g = Grid(n, n, n, h=h)
+    kw = dict(alpha=0.2, cexc=1.0, dt=1e-2, theta=1.0, shift=0.5)
+    op = OP(**kw)
+    m, _ = manufactured.grid_fields(g, 0.0, op.alpha)
+    _, F = manufactured.grid_fields(g, op.dt, op.alpha)
+    b = steppers.rhs(g, op, m, forcing=F)
+    ctx = P.Context(n, n, n, h, 0)
+    prm = P.Params(**kw)
+    md, bd = dev(m), dev(b)
+    if str(n) in gold["unpreconditioned_3d"]:
+        none_count = gold["unpreconditioned_3d"][str(n)]
+    else:
+        _, info = gmres.gmres(lambda x: operators.matvec(g, op, m, x), lambda x: x, b, restart=50, rtol=1e-8)
+        none_count = info["iters"]
+    expect = {"fft_hss": gold["split_3d"], "symmetric": gold["symmetric_3d"], "none": none_count}
+    times = {}
+    for pc, count in expect.items():
+        x, st = P.gmres_solve(ctx, prm, md, bd, restart=50, rtol=1e-8, orth="cgs2", precond=pc)
+        assert st["converged"] == 1
+        assert st["iters"] == count, (pc, st["iters"])
+        torch.cuda.synchronize()
+        t0 = time.perf_counter()
+        for _ in range(3):
+            P.gmres_solve(ctx, prm, md, bd, restart=50, rtol=1e-8, orth="cgs2", precond=pc)
+        torch.cuda.synchronize()
+        times[pc] = (time.perf_counter() - t0) / 3
+    announce(f"3D N={n} solve ms: " + ", ".join(f"{k} {1e3 * v:.2f}" for k, v in times.items()) +
+             f"; none/split = {times['none'] / times['fft_hss']:.2f}")
+    ctx.close()

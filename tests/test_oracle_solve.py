@@ -14,7 +14,7 @@ import numpy as np
 import llg_workloads
 import pytest
 
-from oracle import dense, gmres, manufactured, nodal, operators, steppers, theory
+from oracle import dense, fourier, gmres, manufactured, nodal, operators, steppers, theory
 from oracle.grid import Grid
 from oracle.operators import Params
 
@@ -114,6 +114,45 @@ def test_smooth_rhs_iteration_counts_match_paper(n):
     assert counts["split"] == gold["split_2d"]
     assert counts["symmetric"] == gold["symmetric_2d"]
     assert counts["none"] == gold["unpreconditioned_2d"][str(n)]
+
+
+def test_smooth_rhs_iteration_counts_3d_match_paper():
+    """Sec. 4.3 in 3D on (0, 2 pi)^3 with the 3D manufactured family
+    (oracle.manufactured): split 13, symmetric part 26 and, at N = 16,
+    unpreconditioned 24 iterations, as printed."""
+    gold = GOLD["smooth_rhs_iterations"]
+    for n in (16, 24):
+        g = Grid(n, n, n, lengths=(2 * np.pi,) * 3)
+        prm = Params(alpha=0.2, dt=1e-2, theta=1.0, shift=0.5)
+        m, _ = manufactured.grid_fields(g, 0.0, prm.alpha)
+        _, F = manufactured.grid_fields(g, prm.dt, prm.alpha)
+        b = steppers.rhs(g, prm, m, forcing=F)
+        A = lambda x: operators.matvec(g, prm, m, x)
+        counts = {}
+        for name, M in [("split", lambda x: operators.hss_apply(g, prm, m, x)),
+                        ("symmetric", lambda x: operators.symmetric_apply(g, prm, x)),
+                        ("none", lambda x: x)]:
+            x, info = gmres.gmres(A, M, b, restart=50, rtol=1e-8, maxiter=3000)
+            assert info["converged"]
+            counts[name] = info["iters"]
+        assert counts["split"] == gold["split_3d"]
+        assert counts["symmetric"] == gold["symmetric_3d"]
+        if n == 16:
+            assert counts["none"] == gold["unpreconditioned_3d"]["16"]
+
+
+def test_manufactured_3d_derivatives():
+    """The analytic d_t m and Delta m of the 3D manufactured family against a
+    central difference in t and the spectral Laplacian (exact for these modes)."""
+    g = Grid(12, 12, 12, lengths=(2 * np.pi,) * 3)
+    zz, yy, xx = g.coords()
+    t, e = 0.3, 1e-6
+    m = manufactured.m_exact_3d(xx, yy, zz, t)
+    np.testing.assert_allclose(nodal.dot(m, m), 1.0, atol=1e-15)
+    fd = (manufactured.m_exact_3d(xx, yy, zz, t + e) - manufactured.m_exact_3d(xx, yy, zz, t - e)) / (2 * e)
+    np.testing.assert_allclose(manufactured.dt_m_exact_3d(xx, yy, zz, t), fd, atol=1e-8)
+    np.testing.assert_allclose(manufactured.lap_m_exact_3d(xx, yy, zz, t), -fourier.neg_laplacian(g, m),
+                               atol=1e-13)
 
 
 def _split_count(g, prm, m, b):
