@@ -13,7 +13,9 @@ GMRES(30).  During the headline timed region the library brackets each kernel
 with HIP events (llg_profile_enable) to give the roofline of the dominant
 kernel.  Also reported: the paper's protocol (median of 3 solves after one
 warm-up on the first Picard system), standalone fft_hss_apply / llg_matvec
-bandwidth, the preconditioner comparison of the paper (split FFT-HSS,
+bandwidth, a labelled variant of the precision form (left-preconditioned
+inner GMRES on the fused float32 M^{-1} A), the preconditioner comparison of
+the paper (split FFT-HSS,
 symmetric part, none) on its largest grids, and the FP64 CPU oracle timed on
 a bounded sample.
 
@@ -51,6 +53,8 @@ def parse():
     ap.add_argument("--no-fp64", action="store_true", help="skip the plain FP64 comparison run")
     ap.add_argument("--inner-rtol", type=float, default=1e-5)
     ap.add_argument("--no-comparison", action="store_true", help="skip the preconditioner comparison")
+    ap.add_argument("--no-variant", action="store_true",
+                    help="skip the left-preconditioned FP32-IR variant run")
     ap.add_argument("--op-reps", type=int, default=20)
     ap.add_argument("--copy-calibration", action="store_true",
                     help="only run a plain 1 GiB device copy 5 times (counter calibration) and exit")
@@ -275,6 +279,16 @@ def main():
         res["fp64"] = dict(solves_per_s=solves64 / t64, steps_per_s=args.steps / t64, ms_per_step=1e3 * t64 / args.steps,
                            solves=solves64,
                            gmres_iters=lin64, iters_per_solve=lin64 / solves64)
+    if not args.no_variant:
+        log("FP32-IR variant with left-preconditioned inner GMRES (one fused float32 pipeline per iteration)")
+        tl, stl, _, _ = run_steps(P, ctx, prm, m0_dev, spec, "fp32_ir_left", args.warmup, args.steps,
+                                  args.inner_rtol, False, args.orth)
+        solvesl = sum(s["picard_iters"] for s in stl)
+        linl = sum(s["lin_iters_total"] for s in stl)
+        res["fp32_ir_left"] = dict(solves_per_s=solvesl / tl, steps_per_s=args.steps / tl,
+                                   ms_per_step=1e3 * tl / args.steps, solves=solvesl, gmres_iters=linl,
+                                   iters_per_solve=linl / solvesl,
+                                   max_len_err=max(s["max_len_err"] for s in stl))
     comparison = None
     if not args.no_comparison:
         log("preconditioner comparison (256^2 and 48^3)")
@@ -324,6 +338,7 @@ def main():
                         solves=solves32, gmres_iters=lin32, iters_per_solve=lin32 / solves32,
                         max_len_err=max(s["max_len_err"] for s in st32)),
         "fp64": res.get("fp64"),
+        "fp32_ir_left_variant": res.get("fp32_ir_left"),
         "fp32_ir_over_fp64": (value / res["fp64"]["solves_per_s"]) if "fp64" in res else None,
         "paper_protocol": {"fp32_ir": pp32, "fp64": pp64},
         "precond_comparison": comparison,

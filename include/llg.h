@@ -57,9 +57,13 @@ typedef enum {
 } llg_status;
 
 typedef enum {
-  LLG_FP64 = 0,    /* plain float64 left-preconditioned GMRES */
-  LLG_FP32_IR = 1  /* float32 preconditioner and inner matvec inside float64
-                      flexible GMRES with iterative refinement */
+  LLG_FP64 = 0,        /* plain float64 left-preconditioned GMRES */
+  LLG_FP32_IR = 1,     /* float32 preconditioner and inner matvec inside float64
+                          flexible GMRES with iterative refinement */
+  LLG_FP32_IR_LEFT = 2 /* variant: float64 iterative refinement around a
+                          left-preconditioned inner GMRES whose operator
+                          M^{-1} A is one float32 pipeline (the exact fused
+                          identity); float64 Arnoldi, no float32 basis */
 } llg_precision;
 
 typedef struct llg_ctx llg_ctx;
@@ -87,7 +91,7 @@ typedef struct {
 typedef struct {
   int restart;       /* Krylov cycle length (30 by default) */
   int maxiter;       /* total inner iteration limit */
-  int max_outer;     /* refinement steps of LLG_FP32_IR */
+  int max_outer;     /* refinement steps of LLG_FP32_IR(_LEFT) */
   int use_x0;        /* 1: x holds the initial guess on entry, 0: start from 0 */
   double rtol;       /* accept when ||b - A x||_2 <= rtol ||b||_2 */
   double inner_rtol; /* relative tolerance of each inner FGMRES cycle (FP32_IR) */

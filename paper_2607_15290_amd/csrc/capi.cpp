@@ -74,13 +74,14 @@ llg_status check_opts(const llg_solver_opts* o) {
   if (o->restart < 1 || o->restart > kMaxDots - 2) return fail(LLG_EARG, "restart must be in [1, 62]");
   if (o->maxiter < 1) return fail(LLG_EARG, "maxiter must be >= 1");
   if (!is_fin(o->rtol) || o->rtol <= 0 || o->rtol >= 1) return fail(LLG_EARG, "rtol must be in (0, 1)");
-  if (o->prec != LLG_FP64 && o->prec != LLG_FP32_IR) return fail(LLG_EARG, "unknown precision");
+  if (o->prec != LLG_FP64 && o->prec != LLG_FP32_IR && o->prec != LLG_FP32_IR_LEFT)
+    return fail(LLG_EARG, "unknown precision");
   if (o->orth != 0 && o->orth != 1) return fail(LLG_EARG, "orth must be 0 (delayed CGS2) or 1 (CGS2)");
   if (o->precond < 0 || o->precond > 2) return fail(LLG_EARG, "precond must be 0, 1 or 2");
   if (o->precond != 0 && o->prec != LLG_FP64) return fail(LLG_EARG, "comparison preconditioners run in float64");
   if (o->orth == 0 && o->restart > 31) return fail(LLG_EARG, "delayed CGS2 supports restart <= 31");
   if (o->picard_norm != 0 && o->picard_norm != 1) return fail(LLG_EARG, "picard_norm must be 0 or 1");
-  if (o->prec == LLG_FP32_IR) {
+  if (o->prec != LLG_FP64) {
     if (o->max_outer < 1) return fail(LLG_EARG, "max_outer must be >= 1");
     if (!is_fin(o->inner_rtol) || o->inner_rtol <= 0 || o->inner_rtol >= 1)
       return fail(LLG_EARG, "inner_rtol must be in (0, 1)");
@@ -262,10 +263,8 @@ Work carve(const Ctx& c, int R, int prec, void* base) {
   w.V = reinterpret_cast<double*>(take(sizeof(double) * n4 * (R + 2)));
   w.r = reinterpret_cast<double*>(take(sizeof(double) * n4));
   w.t = reinterpret_cast<double*>(take(sizeof(double) * n4));
-  if (prec == LLG_FP32_IR) {
-    w.Z = reinterpret_cast<float*>(take(sizeof(float) * n4 * R));
-    w.m32 = reinterpret_cast<float*>(take(sizeof(float) * n3));
-  }
+  if (prec == LLG_FP32_IR) w.Z = reinterpret_cast<float*>(take(sizeof(float) * n4 * R));
+  if (prec != LLG_FP64) w.m32 = reinterpret_cast<float*>(take(sizeof(float) * n3));
   w.b = reinterpret_cast<double*>(take(sizeof(double) * n4));
   w.x = reinterpret_cast<double*>(take(sizeof(double) * n4));
   w.m0 = reinterpret_cast<double*>(take(sizeof(double) * n3));
@@ -538,7 +537,9 @@ llg_status gmres_left(const Ctx& c, const ResidOp& RA, const Op& M, const Op& MA
 }
 
 // Precision form: FP64 iterative refinement around right-preconditioned
-// flexible GMRES whose preconditioner and matvec run in float32.
+// flexible GMRES whose preconditioner and matvec run in float32 (LLG_FP32_IR),
+// or around left-preconditioned GMRES on the fused float32 M^{-1} A
+// (LLG_FP32_IR_LEFT, one float32 pipeline per inner iteration).
 llg_status gmres_ir(const Ctx& c, const llg_params* p, const double* m, const double* b, double* x,
                     const llg_solver_opts& o, Work& w, SolveResult& res, hipStream_t st) {
   const long long n4 = 4 * c.ng;
@@ -583,6 +584,52 @@ llg_status gmres_ir(const Ctx& c, const llg_params* p, const double* m, const do
     if (res.outer >= o.max_outer || res.iters >= o.maxiter) break;
     res.outer++;
     res.cycles++;
+    const double eta = std::max(o.inner_rtol, target / rho);
+    if (o.prec == LLG_FP32_IR_LEFT) {
+      // inner GMRES on M^{-1} A d = M^{-1} r, both operators in float32 on
+      // float64 Krylov vectors; stop when the preconditioned residual has
+      // fallen by eta; x += Q y in float64
+      double* Q = w.V;
+      double* U = w.V + size_t(R) * n4;
+      double* W = w.V + size_t(R + 1) * n4;
+      PipeIO<float, double, double> io_m{w.r, w.m32, U, c.ng, nullptr, nullptr};
+      CHK((run_pipeline<float, double, double>(c, PRO_COPY3, EPI_APPLY, sym_ap, na, io_m, st)));
+      double un[2];
+      CHK(dot_and_norm(c, U, nullptr, n4, c.scal, st));
+      CHK_STATUS(fetch(c, c.scal, 2, st, un));
+      auto opl = [&](int, const double* u, double* wout) -> hipError_t {
+        PipeIO<float, double, double> io{u, w.m32, wout, c.ng, nullptr, nullptr};
+        return run_pipeline<float, double, double>(c, PRO_SMINUS, EPI_FUSED, sym_ap, na, io, st);
+      };
+      CycleResult cr;
+      if (o.orth == 0) {
+        CHK_STATUS(cycle_dcgs2(c, opl, Q, U, W, n4, un[1], R, eta, o.maxiter, res.iters, false, cr, st));
+      } else {
+        const double beta = std::sqrt(un[1]);
+        if (!is_fin(beta)) return fail(LLG_ENAN, "non-finite preconditioned residual");
+        if (beta == 0.0) break;
+        CHK(scale_invnorm(c, Q, U, c.scal + 1, n4, st));
+        std::fill(hs.g.begin(), hs.g.end(), 0.0);
+        hs.g[0] = beta;
+        cr.beta0 = beta;
+        for (int j = 0; j < R; ++j) {
+          CHK(opl(j, Q + size_t(j) * n4, Q + size_t(j + 1) * n4));
+          CHK_STATUS(arnoldi_step(c, Q, n4, j, col.data(), st));
+          cr.gres = hs.add_column(j, col.data());
+          res.iters++;
+          cr.k = j + 1;
+          if (cr.gres <= eta * beta || res.iters >= o.maxiter || col[j + 1] == 0.0) break;
+        }
+        hs.solve(cr.k, cr.y);
+      }
+      res.rel_prec = cr.beta0 > 0 ? cr.gres / cr.beta0 : 0.0;
+      if (cr.k == 0) break;
+      CHK(lincomb(c, n4, cr.y, Q, n4, x, st));
+      CHK(RA(x, b, w.r));
+      CHK_STATUS(fetch(c, c.scal, 1, st, rn));
+      rho = std::sqrt(rn[0]);
+      continue;
+    }
     if (o.orth == 0) {
       double* Q = w.V;
       double* W = w.V + size_t(R + 1) * n4;
@@ -596,8 +643,7 @@ llg_status gmres_ir(const Ctx& c, const llg_params* p, const double* m, const do
       };
       CycleResult cr;
       // u_0 = r (the residual buffer is consumed as the cycle's start vector)
-      CHK_STATUS(cycle_dcgs2(c, op, Q, w.r, W, n4, rho * rho, R, std::max(o.inner_rtol, target / rho), o.maxiter,
-                             res.iters, true, cr, st));
+      CHK_STATUS(cycle_dcgs2(c, op, Q, w.r, W, n4, rho * rho, R, eta, o.maxiter, res.iters, true, cr, st));
       res.rel_prec = cr.gres / bnorm;
       if (cr.k == 0) break;
       CHK(lincomb(c, n4, cr.y, w.Z, n4, x, st));
@@ -607,7 +653,6 @@ llg_status gmres_ir(const Ctx& c, const llg_params* p, const double* m, const do
       continue;
     }
     CHK(axpby(c, n4, 1.0 / rho, w.r, 0.0, w.r, w.V, st));
-    const double eta = std::max(o.inner_rtol, target / rho);
     std::fill(hs.g.begin(), hs.g.end(), 0.0);
     hs.g[0] = rho;
     int k = 0;
@@ -647,7 +692,7 @@ llg_status check_m(const Ctx& c, const double* m, hipStream_t st) {
 llg_status solve(const Ctx& c, const llg_params* p, const double* m, const double* b, double* x,
                  const llg_solver_opts& o, Work& w, SolveResult& res, hipStream_t st) {
   CHK_STATUS(check_m(c, m, st));
-  if (o.prec == LLG_FP32_IR) return gmres_ir(c, p, m, b, x, o, w, res, st);
+  if (o.prec != LLG_FP64) return gmres_ir(c, p, m, b, x, o, w, res, st);
   const ResidOp RA = resid_op(c, EPI_MATVEC, sym_for(c, p->alpha, hcoef(p), false), nodal_for(p), m, st);
   if (o.precond == 1) {  // symmetric part (lambda I + calH)^{-1}
     const SymArgs sa = sym_for(c, p->alpha + p->shift, hcoef(p), true);
@@ -805,7 +850,9 @@ llg_status llg_ctx_destroy(llg_ctx* ctx) {
 }
 
 size_t llg_workspace_bytes(const llg_ctx* ctx, int restart, int prec) {
-  if (!ctx || restart < 1 || restart > kMaxDots - 2 || (prec != LLG_FP64 && prec != LLG_FP32_IR)) return 0;
+  if (!ctx || restart < 1 || restart > kMaxDots - 2 ||
+      (prec != LLG_FP64 && prec != LLG_FP32_IR && prec != LLG_FP32_IR_LEFT))
+    return 0;
   return carve(ctx->c, restart, prec, nullptr).bytes;
 }
 

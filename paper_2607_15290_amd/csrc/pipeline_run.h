@@ -9,15 +9,20 @@ namespace llg {
 
 // Which (prologue, epilogue) modes exist for a type combination.  The mixed
 // combinations serve only the precision form: float32 apply reading float64
-// Krylov vectors, and float32 matvec writing float64 Krylov vectors.
+// Krylov vectors, float32 matvec writing float64 Krylov vectors, and float32
+// apply / fused M^{-1} A between float64 Krylov vectors.
 template <typename T, typename TIn, typename TOut>
 constexpr bool has_pro(int pro) {
   if constexpr (std::is_same<T, TIn>::value && std::is_same<T, TOut>::value) return true;
+  else if constexpr (std::is_same<TIn, double>::value && std::is_same<TOut, double>::value)
+    return pro == PRO_COPY3 || pro == PRO_SMINUS;
   else return pro == PRO_COPY3;
 }
 template <typename T, typename TIn, typename TOut>
 constexpr bool has_epi(int epi) {
   if constexpr (std::is_same<T, TIn>::value && std::is_same<T, TOut>::value) return true;
+  else if constexpr (std::is_same<TIn, double>::value && std::is_same<TOut, double>::value)
+    return epi == EPI_APPLY || epi == EPI_FUSED;
   else if constexpr (std::is_same<TIn, double>::value) return epi == EPI_APPLY;
   else return epi == EPI_MATVEC;
 }

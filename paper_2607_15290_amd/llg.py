@@ -17,7 +17,9 @@ from . import _lib as L
 
 FP64 = 0
 FP32_IR = 1
-_PREC = {"fp64": FP64, "fp32_ir": FP32_IR, FP64: FP64, FP32_IR: FP32_IR}
+FP32_IR_LEFT = 2
+_PREC = {"fp64": FP64, "fp32_ir": FP32_IR, "fp32_ir_left": FP32_IR_LEFT, FP64: FP64, FP32_IR: FP32_IR,
+         FP32_IR_LEFT: FP32_IR_LEFT}
 
 
 class LLGError(RuntimeError):

@@ -142,8 +142,15 @@ def test_fp32_ir_matches_fp64():
         b = steppers.rhs(g, op, m)
         ctx = P.Context(nx, ny, nz, h, 0)
         x64, s64 = P.gmres_solve(ctx, prm, dev(m), dev(b), rtol=1e-10)
-        x32, s32 = P.gmres_solve(ctx, prm, dev(m), dev(b), rtol=1e-10, prec="fp32_ir", inner_rtol=1e-5)
-        assert s32["converged"] == 1 and s32["rel_res_true"] <= 1e-10
-        assert s32["outer_steps"] >= 2
-        assert rel(host(x32), host(x64)) <= 1e-8
+        # flexible inner GMRES (the precision form) and the left-preconditioned
+        # inner variant, each with both Arnoldi variants
+        for prec in ("fp32_ir", "fp32_ir_left"):
+            for orth in ("dcgs2", "cgs2"):
+                x32, s32 = P.gmres_solve(ctx, prm, dev(m), dev(b), rtol=1e-10, prec=prec, inner_rtol=1e-5,
+                                         orth=orth)
+                assert s32["converged"] == 1 and s32["rel_res_true"] <= 1e-10, (prec, orth)
+                assert s32["outer_steps"] >= 2
+                assert rel(host(x32), host(x64)) <= 1e-8
+                # inner iterations comparable to the float64 solve's
+                assert s32["iters"] <= 2 * s64["iters"] + 10, (prec, orth, s32["iters"], s64["iters"])
         ctx.close()
