@@ -256,6 +256,13 @@ typedef struct {
 llg_status llg_profile_enable(llg_ctx* ctx, int enable);
 int llg_profile_read(llg_ctx* ctx, llg_kernel_profile* out, int max_entries);
 
+/* Restrict the recording to the kernel kinds named in `kinds`, a
+ * comma-separated list of the names llg_profile_read reports (e.g.
+ * "cgs_update_dots,cgs_dots"); NULL or "" selects every kind (the default).
+ * Fewer bracketed launches means less event overhead in a timed region.
+ * Errors: LLG_EARG (null context, unknown name; selection unchanged). */
+llg_status llg_profile_select(llg_ctx* ctx, const char* kinds);
+
 /* Message describing the last error on this thread ("" if none). */
 const char* llg_last_error(void);
 

@@ -75,6 +75,7 @@ SIGNATURES = {
     "llg_rhs": (I, [P, ctypes.POINTER(LLGParams), P, P, P]),
     "llg_profile_enable": (I, [P, I]),
     "llg_profile_read": (I, [P, ctypes.POINTER(LLGKernelProfile), I]),
+    "llg_profile_select": (I, [P, ctypes.c_char_p]),
     "llg_last_error": (ctypes.c_char_p, []),
 }
 

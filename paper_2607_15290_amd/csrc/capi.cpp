@@ -24,6 +24,7 @@ namespace llg {
 Profiler* profiler_new();
 void profiler_delete(Profiler* p);
 void profiler_enable(Profiler* p, bool on);
+bool profiler_select(Profiler* p, const char* kinds);
 int profiler_read(Profiler* p, llg_kernel_profile* out, int max_entries);
 
 static thread_local std::string g_err;
@@ -859,6 +860,12 @@ size_t llg_workspace_bytes(const llg_ctx* ctx, int restart, int prec) {
 llg_status llg_profile_enable(llg_ctx* ctx, int enable) {
   if (!ctx || !ctx->c.prof) return fail(LLG_EARG, "null context");
   profiler_enable(ctx->c.prof, enable != 0);
+  return LLG_OK;
+}
+
+llg_status llg_profile_select(llg_ctx* ctx, const char* kinds) {
+  if (!ctx || !ctx->c.prof) return fail(LLG_EARG, "null context");
+  if (!profiler_select(ctx->c.prof, kinds)) return fail(LLG_EARG, "unknown kernel kind in the selection");
   return LLG_OK;
 }
 

@@ -2,6 +2,7 @@
 // aggregated per kernel kind with the launches' algorithmic bytes.
 #include <hip/hip_runtime.h>
 
+#include <cstring>
 #include <vector>
 
 #include "llg_internal.h"
@@ -10,6 +11,10 @@ namespace llg {
 
 struct Profiler {
   bool on = false;
+  bool sel[KK_COUNT];  // kinds that are recorded while on
+  Profiler() {
+    for (bool& b : sel) b = true;
+  }
   struct Rec {
     int kind;
     hipEvent_t a, b;
@@ -48,7 +53,7 @@ static const char* kNames[KK_COUNT] = {"xfwd",      "axis_fwd",          "axis_f
 const char* kernel_kind_name(int k) { return (k >= 0 && k < KK_COUNT) ? kNames[k] : "?"; }
 
 ProfScope::ProfScope(Profiler* prof, hipStream_t s, int k, double b) : p(prof), st(s), kind(k), bytes(b), a(nullptr) {
-  if (p && p->on) {
+  if (p && p->on && p->sel[k]) {
     a = p->take();
     if (a) (void)hipEventRecord(a, st);
   }
@@ -69,6 +74,30 @@ void profiler_delete(Profiler* p) { delete p; }
 void profiler_enable(Profiler* p, bool on) {
   if (on) p->recycle();
   p->on = on;
+}
+
+// Select the kinds to record from a comma-separated list of names (null or
+// empty: all kinds).  Returns false on an unknown name (selection unchanged).
+bool profiler_select(Profiler* p, const char* kinds) {
+  bool want[KK_COUNT];
+  const bool all = kinds == nullptr || kinds[0] == 0;
+  for (bool& b : want) b = all;
+  if (!all) {
+    const char* q = kinds;
+    while (*q) {
+      const char* e = q;
+      while (*e && *e != ',') ++e;
+      const size_t len = size_t(e - q);
+      int found = -1;
+      for (int k = 0; k < KK_COUNT; ++k)
+        if (std::strlen(kNames[k]) == len && std::strncmp(kNames[k], q, len) == 0) found = k;
+      if (found < 0) return false;
+      want[found] = true;
+      q = *e ? e + 1 : e;
+    }
+  }
+  for (int k = 0; k < KK_COUNT; ++k) p->sel[k] = want[k];
+  return true;
 }
 
 int profiler_read(Profiler* p, llg_kernel_profile* out, int max_entries) {

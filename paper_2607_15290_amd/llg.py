@@ -293,6 +293,12 @@ def llg_profile_enable(ctx, enable=True):
     _check(ctx.lib.llg_profile_enable(ctx.handle, int(bool(enable))), "llg_profile_enable")
 
 
+def llg_profile_select(ctx, kinds=None):
+    """Record only the named kernel kinds (list of names; None: all)."""
+    arg = None if not kinds else ",".join(kinds).encode()
+    _check(ctx.lib.llg_profile_select(ctx.handle, arg), "llg_profile_select")
+
+
 def llg_profile_read(ctx):
     """Per-kernel totals recorded since llg_profile_enable:
     {name: dict(launches, total_ms, bytes)}."""
