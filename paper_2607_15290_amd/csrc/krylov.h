@@ -29,8 +29,9 @@ hipError_t dcgs_update(const Ctx& c, const double* Q, long long ld, const DcgsCo
 hipError_t reduce_partials(const Ctx& c, int nv, double* out, bool is_max, hipStream_t st);
 // sum over the first nb block partials (stride kMaxDots) of nv values
 hipError_t reduce_partials_n(const Ctx& c, int nb, int nv, double* out, hipStream_t st);
-// Blocks of a delayed-CGS2 pass over n2 16-byte elements: two elements per
-// thread, at most kRedBlocksMax; depends only on n2 (deterministic order).
+// Blocks of a delayed-CGS2 pass over n2 16-byte elements: one element per
+// thread of a 512-thread block (2 kRedThreads), at most kRedBlocksMax blocks
+// (grid-strided beyond); depends only on n2 (deterministic order).
 inline int red_blocks(long long n2) {
   long long g = (n2 + 2 * kRedThreads - 1) / (2 * kRedThreads);
   if (g > kRedBlocksMax) g = kRedBlocksMax;
