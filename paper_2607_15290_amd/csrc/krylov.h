@@ -26,8 +26,17 @@ hipError_t dcgs_dots(const Ctx& c, const double* Q, long long ld, int j, const d
 hipError_t dcgs_update(const Ctx& c, const double* Q, long long ld, const DcgsCoef& cf, const double* bd, double* u,
                        const double* w, double* qj, long long n, double* out, hipStream_t st);
 
-hipError_t reduce_partials(const Ctx& c, int nv, double* out, bool is_max, hipStream_t st);
-// sum over the first nb block partials (stride kMaxDots) of nv values
+// out[i] = sum (or max) of the nb value-major partials of value i, i < nv
+hipError_t reduce_partials(const Ctx& c, int nb, int nv, double* out, bool is_max, hipStream_t st);
+// Blocks of a reducing streaming kernel over n elements: about four elements
+// per thread, at most kNodalBlocksMax; depends only on n (deterministic order).
+constexpr int kNodalBlocksMax = 16384;
+inline int nodal_blocks(long long n) {
+  long long g = (n + 4 * kRedThreads - 1) / (4 * kRedThreads);
+  if (g > kNodalBlocksMax) g = kNodalBlocksMax;
+  return int(g < 1 ? 1 : g);
+}
+// out[i] = sum of the nb value-major partials of value i, i < nv (1024-thread reducer)
 hipError_t reduce_partials_n(const Ctx& c, int nb, int nv, double* out, hipStream_t st);
 // Blocks of a delayed-CGS2 pass over n2 16-byte elements: one element per
 // thread of a 512-thread block (2 kRedThreads), at most kRedBlocksMax blocks

@@ -1,11 +1,11 @@
 // Streaming vector kernels of the Krylov solvers and the steppers.
 //
-// All reductions are two-stage and deterministic: a fixed grid of kRedBlocks
-// blocks accumulates per-thread partial sums in a fixed order, reduces them
-// across the block by wavefront shuffles, and writes one partial per block;
-// a second kernel sums the kRedBlocks partials of each value in a fixed tree.
-// The grid never depends on timing, so every reduced value is bitwise
-// reproducible from run to run.
+// All reductions are two-stage and deterministic: a grid whose size depends
+// only on the vector length accumulates per-thread partial sums in a fixed
+// order, reduces them across the block by wavefront shuffles, and writes one
+// partial per block; a second kernel sums the partials of each value in a
+// fixed tree.  The grid never depends on timing, so every reduced value is
+// bitwise reproducible from run to run.
 //
 // Arnoldi orthogonalization is classical Gram-Schmidt with one
 // re-orthogonalization (CGS2), as three streaming passes over the basis:
@@ -41,7 +41,8 @@ __device__ __forceinline__ void stnt(double2* p, double2 v) {
   __builtin_nontemporal_store(v.y, &p->y);
 }
 
-// Reduce acc[0..nv) over the block and store partial[blockIdx.x * kMaxDots + i].
+// Reduce acc[0..nv) over the block and store partial[i * gridDim.x + blockIdx.x]
+// (value-major: the partials of one value are contiguous).
 template <int MAXV, bool MAX = false>
 __device__ __forceinline__ void block_store(double (&acc)[MAXV], int nv, double* __restrict__ partial) {
   __shared__ double sm[kRedThreads / 64][MAXV];
@@ -58,18 +59,18 @@ __device__ __forceinline__ void block_store(double (&acc)[MAXV], int nv, double*
     double s = sm[0][threadIdx.x];
 #pragma unroll
     for (int w = 1; w < kRedThreads / 64; ++w) s = MAX ? fmax(s, sm[w][threadIdx.x]) : s + sm[w][threadIdx.x];
-    partial[blockIdx.x * kMaxDots + threadIdx.x] = s;
+    partial[(long long)threadIdx.x * gridDim.x + blockIdx.x] = s;
   }
 }
 
-// out[i] = sum (or max) over blocks of partial[b * kMaxDots + i]; one block per value.
+// out[i] = sum (or max) over blocks of partial[i * nb + b]; one block per value.
 template <bool MAX>
 __global__ __launch_bounds__(kRedThreads) void k_reduce(const double* __restrict__ partial, int nb,
                                                        double* __restrict__ out) {
   const int i = blockIdx.x;
   double s = MAX ? -INFINITY : 0.0;
   for (int b = threadIdx.x; b < nb; b += kRedThreads) {
-    const double v = partial[b * kMaxDots + i];
+    const double v = partial[(long long)i * nb + b];
     s = MAX ? fmax(s, v) : s + v;
   }
   __shared__ double sm[kRedThreads / 64];
@@ -384,18 +385,18 @@ hipError_t reduce_flat(const Ctx& c, int nb, double* out, hipStream_t st) {
   return hipGetLastError();
 }
 
-hipError_t reduce_partials(const Ctx& c, int nv, double* out, bool is_max, hipStream_t st) {
-  ProfScope ps(c.prof, st, KK_REDUCE, 8.0 * kRedBlocks * nv);
+hipError_t reduce_partials(const Ctx& c, int nb, int nv, double* out, bool is_max, hipStream_t st) {
+  ProfScope ps(c.prof, st, KK_REDUCE, 8.0 * nb * nv);
   if (is_max)
-    hipLaunchKernelGGL((k_reduce<true>), dim3(nv), dim3(kRedThreads), 0, st, c.partial, kRedBlocks, out);
+    hipLaunchKernelGGL((k_reduce<true>), dim3(nv), dim3(kRedThreads), 0, st, c.partial, nb, out);
   else
-    hipLaunchKernelGGL((k_reduce<false>), dim3(nv), dim3(kRedThreads), 0, st, c.partial, kRedBlocks, out);
+    hipLaunchKernelGGL((k_reduce<false>), dim3(nv), dim3(kRedThreads), 0, st, c.partial, nb, out);
   return hipGetLastError();
 }
 
 template <int MAXV>
 static void mdot_t(const Ctx& c, const double* V, long long ld, int nv, const double* w, long long n, hipStream_t st) {
-  hipLaunchKernelGGL((k_mdot<MAXV>), dim3(kRedBlocks), dim3(kRedThreads), 0, st, V, ld, nv, w, n, c.partial);
+  hipLaunchKernelGGL((k_mdot<MAXV>), dim3(nodal_blocks(n)), dim3(kRedThreads), 0, st, V, ld, nv, w, n, c.partial);
 }
 hipError_t cgs_dots(const Ctx& c, const double* V, long long ld, int nv, const double* w, long long n, double* out,
                     hipStream_t st) {
@@ -406,13 +407,14 @@ hipError_t cgs_dots(const Ctx& c, const double* V, long long ld, int nv, const d
   else if (nv <= 32) mdot_t<32>(c, V, ld, nv, w, n, st);
   else mdot_t<64>(c, V, ld, nv, w, n, st);
   }
-  return reduce_partials(c, nv, out, false, st);
+  return reduce_partials(c, nodal_blocks(n), nv, out, false, st);
 }
 
 template <int MAXV>
 static void upd_t(const Ctx& c, const double* V, long long ld, int nv, const double* cf, double* w, long long n,
                   hipStream_t st) {
-  hipLaunchKernelGGL((k_update_mdot<MAXV>), dim3(kRedBlocks), dim3(kRedThreads), 0, st, V, ld, nv, cf, w, n, c.partial);
+  hipLaunchKernelGGL((k_update_mdot<MAXV>), dim3(nodal_blocks(n)), dim3(kRedThreads), 0, st, V, ld, nv, cf, w, n,
+                     c.partial);
 }
 hipError_t cgs_update_dots(const Ctx& c, const double* V, long long ld, int nv, const double* cf, double* w,
                            long long n, double* out, hipStream_t st) {
@@ -423,13 +425,13 @@ hipError_t cgs_update_dots(const Ctx& c, const double* V, long long ld, int nv, 
   else if (nv <= 32) upd_t<32>(c, V, ld, nv, cf, w, n, st);
   else upd_t<64>(c, V, ld, nv, cf, w, n, st);
   }
-  return reduce_partials(c, nv, out, false, st);
+  return reduce_partials(c, nodal_blocks(n), nv, out, false, st);
 }
 
 template <int MAXV>
 static void updn_t(const Ctx& c, const double* V, long long ld, int nv, const double* cf, const double* w,
                    double* o, long long n, hipStream_t st) {
-  hipLaunchKernelGGL((k_update_norm<MAXV>), dim3(kRedBlocks), dim3(kRedThreads), 0, st, V, ld, nv, cf, w, o, n,
+  hipLaunchKernelGGL((k_update_norm<MAXV>), dim3(nodal_blocks(n)), dim3(kRedThreads), 0, st, V, ld, nv, cf, w, o, n,
                      c.partial);
 }
 hipError_t cgs_update_norm(const Ctx& c, const double* V, long long ld, int nv, const double* cf, const double* w,
@@ -441,7 +443,7 @@ hipError_t cgs_update_norm(const Ctx& c, const double* V, long long ld, int nv, 
   else if (nv <= 32) updn_t<32>(c, V, ld, nv, cf, w, out_vec, n, st);
   else updn_t<64>(c, V, ld, nv, cf, w, out_vec, n, st);
   }
-  return reduce_partials(c, 1, out_nrm2, false, st);
+  return reduce_partials(c, nodal_blocks(n), 1, out_nrm2, false, st);
 }
 
 
@@ -566,17 +568,17 @@ hipError_t to_f32(const Ctx& c, long long n, const double* a, float* b, hipStrea
 hipError_t dot_and_norm(const Ctx& c, const double* x, const double* y, long long n, double* out, hipStream_t st) {
   {
   ProfScope ps(c.prof, st, KK_DOT2, 8.0 * n * (y ? 2 : 1));
-  hipLaunchKernelGGL(k_dot2, dim3(kRedBlocks), dim3(kRedThreads), 0, st, x, y, n, c.partial);
+  hipLaunchKernelGGL(k_dot2, dim3(nodal_blocks(n)), dim3(kRedThreads), 0, st, x, y, n, c.partial);
   }
-  return reduce_partials(c, 2, out, false, st);
+  return reduce_partials(c, nodal_blocks(n), 2, out, false, st);
 }
 
 hipError_t diff_norms(const Ctx& c, const double* a, const double* b, long long n, double* out, hipStream_t st) {
   {
   ProfScope ps(c.prof, st, KK_DOT2, 8.0 * n * (b ? 2 : 1));
-  hipLaunchKernelGGL(k_diffnorm, dim3(kRedBlocks), dim3(kRedThreads), 0, st, a, b, n, c.partial);
+  hipLaunchKernelGGL(k_diffnorm, dim3(nodal_blocks(n)), dim3(kRedThreads), 0, st, a, b, n, c.partial);
   }
-  return reduce_partials(c, 2, out, false, st);
+  return reduce_partials(c, nodal_blocks(n), 2, out, false, st);
 }
 
 }  // namespace llg

@@ -23,7 +23,6 @@ void set_error(const std::string& msg);
 
 // Number of blocks used by every streaming reduction (fixed per context so the
 // reduction order, and hence every reduced value, is bitwise reproducible).
-constexpr int kRedBlocks = 1024;
 constexpr int kRedBlocksMax = 65536;  // partial buffer rows (large dot passes)
 constexpr int kRedThreads = 256;
 constexpr int kMaxDots = 64;
@@ -58,7 +57,7 @@ struct Ctx {
   cx<float>* tw_f[3] = {nullptr, nullptr, nullptr};
   void* spec = nullptr;  // spectral scratch (complex double capacity)
   size_t spec_bytes = 0;
-  double* partial = nullptr;  // kRedBlocks x kMaxDots reduction partials
+  double* partial = nullptr;  // kRedBlocksMax x kMaxDots reduction partials
   double* dots = nullptr;     // kMaxDots reduced values (device)
   double* dots2 = nullptr;    // second set (CGS2 re-orthogonalization)
   double* scal = nullptr;     // small device scalars

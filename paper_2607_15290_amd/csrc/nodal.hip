@@ -45,7 +45,7 @@ __device__ __forceinline__ void bstore(double (&acc)[NV], double* __restrict__ p
       const double o = sm[k][threadIdx.x];
       s = OP == 0 ? s + o : (OP == 1 ? fmax(s, o) : fmin(s, o));
     }
-    partial[blockIdx.x * kMaxDots + threadIdx.x] = s;
+    partial[(long long)threadIdx.x * gridDim.x + blockIdx.x] = s;
   }
 }
 
@@ -64,7 +64,7 @@ __global__ __launch_bounds__(kRedThreads) void k_m_check(const double* __restric
   }
   bstore<1, 2>(mn, partial);
   __syncthreads();
-  bstore<1, 1>(bad, partial + 1);
+  bstore<1, 1>(bad, partial + gridDim.x);
 }
 
 __global__ __launch_bounds__(kRedThreads) void k_euler_update(double* __restrict__ m, const double* __restrict__ v,
@@ -214,8 +214,8 @@ __global__ __launch_bounds__(kRedThreads) void k_reduce_min_max(const double* __
                                                                double* __restrict__ out) {
   double mn[1] = {INFINITY}, mx[1] = {-INFINITY};
   for (int b = threadIdx.x; b < nb; b += kRedThreads) {
-    mn[0] = fmin(mn[0], partial[b * kMaxDots]);
-    mx[0] = fmax(mx[0], partial[b * kMaxDots + 1]);
+    mn[0] = fmin(mn[0], partial[b]);
+    mx[0] = fmax(mx[0], partial[nb + b]);
   }
   __shared__ double sm[2][kRedThreads / 64];
   const double a = -wmax(-mn[0]), b = wmax(mx[0]);
@@ -246,8 +246,9 @@ hipError_t m_check(const Ctx& c, const double* m, double* out, hipStream_t st) {
   hipError_t e_ = hipSuccess;
   {
   ProfScope ps(c.prof, st, KK_NODAL, 0.0);
-  hipLaunchKernelGGL(k_m_check, dim3(kRedBlocks), dim3(kRedThreads), 0, st, m, c.ng, c.partial);
-  hipLaunchKernelGGL((k_reduce_min_max), dim3(1), dim3(kRedThreads), 0, st, c.partial, kRedBlocks, out);
+  const int nb = nodal_blocks(c.ng);
+  hipLaunchKernelGGL(k_m_check, dim3(nb), dim3(kRedThreads), 0, st, m, c.ng, c.partial);
+  hipLaunchKernelGGL((k_reduce_min_max), dim3(1), dim3(kRedThreads), 0, st, c.partial, nb, out);
   e_ = hipGetLastError();
   }
   return e_;
@@ -257,8 +258,8 @@ hipError_t euler_update(const Ctx& c, double* m, const double* v, double k, doub
   hipError_t e_ = hipSuccess;
   {
   ProfScope ps(c.prof, st, KK_NODAL, 0.0);
-  hipLaunchKernelGGL(k_euler_update, dim3(kRedBlocks), dim3(kRedThreads), 0, st, m, v, k, c.ng, c.partial);
-  e_ = reduce_partials(c, 1, out, true, st);
+  hipLaunchKernelGGL(k_euler_update, dim3(nodal_blocks(c.ng)), dim3(kRedThreads), 0, st, m, v, k, c.ng, c.partial);
+  e_ = reduce_partials(c, nodal_blocks(c.ng), 1, out, true, st);
   }
   return e_;
 }
@@ -277,8 +278,8 @@ hipError_t len_err(const Ctx& c, const double* m, double* out, hipStream_t st) {
   hipError_t e_ = hipSuccess;
   {
   ProfScope ps(c.prof, st, KK_NODAL, 0.0);
-  hipLaunchKernelGGL(k_len_err, dim3(kRedBlocks), dim3(kRedThreads), 0, st, m, c.ng, c.partial);
-  e_ = reduce_partials(c, 1, out, true, st);
+  hipLaunchKernelGGL(k_len_err, dim3(nodal_blocks(c.ng)), dim3(kRedThreads), 0, st, m, c.ng, c.partial);
+  e_ = reduce_partials(c, nodal_blocks(c.ng), 1, out, true, st);
   }
   return e_;
 }
@@ -289,9 +290,9 @@ hipError_t midpoint_diag(const Ctx& c, const NodalArgs& na, double alpha, double
   hipError_t e_ = hipSuccess;
   {
   ProfScope ps(c.prof, st, KK_NODAL, 0.0);
-  hipLaunchKernelGGL(k_midpoint_diag, dim3(kRedBlocks), dim3(kRedThreads), 0, st, na, alpha, cexc, k, m0, v, r, lm0,
-                     lv, c.ng, c.partial);
-  e_ = reduce_partials(c, 5, out, false, st);
+  hipLaunchKernelGGL(k_midpoint_diag, dim3(nodal_blocks(c.ng)), dim3(kRedThreads), 0, st, na, alpha, cexc, k, m0, v,
+                     r, lm0, lv, c.ng, c.partial);
+  e_ = reduce_partials(c, nodal_blocks(c.ng), 5, out, false, st);
   }
   return e_;
 }
@@ -301,9 +302,9 @@ hipError_t picard_update(const Ctx& c, const double* m0, const double* v, double
   hipError_t e_ = hipSuccess;
   {
   ProfScope ps(c.prof, st, KK_NODAL, 0.0);
-  hipLaunchKernelGGL(k_picard_update, dim3(kRedBlocks), dim3(kRedThreads), 0, st, m0, v, vold, mh, a, 3 * c.ng,
-                     c.partial);
-  e_ = reduce_partials(c, 3, out, false, st);
+  hipLaunchKernelGGL(k_picard_update, dim3(nodal_blocks(3 * c.ng)), dim3(kRedThreads), 0, st, m0, v, vold, mh, a,
+                     3 * c.ng, c.partial);
+  e_ = reduce_partials(c, nodal_blocks(3 * c.ng), 3, out, false, st);
   }
   return e_;
 }
@@ -313,8 +314,8 @@ hipError_t energy_sum(const Ctx& c, const NodalArgs& na, double cexc, const doub
   hipError_t e_ = hipSuccess;
   {
   ProfScope ps(c.prof, st, KK_NODAL, 0.0);
-  hipLaunchKernelGGL(k_energy, dim3(kRedBlocks), dim3(kRedThreads), 0, st, na, cexc, m, lm, c.ng, c.partial);
-  e_ = reduce_partials(c, 1, out, false, st);
+  hipLaunchKernelGGL(k_energy, dim3(nodal_blocks(c.ng)), dim3(kRedThreads), 0, st, na, cexc, m, lm, c.ng, c.partial);
+  e_ = reduce_partials(c, nodal_blocks(c.ng), 1, out, false, st);
   }
   return e_;
 }
@@ -324,9 +325,9 @@ hipError_t adjoint_finish(const Ctx& c, const NodalArgs& na, const double* v, co
   hipError_t e_ = hipSuccess;
   {
   ProfScope ps(c.prof, st, KK_NODAL, 0.0);
-  hipLaunchKernelGGL(k_adjoint_finish, dim3(kRedBlocks), dim3(kRedThreads), 0, st, na, v, r, mu, lmu, gbar,
+  hipLaunchKernelGGL(k_adjoint_finish, dim3(nodal_blocks(c.ng)), dim3(kRedThreads), 0, st, na, v, r, mu, lmu, gbar,
                      hbar_field, c.ng, c.partial);
-  e_ = reduce_partials(c, 3, out_hsum, false, st);
+  e_ = reduce_partials(c, nodal_blocks(c.ng), 3, out_hsum, false, st);
   }
   return e_;
 }

@@ -36,6 +36,15 @@ __device__ __forceinline__ int xphys(int pos) { return pos + (pos >> 4); }
 #ifndef LLG_PIPE_NT
 #define LLG_PIPE_NT 1
 #endif
+// Node pairs per thread whose plane loads are issued together in the x passes
+// (float32: 6, about 4% faster x-forward at 256^3 than 3; float64: 3, the
+// larger batch costs occupancy).
+#ifndef LLG_XBATCH_F32
+#define LLG_XBATCH_F32 6
+#endif
+#ifndef LLG_XBATCH_F64
+#define LLG_XBATCH_F64 3
+#endif
 template <typename U>
 __device__ __forceinline__ U ld_s(const U* p) {
 #if LLG_PIPE_NT
@@ -322,7 +331,7 @@ __global__ __launch_bounds__(192) void k_xfwd(const TIn* __restrict__ in, const 
   // together; only the LDS writes are predicated.
   constexpr int NPAIR = C::LX * NH;
   constexpr int ITERS = (NPAIR + C::NT - 1) / C::NT;
-  constexpr int BATCH = 3;  // node pairs whose loads are in flight together
+  constexpr int BATCH = sizeof(T) == 4 ? LLG_XBATCH_F32 : LLG_XBATCH_F64;
 #pragma unroll
   for (int it0 = 0; it0 < ITERS; it0 += BATCH) {
     ProRaw<T, TIn, PRO> raw[BATCH];
@@ -442,7 +451,7 @@ __global__ __launch_bounds__(192) void k_xinv(PipeIO<T, TIn, TOut> io, const cx<
   double rsum = 0.0;
   constexpr int NPAIR = C::LX * NH;
   constexpr int ITERS = (NPAIR + C::NT - 1) / C::NT;
-  constexpr int BATCH = 3;
+  constexpr int BATCH = sizeof(T) == 4 ? LLG_XBATCH_F32 : LLG_XBATCH_F64;
 #pragma unroll
   for (int it0 = 0; it0 < ITERS; it0 += BATCH) {
   EpiRaw<T, TIn, TOut, EPI> raw[BATCH];
