@@ -68,6 +68,9 @@ void launch_xinv(const Ctx& c, const NodalArgs& na, const PipeIO<T, TIn, TOut>& 
 template <typename T, typename TIn, typename TOut, int NH>
 hipError_t run_nh(const Ctx& c, int pro, int epi, const SymArgs& sym, const NodalArgs& na,
                   const PipeIO<T, TIn, TOut>& io, hipStream_t st) {
+  // a mode without an instantiation for this type combination is an error,
+  // never a silently skipped pass
+  if (!has_pro<T, TIn, TOut>(pro) || !has_epi<T, TIn, TOut>(epi)) return hipErrorInvalidValue;
   switch (pro) {
     case PRO_COPY3: launch_xfwd<T, TIn, TOut, NH, PRO_COPY3>(c, na, io, st); break;
     case PRO_SMINUS: launch_xfwd<T, TIn, TOut, NH, PRO_SMINUS>(c, na, io, st); break;

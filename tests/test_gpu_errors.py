@@ -1,0 +1,117 @@
+"""Error paths of the C ABI on the GPU.  Every failure is forced from the host
+(arguments, iteration limits, a zero or non-finite magnetization node, a
+short workspace): the library must return the documented status, leave a
+message in llg_last_error, and keep the context usable afterwards."""
+
+import ctypes
+
+import numpy as np
+import pytest
+import torch
+
+import paper_2607_15290_amd as P
+from paper_2607_15290_amd import _lib as L
+from oracle import steppers
+from oracle.grid import Grid
+from tests.gpu_util import announce, both_params, dev, host, rel, unit_field
+
+pytestmark = pytest.mark.gpu
+
+N = 16
+
+
+def _setup():
+    g = Grid(N, N, 1, h=1.0 / N)
+    prm, op = both_params(alpha=0.1, cexc=1.0, dt=1e-3, theta=1.0, shift=0.5, h_uniform=(0.0, 0.0, 0.5))
+    m = unit_field((1, N, N), 5, smooth=4.0)
+    b = steppers.rhs(g, op, m)
+    ctx = P.Context(N, N, 1, 1.0 / N, 0)
+    return g, prm, op, m, b, ctx
+
+
+def _last_error(ctx):
+    return ctx.lib.llg_last_error().decode()
+
+
+def test_status_codes_for_bad_inputs():
+    announce("error paths: status codes")
+    g, prm, op, m, b, ctx = _setup()
+    md, bd = dev(m), dev(b)
+    # zero magnetization at one node (Proposition 1 needs m_i != 0)
+    mz = m.copy()
+    mz[:, 0, 3, 5] = 0.0
+    _, st = P.gmres_solve(ctx, prm, dev(mz), bd, check=False)
+    assert st["status"] == "LLG_EZERO_M" and "zero" in _last_error(ctx)
+    # non-finite magnetization and right-hand side
+    mn = m.copy()
+    mn[1, 0, 2, 2] = np.nan
+    _, st = P.gmres_solve(ctx, prm, dev(mn), bd, check=False)
+    assert st["status"] == "LLG_ENAN"
+    bn = b.copy()
+    bn[0, 0, 1, 1] = np.inf
+    _, st = P.gmres_solve(ctx, prm, md, dev(bn), check=False)
+    assert st["status"] == "LLG_ENAN"
+    # iteration limit: ENOCONV with a finite last iterate and filled stats
+    x, st = P.gmres_solve(ctx, prm, md, bd, rtol=1e-14, maxiter=2, check=False)
+    assert st["status"] == "LLG_ENOCONV" and st["converged"] == 0 and st["iters"] == 2
+    assert np.all(np.isfinite(host(x)))
+    # Picard limit: EPICARD after picard_max iterations, state written
+    prm2, _ = both_params(alpha=0.1, cexc=1.0, dt=5e-3, theta=0.5, shift=0.5, h_uniform=(0.0, 0.0, 0.5))
+    mm = md.clone()
+    st = P.llg_step_midpoint(ctx, prm2, mm, picard_tol=1e-14, picard_max=1, check=False)
+    assert st["status"] == "LLG_EPICARD" and st["picard_iters"] == 1 and st["converged"] == 0
+    # the context still solves correctly afterwards
+    x, st = P.gmres_solve(ctx, prm, md, bd, rtol=1e-12)
+    xref, _ = steppers.solve_saddle(g, op, m, b, rtol=1e-12)
+    assert st["converged"] == 1 and rel(host(x), xref) <= 1e-9
+    ctx.close()
+
+
+def test_argument_errors():
+    announce("error paths: argument checks")
+    g, prm, op, m, b, ctx = _setup()
+    md, bd = dev(m), dev(b)
+    bad_opts = [dict(restart=40, orth="dcgs2"), dict(rtol=0.0), dict(rtol=1.5), dict(maxiter=0),
+                dict(prec="fp32_ir", precond="none"), dict(prec="fp32_ir", inner_rtol=0.0),
+                dict(prec="fp32_ir", max_outer=0)]
+    for kw in bad_opts:
+        _, st = P.gmres_solve(ctx, prm, md, bd, check=False, **kw)
+        assert st["status"] == "LLG_EARG", kw
+        assert len(_last_error(ctx)) > 0
+    # restart outside [1, 62]: no workspace size exists, and the solver rejects it
+    assert ctx.lib.llg_workspace_bytes(ctx.handle, 0, 0) == 0
+    assert ctx.lib.llg_workspace_bytes(ctx.handle, 63, 0) == 0
+    for pkw in [dict(alpha=0.0), dict(shift=-1.0), dict(theta=1.5), dict(dt=float("nan")),
+                dict(aniso_k=0.2, aniso_axis=(1.0, 1.0, 0.0)), dict(demag=float("inf"))]:
+        kw = dict(alpha=0.1, cexc=1.0, dt=1e-3, theta=1.0, shift=0.5)
+        kw.update(pkw)
+        _, st = P.gmres_solve(ctx, P.Params(**kw), md, bd, check=False)
+        assert st["status"] == "LLG_EARG", pkw
+    # aliasing: x == b for the solver, y == x for the matvec
+    o = L.LLGSolverOpts()
+    o.restart, o.maxiter, o.max_outer, o.rtol, o.inner_rtol = 30, 100, 10, 1e-10, 1e-5
+    work = ctx.workspace(30, "fp64")
+    pr = prm.c_struct()
+    s = ctx.lib.gmres_solve(ctx.handle, ctypes.byref(pr), md.data_ptr(), bd.data_ptr(), bd.data_ptr(),
+                            ctypes.byref(o), None, work.data_ptr(), work.numel(), None)
+    assert s == 1 and "alias" in _last_error(ctx)
+    s = ctx.lib.llg_matvec(ctx.handle, ctypes.byref(pr), md.data_ptr(), bd.data_ptr(), bd.data_ptr(), 0, None)
+    assert s == 1
+    x = torch.zeros_like(bd)
+    for r in (0, 63):
+        o.restart = r
+        s = ctx.lib.gmres_solve(ctx.handle, ctypes.byref(pr), md.data_ptr(), bd.data_ptr(), x.data_ptr(),
+                                ctypes.byref(o), None, work.data_ptr(), work.numel(), None)
+        assert s == 1, r
+    o.restart = 30
+    # a workspace one byte short
+    need = ctx.lib.llg_workspace_bytes(ctx.handle, 30, 0)
+    small = torch.empty(need - 1, dtype=torch.uint8, device="cuda:0")
+    x = torch.zeros_like(bd)
+    s = ctx.lib.gmres_solve(ctx.handle, ctypes.byref(pr), md.data_ptr(), bd.data_ptr(), x.data_ptr(),
+                            ctypes.byref(o), None, small.data_ptr(), small.numel(), None)
+    assert s == 7 and "workspace" in _last_error(ctx)
+    # unknown profiler kind
+    assert ctx.lib.llg_profile_select(ctx.handle, b"no_such_kind") == 1
+    assert ctx.lib.llg_profile_select(ctx.handle, None) == 0
+    ctx.close()
