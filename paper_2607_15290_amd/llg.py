@@ -52,7 +52,11 @@ class Params:
     aniso_k: float = 0.0
     aniso_axis: tuple = (0.0, 0.0, 1.0)
 
-    def c_struct(self):
+    def c_struct(self, ctx=None):
+        """The llg_params struct.  With a context, the spatial field (read by the
+        kernels through a raw pointer) is checked against that context's grid."""
+        if self.h_field is not None and ctx is not None:
+            ctx.check(self.h_field, 3, name="h_field")
         p = L.LLGParams()
         p.alpha, p.cexc, p.dt, p.theta, p.shift = (float(self.alpha), float(self.cexc), float(self.dt),
                                                    float(self.theta), float(self.shift))
@@ -154,7 +158,7 @@ class Context:
 def llg_matvec(ctx, params, m, x, y=None, transpose=False):
     """y = A x (or A^T x).  See llg_matvec in include/llg.h."""
     y = ctx.new(4) if y is None else y
-    p = params.c_struct()
+    p = params.c_struct(ctx)
     _check(ctx.lib.llg_matvec(ctx.handle, ctypes.byref(p), ctx.check(m, 3, name="m"), ctx.check(x, 4, name="x"),
                               ctx.check(y, 4, name="y"), int(bool(transpose)), ctx.stream()), "llg_matvec")
     return y
@@ -163,7 +167,7 @@ def llg_matvec(ctx, params, m, x, y=None, transpose=False):
 def fft_hss_apply(ctx, params, m, p, z=None, transpose=False):
     """z = M^{-1} p (or M^{-T} p).  See fft_hss_apply in include/llg.h."""
     z = ctx.new(4) if z is None else z
-    pr = params.c_struct()
+    pr = params.c_struct(ctx)
     _check(ctx.lib.fft_hss_apply(ctx.handle, ctypes.byref(pr), ctx.check(m, 3, name="m"), ctx.check(p, 4, name="p"),
                                  ctx.check(z, 4, name="z"), int(bool(transpose)), ctx.stream()), "fft_hss_apply")
     return z
@@ -171,7 +175,7 @@ def fft_hss_apply(ctx, params, m, p, z=None, transpose=False):
 
 def llg_matvec_f32(ctx, params, m, x, y=None, transpose=False):
     y = ctx.new(4, torch.float32) if y is None else y
-    p = params.c_struct()
+    p = params.c_struct(ctx)
     f = torch.float32
     _check(ctx.lib.llg_matvec_f32(ctx.handle, ctypes.byref(p), ctx.check(m, 3, f, "m"), ctx.check(x, 4, f, "x"),
                                   ctx.check(y, 4, f, "y"), int(bool(transpose)), ctx.stream()), "llg_matvec_f32")
@@ -180,7 +184,7 @@ def llg_matvec_f32(ctx, params, m, x, y=None, transpose=False):
 
 def fft_hss_apply_f32(ctx, params, m, p, z=None, transpose=False):
     z = ctx.new(4, torch.float32) if z is None else z
-    pr = params.c_struct()
+    pr = params.c_struct(ctx)
     f = torch.float32
     _check(ctx.lib.fft_hss_apply_f32(ctx.handle, ctypes.byref(pr), ctx.check(m, 3, f, "m"), ctx.check(p, 4, f, "p"),
                                      ctx.check(z, 4, f, "z"), int(bool(transpose)), ctx.stream()),
@@ -197,7 +201,7 @@ def gmres_solve(ctx, params, m, b, x=None, use_x0=False, restart=30, rtol=1e-10,
     o = _opts(restart, maxiter, rtol, prec, inner_rtol, max_outer, use_x0, orth, precond)
     st = L.LLGSolverStats()
     work = ctx.workspace(restart, prec)
-    pr = params.c_struct()
+    pr = params.c_struct(ctx)
     s = ctx.lib.gmres_solve(ctx.handle, ctypes.byref(pr), ctx.check(m, 3, name="m"), ctx.check(b, 4, name="b"),
                             ctx.check(x, 4, name="x"), ctypes.byref(o), ctypes.byref(st), work.data_ptr(),
                             work.numel(), ctx.stream())
@@ -214,7 +218,7 @@ def llg_step_euler(ctx, params, m, v_out=None, lam_out=None, restart=30, rtol=1e
     o = _opts(restart, maxiter, rtol, prec, inner_rtol, max_outer, 0, orth)
     st = L.LLGStepStats()
     work = ctx.workspace(restart, prec)
-    pr = params.c_struct()
+    pr = params.c_struct(ctx)
     s = ctx.lib.llg_step_euler(ctx.handle, ctypes.byref(pr), ctx.check(m, 3, name="m"),
                                ctx.check(v_out, 3, name="v_out") if v_out is not None else None,
                                ctx.check(lam_out, 1, name="lam_out") if lam_out is not None else None,
@@ -235,7 +239,7 @@ def llg_step_midpoint(ctx, params, m, v_half=None, lam=None, picard_tol=1e-10, p
     o = _opts(restart, maxiter, rtol, prec, inner_rtol, max_outer, 1, orth, picard_norm=picard_norm)
     st = L.LLGStepStats()
     work = ctx.workspace(restart, prec)
-    pr = params.c_struct()
+    pr = params.c_struct(ctx)
     s = ctx.lib.llg_step_midpoint(ctx.handle, ctypes.byref(pr), ctx.check(m, 3, name="m"),
                                   ctx.check(v_half, 3, name="v_half") if v_half is not None else None,
                                   ctx.check(lam, 1, name="lam") if lam is not None else None,
@@ -257,7 +261,7 @@ def llg_step_midpoint_adjoint(ctx, params, m_n, v, lam, gbar, hbar_field=None, h
     st = L.LLGSolverStats()
     work = ctx.workspace(restart, "fp64")
     hu = (ctypes.c_double * 3)(*(hbar_uniform if hbar_uniform is not None else (0.0, 0.0, 0.0)))
-    pr = params.c_struct()
+    pr = params.c_struct(ctx)
     s = ctx.lib.llg_step_midpoint_adjoint(ctx.handle, ctypes.byref(pr), ctx.check(m_n, 3, name="m_n"),
                                           ctx.check(v, 3, name="v"), ctx.check(lam, 1, name="lam"),
                                           ctx.check(gbar, 3, name="gbar"),
@@ -274,7 +278,7 @@ def llg_step_midpoint_adjoint(ctx, params, m_n, v, lam, gbar, hbar_field=None, h
 def llg_rhs(ctx, params, m, b=None):
     """b = (C_hat Delta_N m + (1+alpha^2) h_low(m), 0).  See llg_rhs in include/llg.h."""
     b = ctx.new(4) if b is None else b
-    pr = params.c_struct()
+    pr = params.c_struct(ctx)
     _check(ctx.lib.llg_rhs(ctx.handle, ctypes.byref(pr), ctx.check(m, 3, name="m"), ctx.check(b, 4, name="b"),
                            ctx.stream()), "llg_rhs")
     return b
@@ -282,7 +286,7 @@ def llg_rhs(ctx, params, m, b=None):
 
 def llg_energy(ctx, params, m):
     e = ctypes.c_double()
-    pr = params.c_struct()
+    pr = params.c_struct(ctx)
     _check(ctx.lib.llg_energy(ctx.handle, ctypes.byref(pr), ctx.check(m, 3, name="m"), ctypes.byref(e), ctx.stream()),
            "llg_energy")
     return e.value

@@ -111,6 +111,12 @@ def test_argument_errors():
     s = ctx.lib.gmres_solve(ctx.handle, ctypes.byref(pr), md.data_ptr(), bd.data_ptr(), x.data_ptr(),
                             ctypes.byref(o), None, small.data_ptr(), small.numel(), None)
     assert s == 7 and "workspace" in _last_error(ctx)
+    # a spatial field of the wrong size or layout is refused before any kernel runs
+    for hf in (torch.zeros((3, 1, N, N + 1), dtype=torch.float64, device="cuda:0"),
+               torch.zeros((3, 1, N, N), dtype=torch.float32, device="cuda:0"),
+               torch.zeros((3, 1, N, 2 * N), dtype=torch.float64, device="cuda:0")[..., ::2]):
+        with pytest.raises(ValueError):
+            P.llg_rhs(ctx, P.Params(alpha=0.1, dt=1e-3, h_field=hf), md)
     # unknown profiler kind
     assert ctx.lib.llg_profile_select(ctx.handle, b"no_such_kind") == 1
     assert ctx.lib.llg_profile_select(ctx.handle, None) == 0
