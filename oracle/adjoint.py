@@ -1,5 +1,7 @@
 """Adjoint of the converged midpoint step.
 
+Test infrastructure: part of the float64 CPU oracle (see the package docstring).
+
 Write u = (v, r) and m_half = m^n + (k/2) v.  The converged step solves the
 residual of eq. "C-N" (Sec. 3.3) with the lower-order field h:
 

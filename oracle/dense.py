@@ -1,5 +1,7 @@
 """Dense tier: naive DFT matrices and the assembled saddle system.
 
+Test infrastructure: part of the float64 CPU oracle (see the package docstring).
+
 Used only on grids of at most a few hundred nodes, to check the FFT tier and
 to provide the direct solve x = A^{-1} b that Proposition 1 (well-posedness)
 guarantees is unique.  The DFT is written out as exp(-2 pi i j k / n), with no

@@ -1,5 +1,7 @@
 """FFT tier of the spectral operators (Sec. 2.3 and Algorithm 1).
 
+Test infrastructure: part of the float64 CPU oracle (see the package docstring).
+
 -Delta_N u = iFFT(|xi|^2 FFT(u)) over the spatial axes, and the shifted
 exchange block (a + b(-Delta_N)) and its inverse are the same Fourier-diagonal
 multiplications.  numpy.fft serves as the library DFT; the dense tier checks it

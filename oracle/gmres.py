@@ -1,5 +1,7 @@
 """Restarted GMRES and flexible GMRES with iterative refinement.
 
+Test infrastructure: part of the float64 CPU oracle (see the package docstring).
+
 The paper preconditions GMRES on the left with the split FFT-HSS operator
 (Sec. 3.2) and accepts a solve by the relative residual of the full saddle
 system (Sec. 4.1).  This is the textbook restarted GMRES (Saad, Iterative

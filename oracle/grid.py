@@ -1,6 +1,8 @@
 """Periodic grid and the Fourier symbol of -Delta_N (Sec. 2.3, "Periodic
 spectral discretization").
 
+Test infrastructure: part of the float64 CPU oracle (see the package docstring).
+
 The cell is prod_l (0, L_l) with N_l nodes per axis and spacing h, so
 L_l = N_l * h.  A Fourier mode with integer wave number k_l has physical wave
 number xi_l = 2*pi*k_l / L_l, and -Delta_N acts on it by |xi|^2.  The wave

@@ -1,5 +1,7 @@
 """Manufactured solution of the temporal-convergence test (Sec. 4.2).
 
+Test infrastructure: part of the float64 CPU oracle (see the package docstring).
+
 On (0, 2 pi)^2, m_e(x, t) = (sin(t+x) cos(t+y), cos(t+x) cos(t+y), sin(t+y)),
 a unit periodic field.  The forcing is obtained by substituting m_e, d_t m_e
 and Delta m_e into the tangent-plane equation

@@ -1,6 +1,8 @@
 """Nodal algebra of the skew/constraint block (Sec. 3.1, eqs. (Bi), (S),
 (Lambda); Sec. 3.2, eq. "inverse S").
 
+Test infrastructure: part of the float64 CPU oracle (see the package docstring).
+
 At node i the skew/constraint block acting on (v_i, r_i) is
 
     S~_i = [[Lambda_i, B_i^T], [-B_i, 0]],  B_i = m_i^T,  Lambda_i = [m_i]_x,

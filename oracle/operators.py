@@ -1,5 +1,7 @@
 """Matrix-free saddle operator and the split FFT-HSS preconditioner.
 
+Test infrastructure: part of the float64 CPU oracle (see the package docstring).
+
 * Saddle matrix (Sec. 2.4, eq. "saddle point system", with the (2,1) block
   -B as in the remark that follows it, and Sec. 3.1, eq. (HS)):
       A = [[H + S, B^T], [-B, 0]],  H = alpha I + theta k C_hat (-Delta_N),

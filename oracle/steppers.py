@@ -1,5 +1,7 @@
 """Time steppers, right-hand side, energy and midpoint diagnostics.
 
+Test infrastructure: part of the float64 CPU oracle (see the package docstring).
+
 * Projected implicit Euler (Sec. 2.4, eq. "total system 2"; Sec. 3.2, last
   paragraph): solve A(m^n) (v, r) = (f, 0) with theta = 1 and
   f = C_hat Delta_N m^n + (1 + alpha^2) h_low, then m_hat = m^n + k v and

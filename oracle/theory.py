@@ -1,5 +1,7 @@
 """Closed-form bounds of Sec. 3.4 (convergence analysis).
 
+Test infrastructure: part of the float64 CPU oracle (see the package docstring).
+
 * Corollary "Computable Fourier spectral enclosure": beta_N = alpha +
   theta k C_hat max|xi|^2, q_bar(lambda) = max(|lambda-alpha|/(lambda+alpha),
   |lambda-beta|/(lambda+beta)), minimized at lambda_bd = sqrt(alpha beta_N).
