@@ -200,10 +200,12 @@ hipError_t op_rhs_low(const Ctx& c, const llg_params* p, const double* m, double
   return op_field(c, field_for(c, p, 0.0, p->cexc, 1.0), EPI_RHS, na, m, b, st);
 }
 
-// Number of x-inverse blocks of a pipeline (one residual partial each).
+// Number of x-inverse blocks of a float64 pipeline (one residual partial
+// each); the launch shape is XCfg<double, nh> (pipeline_kernels.h).
 int xinv_blocks(const Ctx& c) {
   const int nh = c.geom.nh;
-  const int tpl = nh / plan_p(nh);
+  const int key = x_plan_key(8, nh);
+  const int tpl = nh / plan_p(key);
   const int lx = 64 / tpl;
   return int(((long long)c.ny * c.nz + lx - 1) / lx);
 }

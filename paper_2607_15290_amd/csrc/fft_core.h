@@ -62,11 +62,19 @@ __device__ __forceinline__ cx<T> mul_dir_i(cx<T> a) {
 //   N:   96 (P 24)  160 (P 20)  192 (P 24)  320 (P 20)  384 (P 24)
 //   R:  [8,4,3]    [4,4,2,5]   [8,8,3]     [4,4,4,5]   [8,4,4,3]
 // ---------------------------------------------------------------------------
+// A plan key is the line length N, or N | kPlanFine for a plan with fewer
+// points per thread (more threads per line, one more LDS exchange): the
+// float64 x passes use it at N = 128, 256 to halve their LDS per block.
+constexpr int kPlanFine = 1 << 16;
+__host__ __device__ constexpr int plan_n(int key) { return key & (kPlanFine - 1); }
+
 struct Plan {
   int p, nst, r0, r1, r2, r3;
 };
 __host__ __device__ constexpr Plan plan_of(int n) {
   switch (n) {
+    case 128 | kPlanFine: return {8, 3, 8, 4, 4, 1};
+    case 256 | kPlanFine: return {8, 3, 8, 8, 4, 1};
     case 2: return {2, 1, 2, 1, 1, 1};
     case 3: return {3, 1, 3, 1, 1, 1};
     case 4: return {4, 1, 4, 1, 1, 1};
@@ -95,7 +103,7 @@ __host__ __device__ constexpr Plan plan_of(int n) {
     default: return {0, 0, 1, 1, 1, 1};
   }
 }
-// true for the line lengths that have a plan
+// true for the plan keys that have a plan
 __host__ __device__ constexpr bool plan_ok(int n) { return plan_of(n).p > 0; }
 __host__ __device__ constexpr int plan_p(int n) { return plan_of(n).p; }
 __host__ __device__ constexpr int plan_stages(int n) { return plan_of(n).nst; }
@@ -108,17 +116,17 @@ __host__ __device__ constexpr int plan_ns(int n, int s) {
 }
 // Slot of input position t + TPL*q.  The first stage (radix R0, B0 = P/R0
 // butterflies per thread) reads position t + TPL*(b + r*B0) in slot b*R0 + r;
-// when R0 = P this is slot q.
-template <int N>
+// when R0 = P this is slot q.  (KEY: plan key, see kPlanFine.)
+template <int KEY>
 __device__ __forceinline__ constexpr int in_slot(int q) {
-  constexpr int B0 = plan_p(N) / plan_radix(N, 0);
-  return (q % B0) * plan_radix(N, 0) + q / B0;
+  constexpr int B0 = plan_p(KEY) / plan_radix(KEY, 0);
+  return (q % B0) * plan_radix(KEY, 0) + q / B0;
 }
 // position index q held by output slot s of the last stage
-template <int N>
+template <int KEY>
 __device__ __forceinline__ constexpr int out_q(int slot) {
-  constexpr int P = plan_p(N);
-  constexpr int R = plan_radix(N, plan_stages(N) - 1);
+  constexpr int P = plan_p(KEY);
+  constexpr int R = plan_radix(KEY, plan_stages(KEY) - 1);
   return (slot / R) + (slot % R) * (P / R);
 }
 
@@ -274,9 +282,10 @@ __device__ __forceinline__ void dft(cx<T>* v) {
 // go to (j/Ns)*Ns*R + j%Ns + r*Ns.  tw: table exp(-2 pi i m / N), m < N,
 // possibly a strided view (stride tws) of a longer table.
 // ---------------------------------------------------------------------------
-template <typename T, int N, int S, int DIR>
+template <typename T, int KEY, int S, int DIR>
 __device__ __forceinline__ void stage_compute(cx<T>* v, int t, const cx<T>* __restrict__ tw, int tws) {
-  constexpr int P = plan_p(N), TPL = N / P, R = plan_radix(N, S), B = P / R, NS = plan_ns(N, S);
+  constexpr int N = plan_n(KEY);
+  constexpr int P = plan_p(KEY), TPL = N / P, R = plan_radix(KEY, S), B = P / R, NS = plan_ns(KEY, S);
 #pragma unroll
   for (int b = 0; b < B; ++b) {
     if constexpr (NS > 1) {
@@ -298,32 +307,34 @@ __device__ __forceinline__ void stage_compute(cx<T>* v, int t, const cx<T>* __re
 }
 
 // Output position of slot (b*R + r) of stage S for thread t.
-template <int N, int S>
+template <int KEY, int S>
 __device__ __forceinline__ int stage_out_pos(int t, int slot) {
-  constexpr int P = plan_p(N), TPL = N / P, R = plan_radix(N, S), NS = plan_ns(N, S);
+  constexpr int N = plan_n(KEY);
+  constexpr int P = plan_p(KEY), TPL = N / P, R = plan_radix(KEY, S), NS = plan_ns(KEY, S);
   const int b = slot / R, r = slot % R;
   const int j = t + TPL * b;
   return (j / NS) * NS * R + (j % NS) + r * NS;
 }
 // Input position of slot (b*R + r) of stage S for thread t.
-template <int N, int S>
+template <int KEY, int S>
 __device__ __forceinline__ int stage_in_pos(int t, int slot) {
-  constexpr int P = plan_p(N), TPL = N / P, R = plan_radix(N, S);
+  constexpr int N = plan_n(KEY);
+  constexpr int P = plan_p(KEY), TPL = N / P, R = plan_radix(KEY, S);
   const int b = slot / R, r = slot % R;
   return t + TPL * b + r * (N / R);
 }
 
 // Exchange through LDS between stage S-1 and stage S, then compute stage S.
-template <typename T, int N, int S, int DIR, class Lds>
+template <typename T, int KEY, int S, int DIR, class Lds>
 __device__ __forceinline__ void next_stage(cx<T>* v, int t, Lds lds, const cx<T>* __restrict__ tw, int tws) {
-  constexpr int P = plan_p(N);
+  constexpr int P = plan_p(KEY);
   __syncthreads();
 #pragma unroll
-  for (int s = 0; s < P; ++s) lds(stage_out_pos<N, S - 1>(t, s)) = v[s];
+  for (int s = 0; s < P; ++s) lds(stage_out_pos<KEY, S - 1>(t, s)) = v[s];
   __syncthreads();
 #pragma unroll
-  for (int s = 0; s < P; ++s) v[s] = lds(stage_in_pos<N, S>(t, s));
-  stage_compute<T, N, S, DIR>(v, t, tw, tws);
+  for (int s = 0; s < P; ++s) v[s] = lds(stage_in_pos<KEY, S>(t, s));
+  stage_compute<T, KEY, S, DIR>(v, t, tw, tws);
 }
 
 // Full line FFT on registers, exchanging through LDS between stages.
@@ -332,14 +343,14 @@ __device__ __forceinline__ void next_stage(cx<T>* v, int t, Lds lds, const cx<T>
 // ends with the output pattern (slot s <-> position t + TPL out_q(s)).
 // Contains block barriers when there is more than one stage: every thread of
 // the block must call it the same number of times.
-template <typename T, int N, int DIR, class Lds>
+template <typename T, int KEY, int DIR, class Lds>
 __device__ __forceinline__ void line_fft(cx<T>* v, int t, Lds lds, const cx<T>* __restrict__ tw, int tws) {
-  constexpr int NST = plan_stages(N);
-  static_assert(plan_ok(N), "no FFT plan for this length");
-  stage_compute<T, N, 0, DIR>(v, t, tw, tws);
-  if constexpr (NST > 1) next_stage<T, N, 1, DIR>(v, t, lds, tw, tws);
-  if constexpr (NST > 2) next_stage<T, N, 2, DIR>(v, t, lds, tw, tws);
-  if constexpr (NST > 3) next_stage<T, N, 3, DIR>(v, t, lds, tw, tws);
+  constexpr int NST = plan_stages(KEY);
+  static_assert(plan_ok(KEY), "no FFT plan for this length");
+  stage_compute<T, KEY, 0, DIR>(v, t, tw, tws);
+  if constexpr (NST > 1) next_stage<T, KEY, 1, DIR>(v, t, lds, tw, tws);
+  if constexpr (NST > 2) next_stage<T, KEY, 2, DIR>(v, t, lds, tw, tws);
+  if constexpr (NST > 3) next_stage<T, KEY, 3, DIR>(v, t, lds, tw, tws);
 }
 
 }  // namespace llg

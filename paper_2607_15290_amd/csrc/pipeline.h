@@ -34,6 +34,13 @@ namespace llg {
   X(4) X(6) X(8) X(10) X(12) X(16) X(20) X(24) X(32) X(40) X(48) X(64) X(80) X(96) X(128) X(160) X(192) \
   X(256) X(320) X(384) X(512)
 
+// FFT plan key of the x passes for elements of elem_bytes bytes and half-length
+// nh: the float64 passes at nh = 128, 256 take the finer plan (fewer points
+// per thread, half the LDS per block; see kPlanFine).
+__host__ __device__ constexpr int x_plan_key(int elem_bytes, int nh) {
+  return (elem_bytes == 8 && (nh == 128 || nh == 256)) ? (nh | kPlanFine) : nh;
+}
+
 inline bool nh_supported(int n) {
 #define LLG_EQ(v) || n == v
   return false LLG_FOR_NH(LLG_EQ);

@@ -17,9 +17,13 @@
 
 namespace llg {
 
-template <int NH>
+// Launch shape of the x passes for element type T and half-length NH.  The
+// float64 passes at NH = 128, 256 use the finer plan (8 points per thread):
+// half the lines per block, half the LDS, twice the blocks per CU.
+template <typename T, int NH>
 struct XCfg {
-  static constexpr int P = plan_p(NH);
+  static constexpr int KEY = x_plan_key(int(sizeof(T)), NH);
+  static constexpr int P = plan_p(KEY);
   static constexpr int TPL = NH / P;
   static constexpr int LX = 64 / TPL;           // rows per block
   static constexpr int NT = 192;                // 3 fields x LX rows x TPL
@@ -319,7 +323,7 @@ template <typename T, typename TIn, int NH, int PRO>
 __global__ __launch_bounds__(192) void k_xfwd(const TIn* __restrict__ in, const T* __restrict__ m,
                                               cx<T>* __restrict__ spec, SpecGeom g, NodalArgs na,
                                               const cx<T>* __restrict__ twx) {
-  using C = XCfg<NH>;
+  using C = XCfg<T, NH>;
   __shared__ cx<T> lds[3 * C::LX * C::SL];
   const int tid = threadIdx.x;
   const long long nlines = (long long)g.ny * g.nz;
@@ -368,11 +372,11 @@ __global__ __launch_bounds__(192) void k_xfwd(const TIn* __restrict__ in, const 
   auto acc = [line_lds](int pos) -> cx<T>& { return line_lds[xphys(pos)]; };
   cx<T> v[C::P];
 #pragma unroll
-  for (int q = 0; q < C::P; ++q) v[in_slot<NH>(q)] = acc(t + C::TPL * q);
-  line_fft<T, NH, -1>(v, t, acc, twx, 2);
+  for (int q = 0; q < C::P; ++q) v[in_slot<C::KEY>(q)] = acc(t + C::TPL * q);
+  line_fft<T, C::KEY, -1>(v, t, acc, twx, 2);
   __syncthreads();
 #pragma unroll
-  for (int s = 0; s < C::P; ++s) acc(t + C::TPL * out_q<NH>(s)) = v[s];
+  for (int s = 0; s < C::P; ++s) acc(t + C::TPL * out_q<C::KEY>(s)) = v[s];
   __syncthreads();
 
   // split step: U[k] = E[k] + w^k O[k], E/O the DFTs of even/odd samples
@@ -399,7 +403,7 @@ __global__ __launch_bounds__(192) void k_xfwd(const TIn* __restrict__ in, const 
 template <typename T, typename TIn, typename TOut, int NH, int EPI>
 __global__ __launch_bounds__(192) void k_xinv(PipeIO<T, TIn, TOut> io, const cx<T>* __restrict__ spec,
                                               SpecGeom g, NodalArgs na, const cx<T>* __restrict__ twx) {
-  using C = XCfg<NH>;
+  using C = XCfg<T, NH>;
   __shared__ cx<T> lds[3 * C::LX * C::SL];
   const int tid = threadIdx.x;
   const long long nlines = (long long)g.ny * g.nz;
@@ -438,12 +442,12 @@ __global__ __launch_bounds__(192) void k_xinv(PipeIO<T, TIn, TOut> io, const cx<
     const cx<T> e{a.x + bc.x, a.y - bc.y};
     const cx<T> d{a.x - bc.x, a.y + bc.y};
     const cx<T> o = cmulc(d, twx[k]);
-    v[in_slot<NH>(q)] = {e.x - o.y, e.y + o.x};
+    v[in_slot<C::KEY>(q)] = {e.x - o.y, e.y + o.x};
   }
-  line_fft<T, NH, 1>(v, t, acc, twx, 2);
+  line_fft<T, C::KEY, 1>(v, t, acc, twx, 2);
   __syncthreads();
 #pragma unroll
-  for (int s = 0; s < C::P; ++s) acc(t + C::TPL * out_q<NH>(s)) = v[s];
+  for (int s = 0; s < C::P; ++s) acc(t + C::TPL * out_q<C::KEY>(s)) = v[s];
   __syncthreads();
 
   // Epilogue: clamped (unconditional) loads issued a batch of node pairs at

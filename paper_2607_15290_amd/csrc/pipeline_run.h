@@ -30,7 +30,7 @@ constexpr bool has_epi(int epi) {
 template <typename T, typename TIn, typename TOut, int NH, int PRO>
 void launch_xfwd(const Ctx& c, const NodalArgs& na, const PipeIO<T, TIn, TOut>& io, hipStream_t st) {
   if constexpr (has_pro<T, TIn, TOut>(PRO)) {
-    using C = XCfg<NH>;
+    using C = XCfg<T, NH>;
     const long long lines = (long long)c.ny * c.nz;
     const unsigned grid = (unsigned)((lines + C::LX - 1) / C::LX);
     const cx<T>* tw;
@@ -45,7 +45,7 @@ void launch_xfwd(const Ctx& c, const NodalArgs& na, const PipeIO<T, TIn, TOut>& 
 template <typename T, typename TIn, typename TOut, int NH, int EPI>
 void launch_xinv(const Ctx& c, const NodalArgs& na, const PipeIO<T, TIn, TOut>& io, hipStream_t st) {
   if constexpr (has_epi<T, TIn, TOut>(EPI)) {
-    using C = XCfg<NH>;
+    using C = XCfg<T, NH>;
     const long long lines = (long long)c.ny * c.nz;
     const unsigned grid = (unsigned)((lines + C::LX - 1) / C::LX);
     const cx<T>* tw;
