@@ -637,12 +637,7 @@ llg_status gmres_ir(const Ctx& c, const llg_params* p, const double* m, const do
       double* Q = w.V;
       double* W = w.V + size_t(R + 1) * n4;
       auto op = [&](int j, const double* u, double* wout) -> hipError_t {
-        float* zj = w.Z + size_t(j) * n4;
-        PipeIO<float, double, float> io_ap{u, w.m32, zj, c.ng, nullptr, nullptr};
-        hipError_t e = run_pipeline<float, double, float>(c, PRO_COPY3, EPI_APPLY, sym_ap, na, io_ap, st);
-        if (e != hipSuccess) return e;
-        PipeIO<float, float, double> io_mv{zj, w.m32, wout, c.ng, nullptr, nullptr};
-        return run_pipeline<float, float, double>(c, PRO_COPY3, EPI_MATVEC, sym_mv, na, io_mv, st);
+        return run_apply_matvec(c, sym_ap, sym_mv, na, u, w.m32, w.Z + size_t(j) * n4, wout, st);
       };
       CycleResult cr;
       // u_0 = r (the residual buffer is consumed as the cycle's start vector)
@@ -660,11 +655,8 @@ llg_status gmres_ir(const Ctx& c, const llg_params* p, const double* m, const do
     hs.g[0] = rho;
     int k = 0;
     for (int j = 0; j < R; ++j) {
-      float* zj = w.Z + size_t(j) * n4;
-      PipeIO<float, double, float> io_ap{w.V + size_t(j) * n4, w.m32, zj, c.ng, nullptr, nullptr};
-      CHK((run_pipeline<float, double, float>(c, PRO_COPY3, EPI_APPLY, sym_ap, na, io_ap, st)));
-      PipeIO<float, float, double> io_mv{zj, w.m32, w.V + size_t(j + 1) * n4, c.ng, nullptr, nullptr};
-      CHK((run_pipeline<float, float, double>(c, PRO_COPY3, EPI_MATVEC, sym_mv, na, io_mv, st)));
+      CHK(run_apply_matvec(c, sym_ap, sym_mv, na, w.V + size_t(j) * n4, w.m32, w.Z + size_t(j) * n4,
+                           w.V + size_t(j + 1) * n4, st));
       CHK_STATUS(arnoldi_step(c, w.V, n4, j, col.data(), st));
       const double gres = hs.add_column(j, col.data());
       res.iters++;

@@ -31,7 +31,7 @@ constexpr int kMaxDots = 64;
 enum KernelKind : int {
   KK_XFWD = 0, KK_AXIS_FWD, KK_AXIS_FUSED, KK_AXIS_INV, KK_XINV, KK_CGS_DOTS, KK_CGS_UPDATE_DOTS,
   KK_CGS_UPDATE_NORM, KK_REDUCE, KK_SCALE, KK_AXPBY, KK_LINCOMB, KK_CONVERT, KK_DOT2, KK_NODAL, KK_FIELD3,
-  KK_COUNT
+  KK_XMID, KK_COUNT
 };
 const char* kernel_kind_name(int k);
 
@@ -71,6 +71,12 @@ SymArgs sym_for(const Ctx& c, double a, double b, bool invert);
 template <typename T, typename TIn, typename TOut>
 hipError_t run_pipeline(const Ctx& c, int pro, int epi, const SymArgs& sym, const NodalArgs& na,
                         const PipeIO<T, TIn, TOut>& io, hipStream_t st);
+
+// Precision-form inner operator (pipeline_f32.hip): z = M^{-1} v (float32,
+// stored) and w = A z (float32, float64 result), the two pipelines joined by
+// one fused x pass.
+hipError_t run_apply_matvec(const Ctx& c, const SymArgs& sym_ap, const SymArgs& sym_mv, const NodalArgs& na,
+                            const double* v, const float* m32, float* z, double* w, hipStream_t st);
 
 // Lower-order field pipeline (field.hip, float64): forward DFTs of three
 // planes, the 3x3 multiplier of FieldArgs, inverse DFTs, then the x-inverse

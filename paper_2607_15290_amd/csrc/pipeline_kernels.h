@@ -317,6 +317,96 @@ __device__ __forceinline__ void epilogue_compute(const EpiRaw<T, TIn, TOut, EPI>
 }
 
 // ---------------------------------------------------------------------------
+// Shared phases of the x passes (every thread of the block calls them; they
+// contain block barriers).  lds holds 3 fields x LX lines x SL complex.
+// ---------------------------------------------------------------------------
+// LDS holds the real node pairs (u[2k], u[2k+1]) of each line at position k:
+// half-length complex DFT, split step U[k] = E[k] + w^k O[k] (E/O the DFTs of
+// the even/odd samples), store of the rows of three half spectra.
+template <typename T, int NH>
+__device__ __forceinline__ void x_r2c_store(cx<T>* lds, long long line0, long long nlines,
+                                            cx<T>* __restrict__ spec, const SpecGeom& g,
+                                            const cx<T>* __restrict__ twx) {
+  using C = XCfg<T, NH>;
+  const int tid = threadIdx.x;
+  const int t = tid % C::TPL, ln = tid / C::TPL;
+  cx<T>* line_lds = lds + ln * C::SL;
+  auto acc = [line_lds](int pos) -> cx<T>& { return line_lds[xphys(pos)]; };
+  cx<T> v[C::P];
+#pragma unroll
+  for (int q = 0; q < C::P; ++q) v[in_slot<C::KEY>(q)] = acc(t + C::TPL * q);
+  line_fft<T, C::KEY, -1>(v, t, acc, twx, 2);
+  __syncthreads();
+#pragma unroll
+  for (int s = 0; s < C::P; ++s) acc(t + C::TPL * out_q<C::KEY>(s)) = v[s];
+  __syncthreads();
+  constexpr int CS = 3 * (NH + 1);
+  for (int e = tid; e < C::LX * CS; e += C::NT) {
+    const int l = e / CS, col = e % CS;
+    const long long line = line0 + l;
+    if (line >= nlines) continue;
+    const int f = col / (NH + 1), k = col % (NH + 1);
+    const cx<T>* Z = lds + (f * C::LX + l) * C::SL;
+    const cx<T> a = Z[xphys(k == NH ? 0 : k)];
+    const cx<T> bc = Z[xphys(k == 0 ? 0 : NH - k)];
+    const cx<T> b{bc.x, -bc.y};
+    const cx<T> E{T(0.5) * (a.x + b.x), T(0.5) * (a.y + b.y)};
+    const cx<T> O{T(0.5) * (a.y - b.y), T(-0.5) * (a.x - b.x)};
+    const cx<T> w = twx[k];
+    spec[line * g.rs + col] = cadd(E, cmul(w, O));
+  }
+}
+
+// Load the rows of three half spectra of the block's lines, undo the split
+// step (Z[k] = (U[k] + conj U[NH-k]) + i w^{-k} (U[k] - conj U[NH-k])) and run
+// the inverse half-length DFT; on return LDS position k of each line holds the
+// node pair (2k, 2k+1) of each field.
+template <typename T, int NH>
+__device__ __forceinline__ void x_load_c2r(cx<T>* lds, long long line0, long long nlines,
+                                           const cx<T>* __restrict__ spec, const SpecGeom& g,
+                                           const cx<T>* __restrict__ twx) {
+  using C = XCfg<T, NH>;
+  const int tid = threadIdx.x;
+  constexpr int CS = 3 * (NH + 1);
+  {
+    constexpr int NV = C::LX * CS;
+    constexpr int ITERS = (NV + C::NT - 1) / C::NT;
+#pragma unroll
+    for (int it = 0; it < ITERS; ++it) {
+      const int e0 = tid + it * C::NT;
+      const int e = e0 < NV ? e0 : NV - 1;
+      const int l = e / CS, col = e % CS;
+      const long long line = line0 + l < nlines ? line0 + l : nlines - 1;
+      const cx<T> val = spec[line * g.rs + col];
+      if (e0 < NV) {
+        const int f = col / (NH + 1), k = col % (NH + 1);
+        lds[(f * C::LX + l) * C::SL + xphys(k)] = line0 + l < nlines ? val : cx<T>{T(0), T(0)};
+      }
+    }
+  }
+  __syncthreads();
+  const int t = tid % C::TPL, ln = tid / C::TPL;
+  cx<T>* line_lds = lds + ln * C::SL;
+  auto acc = [line_lds](int pos) -> cx<T>& { return line_lds[xphys(pos)]; };
+  cx<T> v[C::P];
+#pragma unroll
+  for (int q = 0; q < C::P; ++q) {
+    const int k = t + C::TPL * q;
+    const cx<T> a = acc(k);
+    const cx<T> bc = acc(NH - k);
+    const cx<T> e{a.x + bc.x, a.y - bc.y};
+    const cx<T> d{a.x - bc.x, a.y + bc.y};
+    const cx<T> o = cmulc(d, twx[k]);
+    v[in_slot<C::KEY>(q)] = {e.x - o.y, e.y + o.x};
+  }
+  line_fft<T, C::KEY, 1>(v, t, acc, twx, 2);
+  __syncthreads();
+#pragma unroll
+  for (int s = 0; s < C::P; ++s) acc(t + C::TPL * out_q<C::KEY>(s)) = v[s];
+  __syncthreads();
+}
+
+// ---------------------------------------------------------------------------
 // k_xfwd
 // ---------------------------------------------------------------------------
 template <typename T, typename TIn, int NH, int PRO>
@@ -366,35 +456,7 @@ __global__ __launch_bounds__(192) void k_xfwd(const TIn* __restrict__ in, const 
     }
   }
   __syncthreads();
-
-  const int t = tid % C::TPL, ln = tid / C::TPL;
-  cx<T>* line_lds = lds + ln * C::SL;
-  auto acc = [line_lds](int pos) -> cx<T>& { return line_lds[xphys(pos)]; };
-  cx<T> v[C::P];
-#pragma unroll
-  for (int q = 0; q < C::P; ++q) v[in_slot<C::KEY>(q)] = acc(t + C::TPL * q);
-  line_fft<T, C::KEY, -1>(v, t, acc, twx, 2);
-  __syncthreads();
-#pragma unroll
-  for (int s = 0; s < C::P; ++s) acc(t + C::TPL * out_q<C::KEY>(s)) = v[s];
-  __syncthreads();
-
-  // split step: U[k] = E[k] + w^k O[k], E/O the DFTs of even/odd samples
-  constexpr int CS = 3 * (NH + 1);
-  for (int e = tid; e < C::LX * CS; e += C::NT) {
-    const int l = e / CS, col = e % CS;
-    const long long line = line0 + l;
-    if (line >= nlines) continue;
-    const int f = col / (NH + 1), k = col % (NH + 1);
-    const cx<T>* Z = lds + (f * C::LX + l) * C::SL;
-    const cx<T> a = Z[xphys(k == NH ? 0 : k)];
-    const cx<T> bc = Z[xphys(k == 0 ? 0 : NH - k)];
-    const cx<T> b{bc.x, -bc.y};
-    const cx<T> E{T(0.5) * (a.x + b.x), T(0.5) * (a.y + b.y)};
-    const cx<T> O{T(0.5) * (a.y - b.y), T(-0.5) * (a.x - b.x)};
-    const cx<T> w = twx[k];
-    spec[line * g.rs + col] = cadd(E, cmul(w, O));
-  }
+  x_r2c_store<T, NH>(lds, line0, nlines, spec, g, twx);
 }
 
 // ---------------------------------------------------------------------------
@@ -411,44 +473,7 @@ __global__ __launch_bounds__(192) void k_xinv(PipeIO<T, TIn, TOut> io, const cx<
   constexpr int NX = 2 * NH;
   constexpr int CS = 3 * (NH + 1);
 
-  {
-    constexpr int NV = C::LX * CS;
-    constexpr int ITERS = (NV + C::NT - 1) / C::NT;
-#pragma unroll
-    for (int it = 0; it < ITERS; ++it) {
-      const int e0 = tid + it * C::NT;
-      const int e = e0 < NV ? e0 : NV - 1;
-      const int l = e / CS, col = e % CS;
-      const long long line = line0 + l < nlines ? line0 + l : nlines - 1;
-      const cx<T> val = spec[line * g.rs + col];
-      if (e0 < NV) {
-        const int f = col / (NH + 1), k = col % (NH + 1);
-        lds[(f * C::LX + l) * C::SL + xphys(k)] = line0 + l < nlines ? val : cx<T>{T(0), T(0)};
-      }
-    }
-  }
-  __syncthreads();
-
-  const int t = tid % C::TPL, ln = tid / C::TPL;
-  cx<T>* line_lds = lds + ln * C::SL;
-  auto acc = [line_lds](int pos) -> cx<T>& { return line_lds[xphys(pos)]; };
-  cx<T> v[C::P];
-#pragma unroll
-  for (int q = 0; q < C::P; ++q) {
-    // Z[k] = (U[k] + conj U[NH-k]) + i w^{-k} (U[k] - conj U[NH-k])
-    const int k = t + C::TPL * q;
-    const cx<T> a = acc(k);
-    const cx<T> bc = acc(NH - k);
-    const cx<T> e{a.x + bc.x, a.y - bc.y};
-    const cx<T> d{a.x - bc.x, a.y + bc.y};
-    const cx<T> o = cmulc(d, twx[k]);
-    v[in_slot<C::KEY>(q)] = {e.x - o.y, e.y + o.x};
-  }
-  line_fft<T, C::KEY, 1>(v, t, acc, twx, 2);
-  __syncthreads();
-#pragma unroll
-  for (int s = 0; s < C::P; ++s) acc(t + C::TPL * out_q<C::KEY>(s)) = v[s];
-  __syncthreads();
+  x_load_c2r<T, NH>(lds, line0, nlines, spec, g, twx);
 
   // Epilogue: clamped (unconditional) loads issued a batch of node pairs at
   // a time, predicated stores.
@@ -517,6 +542,75 @@ __global__ __launch_bounds__(192) void k_xinv(PipeIO<T, TIn, TOut> io, const cx<
       io.red[blockIdx.x] = t;
     }
   }
+}
+
+// ---------------------------------------------------------------------------
+// k_xmid: the junction of the precision form's two float32 pipelines.  One
+// kernel finishes the preconditioner apply (C2R along x, closed-form nodal
+// inverse, z = M^{-1} v written as the flexible basis vector) and starts the
+// matvec on z (R2C along x of z's velocity planes), handing z over in LDS:
+// the matvec's x-forward pass and its read of z disappear.  Each node pair
+// is owned by one thread, which reads the apply's field from an LDS slot and
+// writes z back into the same slot.
+// ---------------------------------------------------------------------------
+template <int NH>
+__global__ __launch_bounds__(192) void k_xmid(PipeIO<float, double, float> io, cx<float>* __restrict__ spec,
+                                              SpecGeom g, NodalArgs na, const cx<float>* __restrict__ twx) {
+  using T = float;
+  using C = XCfg<T, NH>;
+  __shared__ cx<T> lds[3 * C::LX * C::SL];
+  const int tid = threadIdx.x;
+  const long long nlines = (long long)g.ny * g.nz;
+  const long long line0 = (long long)blockIdx.x * C::LX;
+  constexpr int NX = 2 * NH;
+  x_load_c2r<T, NH>(lds, line0, nlines, spec, g, twx);
+
+  constexpr int NPAIR = C::LX * NH;
+  constexpr int ITERS = (NPAIR + C::NT - 1) / C::NT;
+  constexpr int BATCH = LLG_XBATCH_F32;
+#pragma unroll
+  for (int it0 = 0; it0 < ITERS; it0 += BATCH) {
+    EpiRaw<T, double, T, EPI_APPLY> raw[BATCH];
+#pragma unroll
+    for (int b = 0; b < BATCH; ++b) {
+      if (it0 + b < ITERS) {
+        const int e0 = tid + (it0 + b) * C::NT;
+        const int e = e0 < NPAIR ? e0 : NPAIR - 1;
+        const int l = e / NH, xp = e % NH;
+        const long long line = line0 + l < nlines ? line0 + l : nlines - 1;
+        epilogue_load<T, double, T, EPI_APPLY>(io, na, line * NX + 2 * xp, raw[b]);
+      }
+    }
+#pragma unroll
+    for (int b = 0; b < BATCH; ++b) {
+      if (it0 + b >= ITERS) continue;
+      const int e0 = tid + (it0 + b) * C::NT;
+      if (e0 >= NPAIR) continue;  // clamped duplicate: neither stored nor handed over
+      const int l = e0 / NH, xp = e0 % NH;
+      const bool live = line0 + l < nlines;
+      const long long line = live ? line0 + l : nlines - 1;
+      const long long i = line * NX + 2 * xp;
+      cx<T> fz[3];
+#pragma unroll
+      for (int f = 0; f < 3; ++f) fz[f] = lds[(f * C::LX + l) * C::SL + xphys(xp)];
+      T o0[4], o1[4];
+      {
+        const T F0[3] = {fz[0].x, fz[1].x, fz[2].x};
+        epilogue_compute<T, double, T, EPI_APPLY>(raw[b], 0, F0, na, o0);
+        const T F1[3] = {fz[0].y, fz[1].y, fz[2].y};
+        epilogue_compute<T, double, T, EPI_APPLY>(raw[b], 1, F1, na, o1);
+      }
+      if (live) {
+#pragma unroll
+        for (int f = 0; f < 4; ++f) store2(io.out + f * io.ng + i, o0[f], o1[f]);
+      }
+#pragma unroll
+      for (int f = 0; f < 3; ++f)
+        lds[(f * C::LX + l) * C::SL + xphys(xp)] = live ? cx<T>{o0[f], o1[f]} : cx<T>{T(0), T(0)};
+    }
+  }
+  __syncthreads();
+  x_r2c_store<T, NH>(lds, line0, nlines, spec, g, twx);
 }
 
 // ---------------------------------------------------------------------------

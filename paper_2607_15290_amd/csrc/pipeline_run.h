@@ -102,6 +102,44 @@ hipError_t run_nh(const Ctx& c, int pro, int epi, const SymArgs& sym, const Noda
   return hipGetLastError();
 }
 
+// Axis passes of one pipeline on the spectral buffer: y forward, z fused,
+// y inverse (3D) or y fused (2D).
+template <typename T>
+hipError_t run_axes(const Ctx& c, const SymArgs& sym, hipStream_t st) {
+  cx<T>* spec = reinterpret_cast<cx<T>*>(c.spec);
+  hipError_t e;
+  if (c.dim == 2) return launch_axis<T>(c, 1, 2, sym, spec, st);
+  if ((e = launch_axis<T>(c, 1, 0, sym, spec, st)) != hipSuccess) return e;
+  if ((e = launch_axis<T>(c, 2, 2, sym, spec, st)) != hipSuccess) return e;
+  return launch_axis<T>(c, 1, 1, sym, spec, st);
+}
+
+// One inner iteration's operator of the precision form: z = M^{-1} v in
+// float32 (z kept as the flexible basis vector) and w = A z in float32 with a
+// float64 result; the junction of the two pipelines is the fused k_xmid pass.
+template <int NH>
+hipError_t run_apply_matvec_nh(const Ctx& c, const SymArgs& sym_ap, const SymArgs& sym_mv, const NodalArgs& na,
+                               const double* v, const float* m32, float* z, double* w, hipStream_t st) {
+  using C = XCfg<float, NH>;
+  PipeIO<float, double, float> io_ap{v, m32, z, c.ng, nullptr, nullptr};
+  PipeIO<float, float, double> io_mv{z, m32, w, c.ng, nullptr, nullptr};
+  launch_xfwd<float, double, float, NH, PRO_COPY3>(c, na, io_ap, st);
+  hipError_t e;
+  if ((e = run_axes<float>(c, sym_ap, st)) != hipSuccess) return e;
+  {
+    const long long lines = (long long)c.ny * c.nz;
+    const unsigned grid = (unsigned)((lines + C::LX - 1) / C::LX);
+    const double bytes = 2.0 * double(c.geom.cs) * lines * sizeof(cx<float>) + double(c.ng) * (8.0 + 12.0 + 16.0);
+    ProfScope ps(c.prof, st, KK_XMID, bytes);
+    hipLaunchKernelGGL((k_xmid<NH>), dim3(grid), dim3(C::NT), 0, st, io_ap, reinterpret_cast<cx<float>*>(c.spec),
+                       c.geom, na, c.tw_f[0]);
+    if ((e = hipGetLastError()) != hipSuccess) return e;
+  }
+  if ((e = run_axes<float>(c, sym_mv, st)) != hipSuccess) return e;
+  launch_xinv<float, float, double, NH, EPI_MATVEC>(c, na, io_mv, st);
+  return hipGetLastError();
+}
+
 template <typename T, typename TIn, typename TOut>
 hipError_t run_pipeline(const Ctx& c, int pro, int epi, const SymArgs& sym, const NodalArgs& na,
                         const PipeIO<T, TIn, TOut>& io, hipStream_t st) {

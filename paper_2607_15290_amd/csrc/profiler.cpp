@@ -48,7 +48,8 @@ struct Profiler {
 static const char* kNames[KK_COUNT] = {"xfwd",      "axis_fwd",          "axis_fused",        "axis_inv",
                                        "xinv",      "cgs_dots",          "cgs_update_dots",   "cgs_update_norm",
                                        "reduce",    "scale",             "axpby",             "lincomb",
-                                       "convert",   "dot2",              "nodal",             "field3"};
+                                       "convert",   "dot2",              "nodal",             "field3",
+                                       "xmid"};
 
 const char* kernel_kind_name(int k) { return (k >= 0 && k < KK_COUNT) ? kNames[k] : "?"; }
 
