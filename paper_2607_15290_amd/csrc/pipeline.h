@@ -41,6 +41,15 @@ __host__ __device__ constexpr int x_plan_key(int elem_bytes, int nh) {
   return (elem_bytes == 8 && (nh == 128 || nh == 256)) ? (nh | kPlanFine) : nh;
 }
 
+// FFT plan key of the y / z passes: with LLG_AXIS_FINE_F64 the float64
+// passes at N = 256 take the finer plan as well.
+#ifndef LLG_AXIS_FINE_F64
+#define LLG_AXIS_FINE_F64 0
+#endif
+__host__ __device__ constexpr int axis_plan_key(int elem_bytes, int n) {
+  return (LLG_AXIS_FINE_F64 && elem_bytes == 8 && n == 256) ? (n | kPlanFine) : n;
+}
+
 inline bool nh_supported(int n) {
 #define LLG_EQ(v) || n == v
   return false LLG_FOR_NH(LLG_EQ);

@@ -623,10 +623,10 @@ __host__ __device__ constexpr int axis_w(int n) {
 }
 
 template <typename T, int N, int MODE>
-__global__ __launch_bounds__(axis_w(N) * (N / plan_p(N))) void k_axis(cx<T>* __restrict__ spec, SpecGeom g,
-                                                                      int axis, SymArgs sym,
-                                                                      const cx<T>* __restrict__ tw) {
-  constexpr int P = plan_p(N), TPL = N / P, W = axis_w(N);
+__global__ __launch_bounds__(axis_w(N) * (N / plan_p(axis_plan_key(int(sizeof(T)), N)))) void k_axis(
+    cx<T>* __restrict__ spec, SpecGeom g, int axis, SymArgs sym, const cx<T>* __restrict__ tw) {
+  constexpr int KEY = axis_plan_key(int(sizeof(T)), N);
+  constexpr int P = plan_p(KEY), TPL = N / P, W = axis_w(N);
   __shared__ cx<T> lds[N * (W + 1)];
   const int c = threadIdx.x % W, t = threadIdx.x / W;
   const int col = blockIdx.x * W + c;
@@ -643,7 +643,7 @@ __global__ __launch_bounds__(axis_w(N) * (N / plan_p(N))) void k_axis(cx<T>* __r
   cx<T>* base = spec + outer * so + (valid ? col : 0);
   cx<T> v[P];
 #pragma unroll
-  for (int q = 0; q < P; ++q) v[in_slot<N>(q)] = base[(t + TPL * q) * sp];
+  for (int q = 0; q < P; ++q) v[in_slot<KEY>(q)] = base[(t + TPL * q) * sp];
   if (!valid) {
 #pragma unroll
     for (int q = 0; q < P; ++q) v[q] = cx<T>{T(0), T(0)};
@@ -652,9 +652,9 @@ __global__ __launch_bounds__(axis_w(N) * (N / plan_p(N))) void k_axis(cx<T>* __r
   auto acc = [col_lds](int pos) -> cx<T>& { return col_lds[pos * (W + 1)]; };
 
   if constexpr (MODE == 0 || MODE == 1) {
-    line_fft<T, N, MODE == 0 ? -1 : 1>(v, t, acc, tw, 1);
+    line_fft<T, KEY, MODE == 0 ? -1 : 1>(v, t, acc, tw, 1);
   } else {
-    line_fft<T, N, -1>(v, t, acc, tw, 1);
+    line_fft<T, KEY, -1>(v, t, acc, tw, 1);
     // Fourier multiplier (a + b |xi|^2)^{+-1} / N_g
     const int kx = col % (g.nh + 1);
     const double xx = sym.cx * kx;
@@ -668,22 +668,22 @@ __global__ __launch_bounds__(axis_w(N) * (N / plan_p(N))) void k_axis(cx<T>* __r
     cx<T> w[P];
 #pragma unroll
     for (int s = 0; s < P; ++s) {
-      const int q = out_q<N>(s);
+      const int q = out_q<KEY>(s);
       const int kp = t + TPL * q;
       const int ks = kp < N / 2 ? kp : kp - N;
       const double aa = caxis * ks;
       const double lam2 = base2 + aa * aa;
       double mult = sym.a + sym.b * lam2;
       mult = sym.invert ? sym.inv_ng / mult : sym.inv_ng * mult;
-      w[in_slot<N>(q)] = cscale(v[s], T(mult));
+      w[in_slot<KEY>(q)] = cscale(v[s], T(mult));
     }
-    line_fft<T, N, 1>(w, t, acc, tw, 1);
+    line_fft<T, KEY, 1>(w, t, acc, tw, 1);
 #pragma unroll
     for (int s = 0; s < P; ++s) v[s] = w[s];
   }
   if (valid) {
 #pragma unroll
-    for (int s = 0; s < P; ++s) base[(t + TPL * out_q<N>(s)) * sp] = v[s];
+    for (int s = 0; s < P; ++s) base[(t + TPL * out_q<KEY>(s)) * sp] = v[s];
   }
 }
 
