@@ -238,7 +238,7 @@ llg_status fetch(const Ctx& c, const double* dev, int n, hipStream_t st, double*
 size_t align256(size_t b) { return (b + 255) & ~size_t(255); }
 
 struct Work {
-  double* V = nullptr;   // (R + 2) x n4: basis, plus the delayed-CGS2 u and w
+  double* V = nullptr;   // (R + 2) x n4: basis (R + 1 columns) and the Arnoldi operator output
   double* r = nullptr;   // n4
   double* t = nullptr;   // n4 temporary
   float* Z = nullptr;    // R x n4 (precision form)
@@ -344,35 +344,40 @@ llg_status arnoldi_step(const Ctx& c, double* V, long long n4, int j, double* co
 // iteration: two streaming passes over the basis and one host round trip per
 // iteration.
 //
-// U holds the start vector u_0 on entry (not normalized), c0 = ||u_0||^2.
-// Entering iteration j the host knows a = Q_j^T u_j and beta_j =
-// ||u_j - Q_j a|| (from the previous update pass), which finalizes column
+// The device holds the raw directions U = [u_0 .. u_j] (u_0 = the start
+// vector, not normalized, at u0; u_i, i >= 1, at U1 + (i - 1) n4); the
+// orthonormal basis is Q = U T^{-1}, T upper triangular with column j =
+// [a; beta_j].  Entering iteration j the host knows a = Q_j^T u_j and beta_j
+// = ||u_j - Q_j a|| (from the previous update pass), which finalizes column
 // j-1 of the Hessenberg matrix (h_{j-1} + a, subdiagonal beta_j) before any
 // further work, so a converged cycle launches nothing extra.  Then
 //   w = Op(u_j)                                  (u_j not yet re-orthogonalized)
-//   pass 1: b = Q_j^T w, d = u_j.w               (stays on the device)
-//   pass 2: q_j = (u_j - Q_j a)/beta_j,  u_{j+1} = (w - Q_j b - e_j q_j)/beta_j,
-//           e_j = (d - a.b)/beta_j  (the first projection of Op q_j, up to the
-//           factor 1/beta_j: Q_{j+1}^T Op q_j = ([b; e_j] - g)/beta_j with
-//           g = H a, the part of Op(Q_j a) given by the Arnoldi relation);
-//           pass 2 also forms Q_{j+1}^T u_{j+1} and ||u_{j+1}||^2.
-// With flexible = true, Op also stores Ztilde_j = M^{-1} u_j and the returned
-// coefficients multiply Ztilde (q_j's preconditioned vector is
-// (Ztilde_j - Z a)/beta_j, i.e. Z = Ztilde T^{-1} with T upper triangular).
+//   pass 1: p = U_{j+1}^T w, i.e. b = Q_j^T w = T_j^{-T} p_{<j}, d = u_j.w = p_j
+//   pass 2: u_{j+1} = (w - Q_j b - e_j q_j)/beta_j = (w - U_{j+1} gamma)/beta_j,
+//           gamma = T_{j+1}^{-1} [b; e_j], e_j = (d - a.b)/beta_j (the first
+//           projection of Op q_j, up to the factor 1/beta_j: Q_{j+1}^T Op q_j =
+//           ([b; e_j] - g)/beta_j with g = H a, the part of Op(Q_j a) given by
+//           the Arnoldi relation); pass 2 also forms U_{j+1}^T u_{j+1} (so a' =
+//           T_{j+1}^{-T} of it) and ||u_{j+1}||^2.
+// The returned coefficients multiply U (left form) or Ztilde (flexible form:
+// Op also stores Ztilde_j = M^{-1} u_j, and Z = Ztilde T^{-1} like Q).
 struct CycleResult {
   int k = 0;
   double beta0 = 0, gres = 0;
   Coefs y{};
 };
 
-llg_status cycle_dcgs2(const Ctx& c, const std::function<hipError_t(int, const double*, double*)>& op, double* Q,
-                       double* U, double* W, long long n4, double c0, int R, double eta, int maxiter, int& iters,
-                       bool flexible, CycleResult& out, hipStream_t st) {
+llg_status cycle_dcgs2(const Ctx& c, const std::function<hipError_t(int, const double*, double*)>& op,
+                       const double* u0, double* U1, double* W, long long n4, double c0, int R, double eta,
+                       int maxiter, int& iters, CycleResult& out, hipStream_t st) {
+  if (R >= kDcgsMaxCols) return fail(LLG_EARG, "delayed CGS2 needs restart <= 31");
   Hess hs(R);
-  std::vector<double> Hraw(size_t(R + 1) * R, 0.0), T(size_t(R + 1) * (R + 1), 0.0);
-  std::vector<double> hprev, a, col(R + 2), g(R + 2), vals(2 * kMaxDots + 2);
+  std::vector<double> Hraw(size_t(R + 1) * R, 0.0), T(size_t(R + 1) * (R + 1), 0.0),
+      TI(size_t(R + 1) * (R + 1), 0.0);
+  std::vector<double> hprev, a, b(R + 1), col(R + 2), g(R + 2), vals(2 * kMaxDots);
   auto HR = [&](int i, int jj) -> double& { return Hraw[size_t(i) * R + jj]; };
   auto TT = [&](int i, int jj) -> double& { return T[size_t(i) * (R + 1) + jj]; };
+  auto MI = [&](int i, int jj) -> double& { return TI[size_t(i) * (R + 1) + jj]; };
   if (!is_fin(c0)) return fail(LLG_ENAN, "non-finite Krylov start vector");
   double beta = c0 > 0 ? std::sqrt(c0) : 0.0;
   out.beta0 = beta;
@@ -392,23 +397,44 @@ llg_status cycle_dcgs2(const Ctx& c, const std::function<hipError_t(int, const d
       k = j;
       if (out.gres <= eta * out.beta0 || iters >= maxiter || j == R || beta == 0.0) break;
     }
+    // column j of T = [a; beta] and of T^{-1} = [-T_j^{-1} a / beta; 1 / beta]
+    DcgsCoef cf{};
     for (int i = 0; i < j; ++i) TT(i, j) = a[i];
     TT(j, j) = beta;
-    CHK(op(j, U, W));
-    CHK(dcgs_dots(c, Q, n4, j, U, W, n4, c.dots, st));
-    DcgsCoef cf{};
+    for (int i = 0; i < j; ++i) {
+      double sgm = 0;
+      for (int l = i; l < j; ++l) sgm += MI(i, l) * a[l];
+      MI(i, j) = -sgm / beta;
+    }
+    MI(j, j) = 1.0 / beta;
     for (int i = 0; i < j; ++i) cf.a[i] = a[i];
+    for (int i = 0; i <= j; ++i) cf.minv[i] = MI(i, j);
     cf.inv_beta = 1.0 / beta;
     cf.j = j;
-    CHK(dcgs_update(c, Q, n4, cf, c.dots, U, W, Q + size_t(j) * n4, n4, c.dots2, st));
-    // one round trip: pass-1 results (b, d) and the next (a, c)
+    const double* uj = j == 0 ? u0 : U1 + size_t(j - 1) * n4;
+    CHK(op(j, uj, W));
+    CHK(dcgs_dots(c, u0, U1, n4, j, W, n4, c.dots, st));
+    CHK(dcgs_update(c, u0, U1, n4, cf, c.dots, W, U1 + size_t(j) * n4, n4, c.dots2, st));
+    // one round trip: pass-1 dots p and the pass-2 dots of u_{j+1}
     CHK(hipMemcpyAsync(c.host, c.dots, sizeof(double) * 2 * kMaxDots, hipMemcpyDeviceToHost, st));
     CHK(hipStreamSynchronize(st));
     std::memcpy(vals.data(), c.host, sizeof(double) * 2 * kMaxDots);
-    const double* b = vals.data();
-    const double d = vals[j];
-    const double* an = vals.data() + kMaxDots;
-    const double cn = vals[kMaxDots + j + 1];
+    const double* p = vals.data();
+    const double* s = vals.data() + kMaxDots;
+    const double d = p[j];
+    const double cn = s[j + 1];
+    // b = T_j^{-T} p_{<j};  a' = T_{j+1}^{-T} s_{<=j}
+    for (int i = 0; i < j; ++i) {
+      double sgm = 0;
+      for (int l = 0; l <= i; ++l) sgm += MI(l, i) * p[l];
+      b[i] = sgm;
+    }
+    std::vector<double> an(j + 1);
+    for (int i = 0; i <= j; ++i) {
+      double sgm = 0;
+      for (int l = 0; l <= i; ++l) sgm += MI(l, i) * s[l];
+      an[i] = sgm;
+    }
     double ab = 0, aa = 0;
     for (int i = 0; i < j; ++i) ab += a[i] * b[i];
     for (int i = 0; i <= j; ++i) aa += an[i] * an[i];
@@ -422,19 +448,17 @@ llg_status cycle_dcgs2(const Ctx& c, const std::function<hipError_t(int, const d
     hprev.assign(j + 1, 0.0);
     for (int i = 0; i < j; ++i) hprev[i] = (b[i] - g[i]) / beta;
     hprev[j] = ((d - ab) / beta - g[j]) / beta;
-    a.assign(an, an + j + 1);
+    a.swap(an);
     const double beta2 = cn - aa;
     beta = beta2 > 0 ? std::sqrt(beta2) : 0.0;
   }
   out.k = k;
   hs.solve(k, out.y);
-  if (flexible) {
-    // Z = Ztilde T^{-1}: coefficients on Ztilde solve T yt = y
-    for (int i = k - 1; i >= 0; --i) {
-      double sgm = out.y.c[i];
-      for (int l = i + 1; l < k; ++l) sgm -= TT(i, l) * out.y.c[l];
-      out.y.c[i] = sgm / TT(i, i);
-    }
+  // Q = U T^{-1} (and Z = Ztilde T^{-1}): coefficients on U solve T yt = y
+  for (int i = k - 1; i >= 0; --i) {
+    double sgm = out.y.c[i];
+    for (int l = i + 1; l < k; ++l) sgm -= TT(i, l) * out.y.c[l];
+    out.y.c[i] = sgm / TT(i, i);
   }
   return LLG_OK;
 }
@@ -486,21 +510,21 @@ llg_status gmres_left(const Ctx& c, const ResidOp& RA, const Op& M, const Op& MA
     if (res.iters >= o.maxiter) break;
     res.cycles++;
     if (o.orth == 0) {
-      double* Q = w.V;
-      double* U = w.V + size_t(R) * n4;
+      // basis directions u_0 .. u_R in columns 0 .. R of V, Op output in column R + 1
+      double* U0 = w.V;
       double* W = w.V + size_t(R + 1) * n4;
-      CHK(M(w.r, U));
+      CHK(M(w.r, U0));
       double un[2];
-      CHK(dot_and_norm(c, U, nullptr, n4, c.scal, st));
+      CHK(dot_and_norm(c, U0, nullptr, n4, c.scal, st));
       CHK_STATUS(fetch(c, c.scal, 2, st, un));
       CycleResult cr;
       auto op = [&](int, const double* u, double* wout) { return MA(u, wout); };
-      CHK_STATUS(cycle_dcgs2(c, op, Q, U, W, n4, un[1], R, target / rho, o.maxiter, res.iters, false, cr, st));
+      CHK_STATUS(cycle_dcgs2(c, op, U0, U0 + n4, W, n4, un[1], R, target / rho, o.maxiter, res.iters, cr, st));
       if (!is_fin(cr.beta0)) return fail(LLG_ENAN, "non-finite preconditioned residual");
       if (beta0 < 0) beta0 = cr.beta0;
       res.rel_prec = beta0 > 0 ? cr.gres / beta0 : 0.0;
       if (cr.k == 0) break;
-      CHK(lincomb(c, n4, cr.y, Q, n4, x, st));
+      CHK(lincomb(c, n4, cr.y, U0, n4, x, st));
       CHK(RA(x, b, w.r));
       CHK_STATUS(fetch(c, c.scal, 1, st, rn));
       rho = std::sqrt(rn[0]);
@@ -592,13 +616,14 @@ llg_status gmres_ir(const Ctx& c, const llg_params* p, const double* m, const do
       // inner GMRES on M^{-1} A d = M^{-1} r, both operators in float32 on
       // float64 Krylov vectors; stop when the preconditioned residual has
       // fallen by eta; x += Q y in float64
+      // basis in columns 0 .. R of V (delayed CGS2: raw directions; classic
+      // CGS2: orthonormal vectors), Op output in column R + 1
       double* Q = w.V;
-      double* U = w.V + size_t(R) * n4;
       double* W = w.V + size_t(R + 1) * n4;
-      PipeIO<float, double, double> io_m{w.r, w.m32, U, c.ng, nullptr, nullptr};
+      PipeIO<float, double, double> io_m{w.r, w.m32, Q, c.ng, nullptr, nullptr};
       CHK((run_pipeline<float, double, double>(c, PRO_COPY3, EPI_APPLY, sym_ap, na, io_m, st)));
       double un[2];
-      CHK(dot_and_norm(c, U, nullptr, n4, c.scal, st));
+      CHK(dot_and_norm(c, Q, nullptr, n4, c.scal, st));
       CHK_STATUS(fetch(c, c.scal, 2, st, un));
       auto opl = [&](int, const double* u, double* wout) -> hipError_t {
         PipeIO<float, double, double> io{u, w.m32, wout, c.ng, nullptr, nullptr};
@@ -606,12 +631,12 @@ llg_status gmres_ir(const Ctx& c, const llg_params* p, const double* m, const do
       };
       CycleResult cr;
       if (o.orth == 0) {
-        CHK_STATUS(cycle_dcgs2(c, opl, Q, U, W, n4, un[1], R, eta, o.maxiter, res.iters, false, cr, st));
+        CHK_STATUS(cycle_dcgs2(c, opl, Q, Q + n4, W, n4, un[1], R, eta, o.maxiter, res.iters, cr, st));
       } else {
         const double beta = std::sqrt(un[1]);
         if (!is_fin(beta)) return fail(LLG_ENAN, "non-finite preconditioned residual");
         if (beta == 0.0) break;
-        CHK(scale_invnorm(c, Q, U, c.scal + 1, n4, st));
+        CHK(scale_invnorm(c, Q, Q, c.scal + 1, n4, st));
         std::fill(hs.g.begin(), hs.g.end(), 0.0);
         hs.g[0] = beta;
         cr.beta0 = beta;
@@ -634,14 +659,14 @@ llg_status gmres_ir(const Ctx& c, const llg_params* p, const double* m, const do
       continue;
     }
     if (o.orth == 0) {
-      double* Q = w.V;
+      // u_0 = r (the residual buffer is consumed as the cycle's start vector),
+      // u_1 .. u_R in columns 0 .. R - 1 of V, Op output in column R + 1
       double* W = w.V + size_t(R + 1) * n4;
       auto op = [&](int j, const double* u, double* wout) -> hipError_t {
         return run_apply_matvec(c, sym_ap, sym_mv, na, u, w.m32, w.Z + size_t(j) * n4, wout, st);
       };
       CycleResult cr;
-      // u_0 = r (the residual buffer is consumed as the cycle's start vector)
-      CHK_STATUS(cycle_dcgs2(c, op, Q, w.r, W, n4, rho * rho, R, eta, o.maxiter, res.iters, true, cr, st));
+      CHK_STATUS(cycle_dcgs2(c, op, w.r, w.V, W, n4, rho * rho, R, eta, o.maxiter, res.iters, cr, st));
       res.rel_prec = cr.gres / bnorm;
       if (cr.k == 0) break;
       CHK(lincomb(c, n4, cr.y, w.Z, n4, x, st));
@@ -791,6 +816,8 @@ llg_status llg_ctx_create_cell(llg_ctx** out, int nx, int ny, int nz, double lx,
     return cleanup(LLG_ENOMEM, "reduction buffer allocation failed");
   c.dots2 = c.dots + kMaxDots;
   c.scal = c.dots + 2 * kMaxDots;
+  if (hipMalloc(&c.tri, sizeof(double) * (kDcgsMaxCols * kDcgsMaxCols + kDcgsMaxCols)) != hipSuccess)
+    return cleanup(LLG_ENOMEM, "reduction buffer allocation failed");
   if (hipHostMalloc(reinterpret_cast<void**>(&c.host), sizeof(double) * 4 * kMaxDots, hipHostMallocDefault) !=
       hipSuccess)
     return cleanup(LLG_ENOMEM, "pinned host buffer allocation failed");
@@ -838,6 +865,7 @@ llg_status llg_ctx_destroy(llg_ctx* ctx) {
   if (c.spec) (void)hipFree(c.spec);
   if (c.partial) (void)hipFree(c.partial);
   if (c.dots) (void)hipFree(c.dots);
+  if (c.tri) (void)hipFree(c.tri);
   if (c.host) (void)hipHostFree(c.host);
   if (c.prof) profiler_delete(c.prof);
   delete ctx;

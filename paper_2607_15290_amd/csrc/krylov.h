@@ -10,21 +10,25 @@ struct Coefs {
   int n;
 };
 
-// Coefficients of the second pass of CGS2 with delayed re-orthogonalization.
+// Delayed CGS2 keeps the basis as the raw directions U = [u_0 .. u_j]
+// (column 0 at u0, column i >= 1 at U1 + (i - 1) ld); Q = U T^{-1} with T
+// upper triangular, column j of T = [a; beta_j], a = Q_j^T u_j.
 struct DcgsCoef {
-  double a[64];   // re-orthogonalization coefficients of u against Q_0..Q_{j-1}
-  double inv_beta;
+  double a[kDcgsMaxCols];     // a = Q_j^T u_j (entries 0..j-1)
+  double minv[kDcgsMaxCols];  // column j of T^{-1}: [-T_j^{-1} a / beta_j; 1 / beta_j]
+  double inv_beta;            // 1 / beta_j
   int j;
 };
 
-// Pass 1: out = [Q_i.w (i < j), u.w].  j <= 31.
-hipError_t dcgs_dots(const Ctx& c, const double* Q, long long ld, int j, const double* u, const double* w,
+// Pass 1: out = [U_i.w (i <= j)].  j < kDcgsMaxCols.
+hipError_t dcgs_dots(const Ctx& c, const double* u0, const double* U1, long long ld, int j, const double* w,
                      long long n, double* out, hipStream_t st);
-// Pass 2 (bd = pass-1 output on the device):
-//   qj = (u - sum a_i Q_i)/beta ; u <- (w - sum bd_i Q_i - e_j qj)/beta, e_j = (bd_j - a.bd)/beta
-//   out = [Q_i.u (i < j), qj.u, u.u] for the new u.
-hipError_t dcgs_update(const Ctx& c, const double* Q, long long ld, const DcgsCoef& cf, const double* bd, double* u,
-                       const double* w, double* qj, long long n, double* out, hipStream_t st);
+// Pass 2 (p = pass-1 output on the device): with gamma = T_{j+1}^{-1} [b; e_j],
+// b = T_j^{-T} p_{<j}, e_j = (p_j - a.b) / beta_j (computed on the device),
+//   unew = (w - U gamma) / beta_j,   out = [U_i.unew (i <= j), unew.unew].
+// unew must not alias w or a basis column 0..j.
+hipError_t dcgs_update(const Ctx& c, const double* u0, const double* U1, long long ld, const DcgsCoef& cf,
+                       const double* p, const double* w, double* unew, long long n, double* out, hipStream_t st);
 
 // out[i] = sum (or max) of the nb value-major partials of value i, i < nv
 hipError_t reduce_partials(const Ctx& c, int nb, int nv, double* out, bool is_max, hipStream_t st);

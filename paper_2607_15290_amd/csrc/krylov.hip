@@ -194,48 +194,30 @@ __global__ __launch_bounds__(kRedThreads) void k_update_norm(const double* __res
 }
 
 // ---- CGS2 with delayed re-orthogonalization (two passes per iteration) -------
-// Both passes are instantiated for the exact number J of basis vectors, so
-// every basis load of a thread is unconditional and the loads of one element
-// are all in flight together; loads and stores are non-temporal.  Blocks of
-// kDcgsThreads threads, one double2 per thread on a full-size grid (measured
-// 2-7% faster than two per thread, and faster than batching several elements'
-// loads per thread, whose extra streams in flight lower the DRAM efficiency).
+// The basis is kept as the raw Arnoldi directions U = [u_0 .. u_J] (column 0
+// at u0, column i >= 1 at U1 + (i - 1) ld); the orthonormal basis is implicit,
+// Q = U T^{-1}, with T upper triangular (column j = [Q_j^T u_j; beta_j]).
+// Storing U instead of Q saves one vector store per iteration: q_j is never
+// written.  Both passes are instantiated for the exact column count J + 1,
+// so every basis load of a thread is unconditional and the loads of one
+// element are all in flight together; loads and stores are non-temporal.
+// Blocks of kDcgsThreads threads, one double2 per thread on a full-size grid
+// (measured 2-7% faster than two per thread, and faster than batching several
+// elements' loads per thread, whose extra streams in flight lower the DRAM
+// efficiency).
 constexpr int kDcgsThreads = 512;
-//
-// Pass 1: out = [Q_i.w (i < J), u.w], value-major partials.
-template <int J>
-__global__ __launch_bounds__(kDcgsThreads) void k_dcgs_dots(const double2* __restrict__ Q, long long ld2,
-                                                          const double2* __restrict__ u,
-                                                          const double2* __restrict__ w, long long n2,
-                                                          double* __restrict__ partial) {
-  constexpr int NA = J > 0 ? J : 1;
-  double aw[NA];
-#pragma unroll
-  for (int i = 0; i < NA; ++i) aw[i] = 0.0;
-  double cuw = 0.0;
-  const long long stride = (long long)gridDim.x * blockDim.x;
-  for (long long e = (long long)blockIdx.x * blockDim.x + threadIdx.x; e < n2; e += stride) {
-    const double2 uu = ldnt(u + e), ww = ldnt(w + e);
-    double2 q[NA];
-#pragma unroll
-    for (int i = 0; i < J; ++i) q[i] = ldnt(Q + i * ld2 + e);
-    cuw = fma(uu.x, ww.x, fma(uu.y, ww.y, cuw));
-#pragma unroll
-    for (int i = 0; i < J; ++i) aw[i] = fma(q[i].x, ww.x, fma(q[i].y, ww.y, aw[i]));
-  }
-  __shared__ double sm[kDcgsThreads / 64][J + 1];
+
+template <int NV>
+__device__ __forceinline__ void dcgs_block_store(const double (&acc)[NV], double* __restrict__ partial) {
+  __shared__ double sm[kDcgsThreads / 64][NV];
   const int lane = threadIdx.x & 63, wv = threadIdx.x >> 6;
 #pragma unroll
-  for (int i = 0; i < J; ++i) {
-    const double y = wave_sum(aw[i]);
+  for (int i = 0; i < NV; ++i) {
+    const double y = wave_sum(acc[i]);
     if (lane == 0) sm[wv][i] = y;
   }
-  {
-    const double y = wave_sum(cuw);
-    if (lane == 0) sm[wv][J] = y;
-  }
   __syncthreads();
-  if (threadIdx.x < J + 1) {
+  if (threadIdx.x < NV) {
     double t = sm[0][threadIdx.x];
 #pragma unroll
     for (int k = 1; k < kDcgsThreads / 64; ++k) t += sm[k][threadIdx.x];
@@ -243,64 +225,88 @@ __global__ __launch_bounds__(kDcgsThreads) void k_dcgs_dots(const double2* __res
   }
 }
 
-// Pass 2: with (b, d) = pass-1 results (device), a and beta from the host:
-//   q_J = (u - sum_i a_i Q_i) / beta
-//   u  <- (w - sum_i b_i Q_i - e_J q_J) / beta,   e_J = (d - a.b) / beta
-// and, for the next iteration, out = [Q_i.u_new (i < J), q_J.u_new, u_new.u_new].
+// Pass 1: out = [U_i.w (i <= J)], value-major partials.
 template <int J>
-__global__ __launch_bounds__(kDcgsThreads) void k_dcgs_update(const double2* __restrict__ Q, long long ld2,
-                                                            DcgsCoef cf, const double* __restrict__ bd,
-                                                            double2* u, const double2* __restrict__ w,
-                                                            double2* __restrict__ qj, long long n2,
-                                                            double* __restrict__ partial) {
-  constexpr int NA = J > 0 ? J : 1;
-  double bb[NA];
-  double ab = 0.0;
+__global__ __launch_bounds__(kDcgsThreads) void k_dcgs_dots(const double2* __restrict__ u0,
+                                                          const double2* __restrict__ U1, long long ld2,
+                                                          const double2* __restrict__ w, long long n2,
+                                                          double* __restrict__ partial) {
+  double acc[J + 1];
 #pragma unroll
-  for (int i = 0; i < J; ++i) {
-    bb[i] = bd[i];
-    ab = fma(cf.a[i], bb[i], ab);
+  for (int i = 0; i <= J; ++i) acc[i] = 0.0;
+  const long long stride = (long long)gridDim.x * blockDim.x;
+  for (long long e = (long long)blockIdx.x * blockDim.x + threadIdx.x; e < n2; e += stride) {
+    const double2 ww = ldnt(w + e);
+    double2 q[J + 1];
+    q[0] = ldnt(u0 + e);
+#pragma unroll
+    for (int i = 1; i <= J; ++i) q[i] = ldnt(U1 + (i - 1) * ld2 + e);
+#pragma unroll
+    for (int i = 0; i <= J; ++i) acc[i] = fma(q[i].x, ww.x, fma(q[i].y, ww.y, acc[i]));
   }
-  const double ej = (bd[J] - ab) * cf.inv_beta;
+  dcgs_block_store<J + 1>(acc, partial);
+}
+
+// Projection coefficients of pass 2, one wavefront.  With p = U_{j+1}^T w
+// (pass 1, on the device) and Minv = T^{-1} (columns 0..j-1 in minv from the
+// earlier steps, column j in cf):
+//   b = Q_j^T w = Minv_j^T p_{<j},   e_j = q_j.w = (p_j - a.b) / beta_j,
+//   Q_{j+1} [b; e_j] = U_{j+1} gamma,   gamma = Minv_{j+1} [b; e_j].
+// Also stores column j of Minv for the later steps.
+__global__ __launch_bounds__(64) void k_dcgs_coef(DcgsCoef cf, const double* __restrict__ p,
+                                                  double* __restrict__ minv, double* __restrict__ gamma) {
+  const int l = threadIdx.x, j = cf.j;
+  auto mi = [&](int r, int col) { return col == j ? cf.minv[r] : minv[col * kDcgsMaxCols + r]; };
+  double b = 0.0;
+  if (l < j)
+    for (int k = 0; k <= l; ++k) b = fma(mi(k, l), p[k], b);
+  const double ab = wave_sum(l < j ? cf.a[l] * b : 0.0);
+  const double e = (p[j] - ab) * cf.inv_beta;
+  __shared__ double v[64];
+  v[l] = l < j ? b : (l == j ? e : 0.0);
+  __syncthreads();
+  if (l <= j) {
+    double g = 0.0;
+    for (int k = l; k <= j; ++k) g = fma(mi(l, k), v[k], g);
+    gamma[l] = g;
+    minv[j * kDcgsMaxCols + l] = cf.minv[l];
+  }
+}
+
+// Pass 2: unew = (w - U gamma) / beta_j, and, for the next step,
+// out = [U_i.unew (i <= J), unew.unew], value-major partials.
+template <int J>
+__global__ __launch_bounds__(kDcgsThreads) void k_dcgs_update(const double2* __restrict__ u0,
+                                                            const double2* __restrict__ U1, long long ld2,
+                                                            const double* __restrict__ gamma, double inv_beta,
+                                                            const double2* __restrict__ w,
+                                                            double2* __restrict__ unew, long long n2,
+                                                            double* __restrict__ partial) {
+  double gm[J + 1];
+#pragma unroll
+  for (int i = 0; i <= J; ++i) gm[i] = gamma[i];
   double acc[J + 2];
 #pragma unroll
   for (int i = 0; i < J + 2; ++i) acc[i] = 0.0;
   const long long stride = (long long)gridDim.x * blockDim.x;
   for (long long e = (long long)blockIdx.x * blockDim.x + threadIdx.x; e < n2; e += stride) {
-    double2 sa = ldnt(u + e), se = ldnt(w + e);
-    double2 q[NA];
+    double2 se = ldnt(w + e);
+    double2 q[J + 1];
+    q[0] = ldnt(u0 + e);
 #pragma unroll
-    for (int i = 0; i < J; ++i) q[i] = ldnt(Q + i * ld2 + e);
+    for (int i = 1; i <= J; ++i) q[i] = ldnt(U1 + (i - 1) * ld2 + e);
 #pragma unroll
-    for (int i = 0; i < J; ++i) {
-      sa.x = fma(-cf.a[i], q[i].x, sa.x);
-      sa.y = fma(-cf.a[i], q[i].y, sa.y);
-      se.x = fma(-bb[i], q[i].x, se.x);
-      se.y = fma(-bb[i], q[i].y, se.y);
+    for (int i = 0; i <= J; ++i) {
+      se.x = fma(-gm[i], q[i].x, se.x);
+      se.y = fma(-gm[i], q[i].y, se.y);
     }
-    const double2 qn{sa.x * cf.inv_beta, sa.y * cf.inv_beta};
-    const double2 un{(se.x - ej * qn.x) * cf.inv_beta, (se.y - ej * qn.y) * cf.inv_beta};
-    stnt(qj + e, qn);
-    stnt(u + e, un);
+    const double2 un{se.x * inv_beta, se.y * inv_beta};
+    stnt(unew + e, un);
 #pragma unroll
-    for (int i = 0; i < J; ++i) acc[i] = fma(q[i].x, un.x, fma(q[i].y, un.y, acc[i]));
-    acc[J] = fma(qn.x, un.x, fma(qn.y, un.y, acc[J]));
+    for (int i = 0; i <= J; ++i) acc[i] = fma(q[i].x, un.x, fma(q[i].y, un.y, acc[i]));
     acc[J + 1] = fma(un.x, un.x, fma(un.y, un.y, acc[J + 1]));
   }
-  __shared__ double sm[kDcgsThreads / 64][J + 2];
-  const int lane = threadIdx.x & 63, wv = threadIdx.x >> 6;
-#pragma unroll
-  for (int i = 0; i < J + 2; ++i) {
-    const double y = wave_sum(acc[i]);
-    if (lane == 0) sm[wv][i] = y;
-  }
-  __syncthreads();
-  if (threadIdx.x < J + 2) {
-    double t = sm[0][threadIdx.x];
-#pragma unroll
-    for (int k = 1; k < kDcgsThreads / 64; ++k) t += sm[k][threadIdx.x];
-    partial[(long long)threadIdx.x * gridDim.x + blockIdx.x] = t;
-  }
+  dcgs_block_store<J + 2>(acc, partial);
 }
 
 // ---- simple vector kernels -------------------------------------------------
@@ -448,28 +454,29 @@ hipError_t cgs_update_norm(const Ctx& c, const double* V, long long ld, int nv, 
 
 
 template <int J>
-static void dd_t(const Ctx& c, const double* Q, long long ld, const double* u, const double* w, long long n,
+static void dd_t(const Ctx& c, const double* u0, const double* U1, long long ld, const double* w, long long n,
                  hipStream_t st) {
   hipLaunchKernelGGL((k_dcgs_dots<J>), dim3(red_blocks(n / 2)), dim3(kDcgsThreads), 0, st,
-                     reinterpret_cast<const double2*>(Q), ld / 2, reinterpret_cast<const double2*>(u),
+                     reinterpret_cast<const double2*>(u0), reinterpret_cast<const double2*>(U1), ld / 2,
                      reinterpret_cast<const double2*>(w), n / 2, c.partial);
 }
 
 template <int J>
-static void du_t(const Ctx& c, const double* Q, long long ld, const DcgsCoef& cf, const double* bd, double* u,
-                 const double* w, double* qj, long long n, hipStream_t st) {
+static void du_t(const Ctx& c, const double* u0, const double* U1, long long ld, const double* gamma,
+                 double inv_beta, const double* w, double* unew, long long n, hipStream_t st) {
   hipLaunchKernelGGL((k_dcgs_update<J>), dim3(red_blocks(n / 2)), dim3(kDcgsThreads), 0, st,
-                     reinterpret_cast<const double2*>(Q), ld / 2, cf, bd, reinterpret_cast<double2*>(u),
-                     reinterpret_cast<const double2*>(w), reinterpret_cast<double2*>(qj), n / 2, c.partial);
+                     reinterpret_cast<const double2*>(u0), reinterpret_cast<const double2*>(U1), ld / 2, gamma,
+                     inv_beta, reinterpret_cast<const double2*>(w), reinterpret_cast<double2*>(unew), n / 2,
+                     c.partial);
 }
 
-// Runtime J -> template instantiation J = 0..31.
+// Runtime J -> template instantiation J = 0..kDcgsMaxCols - 1.
 template <template <int> class F, int J = 0>
 struct JDispatch {
   template <typename... A>
   static void run(int j, A&&... args) {
     if (j == J) F<J>::go(std::forward<A>(args)...);
-    else if constexpr (J < 31) JDispatch<F, J + 1>::run(j, std::forward<A>(args)...);
+    else if constexpr (J < kDcgsMaxCols - 1) JDispatch<F, J + 1>::run(j, std::forward<A>(args)...);
   }
 };
 template <int J>
@@ -483,22 +490,27 @@ struct UpdF {
   static void go(A&&... a) { du_t<J>(std::forward<A>(a)...); }
 };
 
-hipError_t dcgs_dots(const Ctx& c, const double* Q, long long ld, int j, const double* u, const double* w,
+hipError_t dcgs_dots(const Ctx& c, const double* u0, const double* U1, long long ld, int j, const double* w,
                      long long n, double* out, hipStream_t st) {
-  if (j < 0 || j > 31) return hipErrorInvalidValue;
+  if (j < 0 || j >= kDcgsMaxCols) return hipErrorInvalidValue;
   {
     ProfScope ps(c.prof, st, KK_CGS_DOTS, 8.0 * n * (j + 2));
-    JDispatch<DotsF>::run(j, c, Q, ld, u, w, n, st);
+    JDispatch<DotsF>::run(j, c, u0, U1, ld, w, n, st);
   }
   return reduce_partials_n(c, red_blocks(n / 2), j + 1, out, st);
 }
 
-hipError_t dcgs_update(const Ctx& c, const double* Q, long long ld, const DcgsCoef& cf, const double* bd, double* u,
-                       const double* w, double* qj, long long n, double* out, hipStream_t st) {
-  if (cf.j < 0 || cf.j > 31) return hipErrorInvalidValue;
+hipError_t dcgs_update(const Ctx& c, const double* u0, const double* U1, long long ld, const DcgsCoef& cf,
+                       const double* p, const double* w, double* unew, long long n, double* out, hipStream_t st) {
+  if (cf.j < 0 || cf.j >= kDcgsMaxCols) return hipErrorInvalidValue;
+  double* gamma = c.tri + kDcgsMaxCols * kDcgsMaxCols;
   {
-    ProfScope ps(c.prof, st, KK_CGS_UPDATE_DOTS, 8.0 * n * (cf.j + 4));
-    JDispatch<UpdF>::run(cf.j, c, Q, ld, cf, bd, u, w, qj, n, st);
+    ProfScope ps(c.prof, st, KK_REDUCE, 8.0 * (cf.j + 1) * (cf.j + 3));
+    hipLaunchKernelGGL(k_dcgs_coef, dim3(1), dim3(64), 0, st, cf, p, c.tri, gamma);
+  }
+  {
+    ProfScope ps(c.prof, st, KK_CGS_UPDATE_DOTS, 8.0 * n * (cf.j + 3));
+    JDispatch<UpdF>::run(cf.j, c, u0, U1, ld, gamma, cf.inv_beta, w, unew, n, st);
   }
   return reduce_partials_n(c, red_blocks(n / 2), cf.j + 2, out, st);
 }

@@ -26,6 +26,7 @@ void set_error(const std::string& msg);
 constexpr int kRedBlocksMax = 65536;  // partial buffer rows (large dot passes)
 constexpr int kRedThreads = 256;
 constexpr int kMaxDots = 64;
+constexpr int kDcgsMaxCols = 32;  // delayed-CGS2 basis columns (restart <= 31)
 
 // Kernel kinds known to the event profiler.
 enum KernelKind : int {
@@ -62,6 +63,7 @@ struct Ctx {
   double* dots2 = nullptr;    // second set (CGS2 re-orthogonalization)
   double* scal = nullptr;     // small device scalars
   double* host = nullptr;     // pinned host mirror (4 * kMaxDots doubles)
+  double* tri = nullptr;      // delayed-CGS2 T^{-1} (kDcgsMaxCols^2, column-major) + kDcgsMaxCols coefficients
 };
 
 SymArgs sym_for(const Ctx& c, double a, double b, bool invert);
