@@ -367,9 +367,18 @@ struct CycleResult {
   Coefs y{};
 };
 
-llg_status cycle_dcgs2(const Ctx& c, const std::function<hipError_t(int, const double*, double*)>& op,
-                       const double* u0, double* U1, double* W, long long n4, double c0, int R, double eta,
-                       int maxiter, int& iters, CycleResult& out, hipStream_t st) {
+// With op_dots the operator also leaves pass 1's p = U_{j+1}^T w in c.dots
+// (it receives the basis layout); otherwise it ignores that argument.
+// The precision form takes pass 1 inside its matvec's last x pass (measured
+// 2.5% more solves/s at 256^3 than the separate pass); 0 selects the
+// separate pass.
+#ifndef LLG_FUSE_DOTS
+#define LLG_FUSE_DOTS 1
+#endif
+using ArnoldiOp = std::function<hipError_t(int, const double*, double*, const BasisDots*)>;
+llg_status cycle_dcgs2(const Ctx& c, const ArnoldiOp& op, bool op_dots, const double* u0, double* U1, double* W,
+                       long long n4, double c0, int R, double eta, int maxiter, int& iters, CycleResult& out,
+                       hipStream_t st) {
   if (R >= kDcgsMaxCols) return fail(LLG_EARG, "delayed CGS2 needs restart <= 31");
   Hess hs(R);
   std::vector<double> Hraw(size_t(R + 1) * R, 0.0), T(size_t(R + 1) * (R + 1), 0.0),
@@ -412,8 +421,13 @@ llg_status cycle_dcgs2(const Ctx& c, const std::function<hipError_t(int, const d
     cf.inv_beta = 1.0 / beta;
     cf.j = j;
     const double* uj = j == 0 ? u0 : U1 + size_t(j - 1) * n4;
-    CHK(op(j, uj, W));
-    CHK(dcgs_dots(c, u0, U1, n4, j, W, n4, c.dots, st));
+    if (op_dots) {
+      const BasisDots bq{u0, U1, n4, j + 1, nullptr};
+      CHK(op(j, uj, W, &bq));
+    } else {
+      CHK(op(j, uj, W, nullptr));
+      CHK(dcgs_dots(c, u0, U1, n4, j, W, n4, c.dots, st));
+    }
     CHK(dcgs_update(c, u0, U1, n4, cf, c.dots, W, U1 + size_t(j) * n4, n4, c.dots2, st));
     // one round trip: pass-1 dots p and the pass-2 dots of u_{j+1}
     CHK(hipMemcpyAsync(c.host, c.dots, sizeof(double) * 2 * kMaxDots, hipMemcpyDeviceToHost, st));
@@ -518,8 +532,9 @@ llg_status gmres_left(const Ctx& c, const ResidOp& RA, const Op& M, const Op& MA
       CHK(dot_and_norm(c, U0, nullptr, n4, c.scal, st));
       CHK_STATUS(fetch(c, c.scal, 2, st, un));
       CycleResult cr;
-      auto op = [&](int, const double* u, double* wout) { return MA(u, wout); };
-      CHK_STATUS(cycle_dcgs2(c, op, U0, U0 + n4, W, n4, un[1], R, target / rho, o.maxiter, res.iters, cr, st));
+      auto op = [&](int, const double* u, double* wout, const BasisDots*) { return MA(u, wout); };
+      CHK_STATUS(cycle_dcgs2(c, op, false, U0, U0 + n4, W, n4, un[1], R, target / rho, o.maxiter, res.iters, cr,
+                             st));
       if (!is_fin(cr.beta0)) return fail(LLG_ENAN, "non-finite preconditioned residual");
       if (beta0 < 0) beta0 = cr.beta0;
       res.rel_prec = beta0 > 0 ? cr.gres / beta0 : 0.0;
@@ -625,13 +640,13 @@ llg_status gmres_ir(const Ctx& c, const llg_params* p, const double* m, const do
       double un[2];
       CHK(dot_and_norm(c, Q, nullptr, n4, c.scal, st));
       CHK_STATUS(fetch(c, c.scal, 2, st, un));
-      auto opl = [&](int, const double* u, double* wout) -> hipError_t {
+      auto opl = [&](int, const double* u, double* wout, const BasisDots*) -> hipError_t {
         PipeIO<float, double, double> io{u, w.m32, wout, c.ng, nullptr, nullptr};
         return run_pipeline<float, double, double>(c, PRO_SMINUS, EPI_FUSED, sym_ap, na, io, st);
       };
       CycleResult cr;
       if (o.orth == 0) {
-        CHK_STATUS(cycle_dcgs2(c, opl, Q, Q + n4, W, n4, un[1], R, eta, o.maxiter, res.iters, cr, st));
+        CHK_STATUS(cycle_dcgs2(c, opl, false, Q, Q + n4, W, n4, un[1], R, eta, o.maxiter, res.iters, cr, st));
       } else {
         const double beta = std::sqrt(un[1]);
         if (!is_fin(beta)) return fail(LLG_ENAN, "non-finite preconditioned residual");
@@ -641,7 +656,7 @@ llg_status gmres_ir(const Ctx& c, const llg_params* p, const double* m, const do
         hs.g[0] = beta;
         cr.beta0 = beta;
         for (int j = 0; j < R; ++j) {
-          CHK(opl(j, Q + size_t(j) * n4, Q + size_t(j + 1) * n4));
+          CHK(opl(j, Q + size_t(j) * n4, Q + size_t(j + 1) * n4, nullptr));
           CHK_STATUS(arnoldi_step(c, Q, n4, j, col.data(), st));
           cr.gres = hs.add_column(j, col.data());
           res.iters++;
@@ -662,11 +677,12 @@ llg_status gmres_ir(const Ctx& c, const llg_params* p, const double* m, const do
       // u_0 = r (the residual buffer is consumed as the cycle's start vector),
       // u_1 .. u_R in columns 0 .. R - 1 of V, Op output in column R + 1
       double* W = w.V + size_t(R + 1) * n4;
-      auto op = [&](int j, const double* u, double* wout) -> hipError_t {
-        return run_apply_matvec(c, sym_ap, sym_mv, na, u, w.m32, w.Z + size_t(j) * n4, wout, st);
+      auto op = [&](int j, const double* u, double* wout, const BasisDots* bq) -> hipError_t {
+        return run_apply_matvec(c, sym_ap, sym_mv, na, u, w.m32, w.Z + size_t(j) * n4, wout, st, bq, c.dots);
       };
       CycleResult cr;
-      CHK_STATUS(cycle_dcgs2(c, op, w.r, w.V, W, n4, rho * rho, R, eta, o.maxiter, res.iters, cr, st));
+      CHK_STATUS(cycle_dcgs2(c, op, LLG_FUSE_DOTS != 0, w.r, w.V, W, n4, rho * rho, R, eta, o.maxiter, res.iters,
+                             cr, st));
       res.rel_prec = cr.gres / bnorm;
       if (cr.k == 0) break;
       CHK(lincomb(c, n4, cr.y, w.Z, n4, x, st));

@@ -32,7 +32,7 @@ constexpr int kDcgsMaxCols = 32;  // delayed-CGS2 basis columns (restart <= 31)
 enum KernelKind : int {
   KK_XFWD = 0, KK_AXIS_FWD, KK_AXIS_FUSED, KK_AXIS_INV, KK_XINV, KK_CGS_DOTS, KK_CGS_UPDATE_DOTS,
   KK_CGS_UPDATE_NORM, KK_REDUCE, KK_SCALE, KK_AXPBY, KK_LINCOMB, KK_CONVERT, KK_DOT2, KK_NODAL, KK_FIELD3,
-  KK_XMID, KK_COUNT
+  KK_XMID, KK_XINV_DOTS, KK_COUNT
 };
 const char* kernel_kind_name(int k);
 
@@ -76,9 +76,11 @@ hipError_t run_pipeline(const Ctx& c, int pro, int epi, const SymArgs& sym, cons
 
 // Precision-form inner operator (pipeline_f32.hip): z = M^{-1} v (float32,
 // stored) and w = A z (float32, float64 result), the two pipelines joined by
-// one fused x pass.
+// one fused x pass.  With bd (bd->nv > 0) the last pass also forms the
+// Arnoldi inner products dots_out[q] = u_q . w, q < bd->nv (device).
 hipError_t run_apply_matvec(const Ctx& c, const SymArgs& sym_ap, const SymArgs& sym_mv, const NodalArgs& na,
-                            const double* v, const float* m32, float* z, double* w, hipStream_t st);
+                            const double* v, const float* m32, float* z, double* w, hipStream_t st,
+                            const BasisDots* bd = nullptr, double* dots_out = nullptr);
 
 // Lower-order field pipeline (field.hip, float64): forward DFTs of three
 // planes, the 3x3 multiplier of FieldArgs, inverse DFTs, then the x-inverse

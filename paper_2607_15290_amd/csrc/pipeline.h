@@ -132,4 +132,17 @@ struct PipeIO {
   double* red = nullptr;
 };
 
+// Arnoldi inner products taken by an x-inverse pass on its own output (the
+// precision form's matvec): with basis directions u_0 at u0 and u_i at
+// U1 + (i - 1) ld (1 <= i < nv), each block stores the partial sums of
+// u_i . out over its nodes at partial[i * gridDim.x + blockIdx.x].
+constexpr int kBasisDotsMax = 32;
+struct BasisDots {
+  const double* u0 = nullptr;
+  const double* U1 = nullptr;
+  long long ld = 0;
+  int nv = 0;
+  double* partial = nullptr;
+};
+
 }  // namespace llg

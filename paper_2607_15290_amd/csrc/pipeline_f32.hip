@@ -15,10 +15,11 @@ template hipError_t run_pipeline<float, double, double>(const Ctx&, int, int, co
                                                         const PipeIO<float, double, double>&, hipStream_t);
 
 hipError_t run_apply_matvec(const Ctx& c, const SymArgs& sym_ap, const SymArgs& sym_mv, const NodalArgs& na,
-                            const double* v, const float* m32, float* z, double* w, hipStream_t st) {
+                            const double* v, const float* m32, float* z, double* w, hipStream_t st,
+                            const BasisDots* bd, double* dots_out) {
   switch (c.geom.nh) {
 #define LLG_CASE(n) \
-  case n: return run_apply_matvec_nh<n>(c, sym_ap, sym_mv, na, v, m32, z, w, st);
+  case n: return run_apply_matvec_nh<n>(c, sym_ap, sym_mv, na, v, m32, z, w, bd, dots_out, st);
     LLG_FOR_NH(LLG_CASE)
 #undef LLG_CASE
     default: return hipErrorInvalidValue;

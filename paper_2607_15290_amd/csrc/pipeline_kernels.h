@@ -462,9 +462,16 @@ __global__ __launch_bounds__(192) void k_xfwd(const TIn* __restrict__ in, const 
 // ---------------------------------------------------------------------------
 // k_xinv
 // ---------------------------------------------------------------------------
-template <typename T, typename TIn, typename TOut, int NH, int EPI>
+// With DOTS (float32 matvec writing a float64 Krylov vector only) the pass
+// also forms the inner products of its output with the Arnoldi basis
+// directions (BasisDots), from the output values it still holds in
+// registers: the separate inner-product pass and its read of the output
+// disappear.
+template <typename T, typename TIn, typename TOut, int NH, int EPI, bool DOTS = false>
 __global__ __launch_bounds__(192) void k_xinv(PipeIO<T, TIn, TOut> io, const cx<T>* __restrict__ spec,
-                                              SpecGeom g, NodalArgs na, const cx<T>* __restrict__ twx) {
+                                              SpecGeom g, NodalArgs na, const cx<T>* __restrict__ twx,
+                                              BasisDots bd) {
+  static_assert(!DOTS || (EPI == EPI_MATVEC && std::is_same<TOut, double>::value), "dots: float64 matvec output");
   using C = XCfg<T, NH>;
   __shared__ cx<T> lds[3 * C::LX * C::SL];
   const int tid = threadIdx.x;
@@ -481,6 +488,8 @@ __global__ __launch_bounds__(192) void k_xinv(PipeIO<T, TIn, TOut> io, const cx<
   constexpr int NPAIR = C::LX * NH;
   constexpr int ITERS = (NPAIR + C::NT - 1) / C::NT;
   constexpr int BATCH = sizeof(T) == 4 ? LLG_XBATCH_F32 : LLG_XBATCH_F64;
+  constexpr int KEEP = DOTS ? ITERS : 1;
+  T keep0[KEEP][4], keep1[KEEP][4];  // outputs of the thread's node pairs (0 where not live)
 #pragma unroll
   for (int it0 = 0; it0 < ITERS; it0 += BATCH) {
   EpiRaw<T, TIn, TOut, EPI> raw[BATCH];
@@ -526,7 +535,48 @@ __global__ __launch_bounds__(192) void k_xinv(PipeIO<T, TIn, TOut> io, const cx<
 #pragma unroll
       for (int f = 0; f < NOUT; ++f) store2(io.out + f * io.ng + i, TOut(o0[f]), TOut(o1[f]));
     }
+    if constexpr (DOTS) {
+#pragma unroll
+      for (int f = 0; f < 4; ++f) {
+        keep0[it0 + b][f] = live ? o0[f] : T(0);
+        keep1[it0 + b][f] = live ? o1[f] : T(0);
+      }
+    }
   }
+  }
+  if constexpr (DOTS) {
+    // u_q . out for q < nv: per column, the clamped (unconditional) loads of
+    // all the thread's node pairs are in flight together; dead pairs weigh 0.
+    __shared__ double dred[C::NT / 64][kBasisDotsMax];
+    const int lane = tid & 63, wv = tid >> 6;
+    for (int q = 0; q < bd.nv; ++q) {
+      const double* col = q == 0 ? bd.u0 : bd.U1 + (q - 1) * bd.ld;
+      double t = 0.0;
+#pragma unroll
+      for (int it = 0; it < ITERS; ++it) {
+        const int e0 = tid + it * C::NT;
+        const int e = e0 < NPAIR ? e0 : NPAIR - 1;
+        const int l = e / NH, xp = e % NH;
+        const long long line = line0 + l < nlines ? line0 + l : nlines - 1;
+        const long long i = line * NX + 2 * xp;
+#pragma unroll
+        for (int f = 0; f < 4; ++f) {
+          double a0, a1;
+          load2(col + f * io.ng + i, a0, a1);
+          t = fma(a0, double(keep0[it][f]), fma(a1, double(keep1[it][f]), t));
+        }
+      }
+#pragma unroll
+      for (int off = 32; off > 0; off >>= 1) t += __shfl_xor(t, off, 64);
+      if (lane == 0) dred[wv][q] = t;
+    }
+    __syncthreads();
+    if (tid < bd.nv) {
+      double t = dred[0][tid];
+#pragma unroll
+      for (int k = 1; k < C::NT / 64; ++k) t += dred[k][tid];
+      bd.partial[(long long)tid * gridDim.x + blockIdx.x] = t;
+    }
   }
   if (io.rhs) {
     // block partial of the residual norm (fixed order: deterministic)

@@ -3,6 +3,7 @@
 // run_pipeline for the type combinations they need.
 #pragma once
 #include "llg_internal.h"
+#include "krylov.h"
 #include "pipeline_kernels.h"
 
 namespace llg {
@@ -61,7 +62,7 @@ void launch_xinv(const Ctx& c, const NodalArgs& na, const PipeIO<T, TIn, TOut>& 
     if (io.rhs) node_b += 4.0 * sizeof(TOut);
     ProfScope ps(c.prof, st, KK_XINV, double(c.ng) * node_b + double(c.geom.cs) * lines * 2 * sizeof(T));
     hipLaunchKernelGGL((k_xinv<T, TIn, TOut, NH, EPI>), dim3(grid), dim3(C::NT), 0, st, io,
-                       reinterpret_cast<const cx<T>*>(c.spec), c.geom, na, tw);
+                       reinterpret_cast<const cx<T>*>(c.spec), c.geom, na, tw, BasisDots{});
   }
 }
 
@@ -119,7 +120,8 @@ hipError_t run_axes(const Ctx& c, const SymArgs& sym, hipStream_t st) {
 // float64 result; the junction of the two pipelines is the fused k_xmid pass.
 template <int NH>
 hipError_t run_apply_matvec_nh(const Ctx& c, const SymArgs& sym_ap, const SymArgs& sym_mv, const NodalArgs& na,
-                               const double* v, const float* m32, float* z, double* w, hipStream_t st) {
+                               const double* v, const float* m32, float* z, double* w, const BasisDots* bd,
+                               double* dots_out, hipStream_t st) {
   using C = XCfg<float, NH>;
   PipeIO<float, double, float> io_ap{v, m32, z, c.ng, nullptr, nullptr};
   PipeIO<float, float, double> io_mv{z, m32, w, c.ng, nullptr, nullptr};
@@ -136,8 +138,25 @@ hipError_t run_apply_matvec_nh(const Ctx& c, const SymArgs& sym_ap, const SymArg
     if ((e = hipGetLastError()) != hipSuccess) return e;
   }
   if ((e = run_axes<float>(c, sym_mv, st)) != hipSuccess) return e;
-  launch_xinv<float, float, double, NH, EPI_MATVEC>(c, na, io_mv, st);
-  return hipGetLastError();
+  if (!bd || bd->nv == 0) {
+    launch_xinv<float, float, double, NH, EPI_MATVEC>(c, na, io_mv, st);
+    return hipGetLastError();
+  }
+  // matvec with the Arnoldi inner products of w (out[q] = u_q . w, q < nv)
+  if (bd->nv > kBasisDotsMax) return hipErrorInvalidValue;
+  const long long lines = (long long)c.ny * c.nz;
+  const unsigned grid = (unsigned)((lines + C::LX - 1) / C::LX);
+  if (grid > (unsigned)kRedBlocksMax) return hipErrorInvalidValue;
+  BasisDots kd = *bd;
+  kd.partial = c.partial;
+  {
+    const double node_b = 4.0 * 4 + 3.0 * 4 + 4.0 * 8 + 4.0 * 8 * bd->nv;
+    ProfScope ps(c.prof, st, KK_XINV_DOTS, double(c.ng) * node_b + double(c.geom.cs) * lines * 2 * sizeof(float));
+    hipLaunchKernelGGL((k_xinv<float, float, double, NH, EPI_MATVEC, true>), dim3(grid), dim3(C::NT), 0, st, io_mv,
+                       reinterpret_cast<const cx<float>*>(c.spec), c.geom, na, c.tw_f[0], kd);
+    if ((e = hipGetLastError()) != hipSuccess) return e;
+  }
+  return reduce_partials_n(c, int(grid), bd->nv, dots_out, st);
 }
 
 template <typename T, typename TIn, typename TOut>
