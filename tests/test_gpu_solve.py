@@ -154,3 +154,30 @@ def test_fp32_ir_matches_fp64():
                 # inner iterations comparable to the float64 solve's
                 assert s32["iters"] <= 2 * s64["iters"] + 10, (prec, orth, s32["iters"], s64["iters"])
         ctx.close()
+
+
+@pytest.mark.parametrize("prec", ["fp64", "fp32_ir", "fp32_ir_left"])
+@pytest.mark.parametrize("restart", [1, 2, 5, 31])
+def test_restart_boundaries_match_dense_solve(prec, restart):
+    """Delayed-CGS2 cycles that run to the restart length (the last basis
+    direction and, in the precision form, the matvec's fused inner products
+    over all restart + 1 directions), from restart 1 to the largest the
+    delayed variant allows: a random right-hand side and a large shift make
+    the preconditioned system slow enough that every cycle is cut at the
+    restart length."""
+    nx, ny, nz = 8, 8, 1
+    announce(f"restart boundaries {prec} restart={restart}")
+    h = 1.0 / nx
+    g = Grid(nx, ny, nz, h=h)
+    prm, op = both_params(alpha=0.1, dt=5e-3, theta=1.0, shift=8.0)
+    m = unit_field((nz, ny, nx), 5)
+    b = np.random.default_rng(7).standard_normal((4, nz, ny, nx))
+    xs = dense.solve(g, op, m, b)
+    ctx = P.Context(nx, ny, nz, h, 0)
+    x, st = P.gmres_solve(ctx, prm, dev(m), dev(b), restart=restart, rtol=1e-12, prec=prec, inner_rtol=1e-12,
+                          max_outer=2000, maxiter=20000)
+    assert st["converged"] == 1 and st["rel_res_true"] <= 1e-12, st
+    # at least one cycle was cut at the restart length
+    assert st["iters"] > restart, st
+    assert rel(host(x), xs) <= 1e-9
+    ctx.close()
