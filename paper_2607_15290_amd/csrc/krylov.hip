@@ -206,6 +206,15 @@ __global__ __launch_bounds__(kRedThreads) void k_update_norm(const double* __res
 // elements' loads per thread, whose extra streams in flight lower the DRAM
 // efficiency).
 constexpr int kDcgsThreads = 512;
+// Unused dynamic LDS of the update pass: it caps the pass at two 512-thread
+// blocks per CU (16 waves).  Fewer concurrent vector streams keep the DRAM
+// pages of the j + 3 streams open longer: measured 3% faster than the
+// uncapped pass at 256^3 (one block per CU is 40% slower; the read-only
+// pass 1 gains nothing from the cap).
+#ifndef LLG_DCGS_UPDATE_LDS
+#define LLG_DCGS_UPDATE_LDS 65536
+#endif
+constexpr unsigned kDcgsUpdateLds = LLG_DCGS_UPDATE_LDS;
 
 template <int NV>
 __device__ __forceinline__ void dcgs_block_store(const double (&acc)[NV], double* __restrict__ partial) {
@@ -464,7 +473,7 @@ static void dd_t(const Ctx& c, const double* u0, const double* U1, long long ld,
 template <int J>
 static void du_t(const Ctx& c, const double* u0, const double* U1, long long ld, const double* gamma,
                  double inv_beta, const double* w, double* unew, long long n, hipStream_t st) {
-  hipLaunchKernelGGL((k_dcgs_update<J>), dim3(red_blocks(n / 2)), dim3(kDcgsThreads), 0, st,
+  hipLaunchKernelGGL((k_dcgs_update<J>), dim3(red_blocks(n / 2)), dim3(kDcgsThreads), kDcgsUpdateLds, st,
                      reinterpret_cast<const double2*>(u0), reinterpret_cast<const double2*>(U1), ld / 2, gamma,
                      inv_beta, reinterpret_cast<const double2*>(w), reinterpret_cast<double2*>(unew), n / 2,
                      c.partial);
