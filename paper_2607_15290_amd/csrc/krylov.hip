@@ -11,6 +11,7 @@
 // re-orthogonalization (CGS2), as three streaming passes over the basis:
 //   A: h = V^T w;   B: w -= V h, s = V^T w;   C: w -= V s, ||w||^2.
 #include <cmath>
+#include <cstdint>
 #include <utility>
 
 #include "krylov.h"
@@ -334,11 +335,49 @@ __global__ void k_axpby(long long n, double a, const double* __restrict__ x, dou
 }
 
 // x += sum_i c_i V_i, instantiated for the exact count K so the K basis loads
-// of an element are issued together.
-template <typename TV, int K>
+// of an element group are issued together.  With VEC each thread takes four
+// consecutive elements (one 16-byte load per float32 vector, two per float64
+// vector; the host checks the 16-byte alignment), otherwise one element.
+typedef float f32x4 __attribute__((ext_vector_type(4)));
+typedef double f64x2 __attribute__((ext_vector_type(2)));
+template <typename TV>
+__device__ __forceinline__ void ld4(const TV* p, TV (&v)[4]) {
+  if constexpr (sizeof(TV) == 4) {
+    const f32x4 a = __builtin_nontemporal_load(reinterpret_cast<const f32x4*>(p));
+    v[0] = a.x; v[1] = a.y; v[2] = a.z; v[3] = a.w;
+  } else {
+    const f64x2 a = __builtin_nontemporal_load(reinterpret_cast<const f64x2*>(p));
+    const f64x2 b = __builtin_nontemporal_load(reinterpret_cast<const f64x2*>(p) + 1);
+    v[0] = a.x; v[1] = a.y; v[2] = b.x; v[3] = b.y;
+  }
+}
+template <typename TV, int K, bool VEC>
 __global__ void k_lincomb(long long n, Coefs cf, const TV* __restrict__ V, long long ld, double* __restrict__ x) {
   const long long stride = (long long)gridDim.x * blockDim.x;
-  for (long long e = (long long)blockIdx.x * blockDim.x + threadIdx.x; e < n; e += stride) {
+  const long long t0 = (long long)blockIdx.x * blockDim.x + threadIdx.x;
+  long long done = 0;
+  if constexpr (VEC) {
+    const long long n4 = n / 4;
+    for (long long g = t0; g < n4; g += stride) {
+      const long long e = 4 * g;
+      TV vv[K > 0 ? K : 1][4];
+#pragma unroll
+      for (int i = 0; i < K; ++i) ld4(V + i * ld + e, vv[i]);
+      double2* xp = reinterpret_cast<double2*>(x + e);
+      double2 s0 = xp[0], s1 = xp[1];
+#pragma unroll
+      for (int i = 0; i < K; ++i) {
+        s0.x = fma(cf.c[i], double(vv[i][0]), s0.x);
+        s0.y = fma(cf.c[i], double(vv[i][1]), s0.y);
+        s1.x = fma(cf.c[i], double(vv[i][2]), s1.x);
+        s1.y = fma(cf.c[i], double(vv[i][3]), s1.y);
+      }
+      xp[0] = s0;
+      xp[1] = s1;
+    }
+    done = 4 * n4;
+  }
+  for (long long e = done + t0; e < n; e += stride) {
     TV vv[K > 0 ? K : 1];
 #pragma unroll
     for (int i = 0; i < K; ++i) vv[i] = __builtin_nontemporal_load(V + i * ld + e);
@@ -541,9 +580,15 @@ template <typename TV, int K>
 struct LincombF {
   static void go(const Ctx& c, long long n, const Coefs& cf, const TV* V, long long ld, double* x, hipStream_t st) {
     (void)c;
-    long long g = (n + 255) / 256;
+    const bool vec = (reinterpret_cast<uintptr_t>(V) % 16 == 0) && (reinterpret_cast<uintptr_t>(x) % 16 == 0) &&
+                     (ld % 4 == 0);
+    long long g = ((vec ? n / 4 : n) + 255) / 256;
     if (g > 65536) g = 65536;
-    hipLaunchKernelGGL((k_lincomb<TV, K>), dim3((unsigned)g), dim3(256), 0, st, n, cf, V, ld, x);
+    if (g < 1) g = 1;
+    if (vec)
+      hipLaunchKernelGGL((k_lincomb<TV, K, true>), dim3((unsigned)g), dim3(256), 0, st, n, cf, V, ld, x);
+    else
+      hipLaunchKernelGGL((k_lincomb<TV, K, false>), dim3((unsigned)g), dim3(256), 0, st, n, cf, V, ld, x);
   }
 };
 template <typename TV, int K = 1>
