@@ -150,9 +150,9 @@ llg_status ensure_device(const Ctx& c) {
 // ---- pipelines (float64) ---------------------------------------------------
 hipError_t pipe_d(const Ctx& c, int pro, int epi, const SymArgs& sym, const NodalArgs& na, const double* in,
                   const double* m, double* out, hipStream_t st, const double* aux_v = nullptr,
-                  const double* aux_r = nullptr) {
+                  const double* aux_r = nullptr, const BasisDots* bd = nullptr) {
   PipeIO<double, double, double> io{in, m, out, c.ng, aux_v, aux_r};
-  return run_pipeline<double, double, double>(c, pro, epi, sym, na, io, st);
+  return run_pipeline<double, double, double>(c, pro, epi, sym, na, io, st, bd, c.dots);
 }
 
 // A x (theta, k from p)
@@ -167,10 +167,11 @@ hipError_t op_apply(const Ctx& c, const llg_params* p, const double* m, const do
   return pipe_d(c, tr ? PRO_M2T : PRO_COPY3, tr ? EPI_APPLY_T : EPI_APPLY,
                 sym_for(c, p->alpha + p->shift, hcoef(p), true), nodal_for(p), x, m, z, st);
 }
-// M^{-1} A x in one pipeline
-hipError_t op_fused(const Ctx& c, const llg_params* p, const double* m, const double* x, double* z, hipStream_t st) {
+// M^{-1} A x in one pipeline (with bd: also the Arnoldi inner products of z in c.dots)
+hipError_t op_fused(const Ctx& c, const llg_params* p, const double* m, const double* x, double* z, hipStream_t st,
+                    const BasisDots* bd = nullptr) {
   return pipe_d(c, PRO_SMINUS, EPI_FUSED, sym_for(c, p->alpha + p->shift, hcoef(p), true), nodal_for(p), x, m, z,
-                st);
+                st, nullptr, nullptr, bd);
 }
 // (-Delta_N) u for 3 planes
 hipError_t op_lap(const Ctx& c, const double* u, double* out, hipStream_t st) {
@@ -369,9 +370,10 @@ struct CycleResult {
 
 // With op_dots the operator also leaves pass 1's p = U_{j+1}^T w in c.dots
 // (it receives the basis layout); otherwise it ignores that argument.
-// The precision form takes pass 1 inside its matvec's last x pass (measured
-// 2.5% more solves/s at 256^3 than the separate pass); 0 selects the
-// separate pass.
+// The fused M^{-1} A pass (float64 GMRES and the left precision variant) and
+// the precision form's matvec take delayed-CGS2 pass 1 inside their last x
+// pass (the precision form: measured 2.5% more solves/s at 256^3 than the
+// separate pass); 0 selects the separate pass.
 #ifndef LLG_FUSE_DOTS
 #define LLG_FUSE_DOTS 1
 #endif
@@ -484,8 +486,12 @@ struct SolveResult {
 
 // Left-preconditioned restarted GMRES (FP64) with true-residual acceptance.
 // A: true operator, M: preconditioner, MA: M^{-1} A.
+// MAd (optional): MA that also leaves the delayed-CGS2 pass-1 inner products
+// of its output in c.dots (run_pipeline's BasisDots).
+using OpDots = std::function<hipError_t(const double* in, double* out, const BasisDots* bd)>;
 llg_status gmres_left(const Ctx& c, const ResidOp& RA, const Op& M, const Op& MA, const double* b, double* x,
-                      const llg_solver_opts& o, Work& w, SolveResult& res, hipStream_t st) {
+                      const llg_solver_opts& o, Work& w, SolveResult& res, hipStream_t st,
+                      const OpDots* MAd = nullptr) {
   const long long n4 = 4 * c.ng;
   const int R = o.restart;
   double nb[2];
@@ -532,9 +538,11 @@ llg_status gmres_left(const Ctx& c, const ResidOp& RA, const Op& M, const Op& MA
       CHK(dot_and_norm(c, U0, nullptr, n4, c.scal, st));
       CHK_STATUS(fetch(c, c.scal, 2, st, un));
       CycleResult cr;
-      auto op = [&](int, const double* u, double* wout, const BasisDots*) { return MA(u, wout); };
-      CHK_STATUS(cycle_dcgs2(c, op, false, U0, U0 + n4, W, n4, un[1], R, target / rho, o.maxiter, res.iters, cr,
-                             st));
+      auto op = [&](int, const double* u, double* wout, const BasisDots* bq) {
+        return MAd ? (*MAd)(u, wout, bq) : MA(u, wout);
+      };
+      CHK_STATUS(cycle_dcgs2(c, op, MAd != nullptr && LLG_FUSE_DOTS != 0, U0, U0 + n4, W, n4, un[1], R,
+                             target / rho, o.maxiter, res.iters, cr, st));
       if (!is_fin(cr.beta0)) return fail(LLG_ENAN, "non-finite preconditioned residual");
       if (beta0 < 0) beta0 = cr.beta0;
       res.rel_prec = beta0 > 0 ? cr.gres / beta0 : 0.0;
@@ -640,13 +648,14 @@ llg_status gmres_ir(const Ctx& c, const llg_params* p, const double* m, const do
       double un[2];
       CHK(dot_and_norm(c, Q, nullptr, n4, c.scal, st));
       CHK_STATUS(fetch(c, c.scal, 2, st, un));
-      auto opl = [&](int, const double* u, double* wout, const BasisDots*) -> hipError_t {
+      auto opl = [&](int, const double* u, double* wout, const BasisDots* bq) -> hipError_t {
         PipeIO<float, double, double> io{u, w.m32, wout, c.ng, nullptr, nullptr};
-        return run_pipeline<float, double, double>(c, PRO_SMINUS, EPI_FUSED, sym_ap, na, io, st);
+        return run_pipeline<float, double, double>(c, PRO_SMINUS, EPI_FUSED, sym_ap, na, io, st, bq, c.dots);
       };
       CycleResult cr;
       if (o.orth == 0) {
-        CHK_STATUS(cycle_dcgs2(c, opl, false, Q, Q + n4, W, n4, un[1], R, eta, o.maxiter, res.iters, cr, st));
+        CHK_STATUS(cycle_dcgs2(c, opl, LLG_FUSE_DOTS != 0, Q, Q + n4, W, n4, un[1], R, eta, o.maxiter, res.iters,
+                               cr, st));
       } else {
         const double beta = std::sqrt(un[1]);
         if (!is_fin(beta)) return fail(LLG_ENAN, "non-finite preconditioned residual");
@@ -750,7 +759,10 @@ llg_status solve(const Ctx& c, const llg_params* p, const double* m, const doubl
   }
   Op M = [&](const double* in, double* out) { return op_apply(c, p, m, in, out, false, st); };
   Op MA = [&](const double* in, double* out) { return op_fused(c, p, m, in, out, st); };
-  return gmres_left(c, RA, M, MA, b, x, o, w, res, st);
+  OpDots MAd = [&](const double* in, double* out, const BasisDots* bd) {
+    return op_fused(c, p, m, in, out, st, bd);
+  };
+  return gmres_left(c, RA, M, MA, b, x, o, w, res, st, &MAd);
 }
 
 void fill_stats(const SolveResult& r, llg_solver_stats* s) {

@@ -70,9 +70,12 @@ SymArgs sym_for(const Ctx& c, double a, double b, bool invert);
 
 // Launch one spectral pipeline (pipeline.h).  Defined per type combination
 // in the pipeline_*.hip translation units.
+// With bd (bd->nv > 0; fused M^{-1} A passes with a float64 output only) the
+// last pass also leaves the Arnoldi inner products u_q . out in dots_out.
 template <typename T, typename TIn, typename TOut>
 hipError_t run_pipeline(const Ctx& c, int pro, int epi, const SymArgs& sym, const NodalArgs& na,
-                        const PipeIO<T, TIn, TOut>& io, hipStream_t st);
+                        const PipeIO<T, TIn, TOut>& io, hipStream_t st, const BasisDots* bd = nullptr,
+                        double* dots_out = nullptr);
 
 // Precision-form inner operator (pipeline_f32.hip): z = M^{-1} v (float32,
 // stored) and w = A z (float32, float64 result), the two pipelines joined by

@@ -6,13 +6,17 @@
 
 namespace llg {
 template hipError_t run_pipeline<float, float, float>(const Ctx&, int, int, const SymArgs&, const NodalArgs&,
-                                                      const PipeIO<float, float, float>&, hipStream_t);
+                                                      const PipeIO<float, float, float>&, hipStream_t,
+                                                         const BasisDots*, double*);
 template hipError_t run_pipeline<float, double, float>(const Ctx&, int, int, const SymArgs&, const NodalArgs&,
-                                                       const PipeIO<float, double, float>&, hipStream_t);
+                                                       const PipeIO<float, double, float>&, hipStream_t,
+                                                         const BasisDots*, double*);
 template hipError_t run_pipeline<float, float, double>(const Ctx&, int, int, const SymArgs&, const NodalArgs&,
-                                                       const PipeIO<float, float, double>&, hipStream_t);
+                                                       const PipeIO<float, float, double>&, hipStream_t,
+                                                         const BasisDots*, double*);
 template hipError_t run_pipeline<float, double, double>(const Ctx&, int, int, const SymArgs&, const NodalArgs&,
-                                                        const PipeIO<float, double, double>&, hipStream_t);
+                                                        const PipeIO<float, double, double>&, hipStream_t,
+                                                         const BasisDots*, double*);
 
 hipError_t run_apply_matvec(const Ctx& c, const SymArgs& sym_ap, const SymArgs& sym_mv, const NodalArgs& na,
                             const double* v, const float* m32, float* z, double* w, hipStream_t st,

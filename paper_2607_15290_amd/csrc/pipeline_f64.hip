@@ -3,5 +3,6 @@
 
 namespace llg {
 template hipError_t run_pipeline<double, double, double>(const Ctx&, int, int, const SymArgs&, const NodalArgs&,
-                                                         const PipeIO<double, double, double>&, hipStream_t);
+                                                         const PipeIO<double, double, double>&, hipStream_t,
+                                                         const BasisDots*, double*);
 }  // namespace llg

@@ -462,16 +462,17 @@ __global__ __launch_bounds__(192) void k_xfwd(const TIn* __restrict__ in, const 
 // ---------------------------------------------------------------------------
 // k_xinv
 // ---------------------------------------------------------------------------
-// With DOTS (float32 matvec writing a float64 Krylov vector only) the pass
-// also forms the inner products of its output with the Arnoldi basis
-// directions (BasisDots), from the output values it still holds in
-// registers: the separate inner-product pass and its read of the output
-// disappear.
+// With DOTS (a matvec or fused M^{-1} A pass writing a float64 Krylov
+// vector) the pass also forms the inner products of its output with the
+// Arnoldi basis directions (BasisDots), from the output values it still
+// holds in registers: the separate inner-product pass and its read of the
+// output disappear.
 template <typename T, typename TIn, typename TOut, int NH, int EPI, bool DOTS = false>
 __global__ __launch_bounds__(192) void k_xinv(PipeIO<T, TIn, TOut> io, const cx<T>* __restrict__ spec,
                                               SpecGeom g, NodalArgs na, const cx<T>* __restrict__ twx,
                                               BasisDots bd) {
-  static_assert(!DOTS || (EPI == EPI_MATVEC && std::is_same<TOut, double>::value), "dots: float64 matvec output");
+  static_assert(!DOTS || ((EPI == EPI_MATVEC || EPI == EPI_FUSED) && std::is_same<TOut, double>::value),
+                "dots: float64 Krylov output of a matvec or fused pass");
   using C = XCfg<T, NH>;
   __shared__ cx<T> lds[3 * C::LX * C::SL];
   const int tid = threadIdx.x;

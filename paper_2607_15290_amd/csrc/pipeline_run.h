@@ -43,6 +43,21 @@ void launch_xfwd(const Ctx& c, const NodalArgs& na, const PipeIO<T, TIn, TOut>& 
   }
 }
 
+// Per-node bytes of an x-inverse epilogue's plane reads and writes.
+template <typename T, typename TIn, typename TOut, int EPI>
+double xinv_node_bytes(const NodalArgs& na, const PipeIO<T, TIn, TOut>& io) {
+  double node_b = 0;
+  if (EPI == EPI_STORE3) node_b = 3.0 * sizeof(TOut);
+  else if (EPI == EPI_RHS) node_b = 4.0 * sizeof(TOut) + (na.hfield ? 24.0 : 0.0);
+  else if (EPI == EPI_APPLY) node_b = 1.0 * sizeof(TIn) + 3.0 * sizeof(T) + 4.0 * sizeof(TOut);
+  else if (EPI == EPI_APPLY_SYM) node_b = 1.0 * sizeof(TIn) + 4.0 * sizeof(TOut);
+  else if (EPI == EPI_JT) node_b = 4.0 * sizeof(TIn) + 7.0 * sizeof(T) + 4.0 * sizeof(TOut);
+  else if (EPI == EPI_ADDF) node_b = 3.0 * sizeof(T) + 4.0 * sizeof(TOut);
+  else node_b = 4.0 * sizeof(TIn) + 3.0 * sizeof(T) + 4.0 * sizeof(TOut);
+  if (io.rhs) node_b += 4.0 * sizeof(TOut);
+  return node_b;
+}
+
 template <typename T, typename TIn, typename TOut, int NH, int EPI>
 void launch_xinv(const Ctx& c, const NodalArgs& na, const PipeIO<T, TIn, TOut>& io, hipStream_t st) {
   if constexpr (has_epi<T, TIn, TOut>(EPI)) {
@@ -51,24 +66,41 @@ void launch_xinv(const Ctx& c, const NodalArgs& na, const PipeIO<T, TIn, TOut>& 
     const unsigned grid = (unsigned)((lines + C::LX - 1) / C::LX);
     const cx<T>* tw;
     if constexpr (std::is_same<T, double>::value) tw = c.tw_d[0]; else tw = c.tw_f[0];
-    double node_b = 0;  // per-node bytes of the epilogue reads and writes
-    if (EPI == EPI_STORE3) node_b = 3.0 * sizeof(TOut);
-    else if (EPI == EPI_RHS) node_b = 4.0 * sizeof(TOut) + (na.hfield ? 24.0 : 0.0);
-    else if (EPI == EPI_APPLY) node_b = 1.0 * sizeof(TIn) + 3.0 * sizeof(T) + 4.0 * sizeof(TOut);
-    else if (EPI == EPI_APPLY_SYM) node_b = 1.0 * sizeof(TIn) + 4.0 * sizeof(TOut);
-    else if (EPI == EPI_JT) node_b = 4.0 * sizeof(TIn) + 7.0 * sizeof(T) + 4.0 * sizeof(TOut);
-    else if (EPI == EPI_ADDF) node_b = 3.0 * sizeof(T) + 4.0 * sizeof(TOut);
-    else node_b = 4.0 * sizeof(TIn) + 3.0 * sizeof(T) + 4.0 * sizeof(TOut);
-    if (io.rhs) node_b += 4.0 * sizeof(TOut);
+    const double node_b = xinv_node_bytes<T, TIn, TOut, EPI>(na, io);
     ProfScope ps(c.prof, st, KK_XINV, double(c.ng) * node_b + double(c.geom.cs) * lines * 2 * sizeof(T));
     hipLaunchKernelGGL((k_xinv<T, TIn, TOut, NH, EPI>), dim3(grid), dim3(C::NT), 0, st, io,
                        reinterpret_cast<const cx<T>*>(c.spec), c.geom, na, tw, BasisDots{});
   }
 }
 
+// x-inverse pass that also forms the Arnoldi inner products of its float64
+// output (dots_out[q] = u_q . out, q < bd.nv, on the device).
+template <typename T, typename TIn, typename TOut, int NH, int EPI>
+hipError_t launch_xinv_dots(const Ctx& c, const NodalArgs& na, const PipeIO<T, TIn, TOut>& io, const BasisDots& bd,
+                            double* dots_out, hipStream_t st) {
+  using C = XCfg<T, NH>;
+  if (bd.nv < 1 || bd.nv > kBasisDotsMax || io.rhs) return hipErrorInvalidValue;
+  const long long lines = (long long)c.ny * c.nz;
+  const unsigned grid = (unsigned)((lines + C::LX - 1) / C::LX);
+  if (grid > (unsigned)kRedBlocksMax) return hipErrorInvalidValue;
+  const cx<T>* tw;
+  if constexpr (std::is_same<T, double>::value) tw = c.tw_d[0]; else tw = c.tw_f[0];
+  BasisDots kd = bd;
+  kd.partial = c.partial;
+  {
+    const double node_b = xinv_node_bytes<T, TIn, TOut, EPI>(na, io) + 4.0 * 8 * bd.nv;
+    ProfScope ps(c.prof, st, KK_XINV_DOTS, double(c.ng) * node_b + double(c.geom.cs) * lines * 2 * sizeof(T));
+    hipLaunchKernelGGL((k_xinv<T, TIn, TOut, NH, EPI, true>), dim3(grid), dim3(C::NT), 0, st, io,
+                       reinterpret_cast<const cx<T>*>(c.spec), c.geom, na, tw, kd);
+    hipError_t e = hipGetLastError();
+    if (e != hipSuccess) return e;
+  }
+  return reduce_partials_n(c, int(grid), bd.nv, dots_out, st);
+}
+
 template <typename T, typename TIn, typename TOut, int NH>
 hipError_t run_nh(const Ctx& c, int pro, int epi, const SymArgs& sym, const NodalArgs& na,
-                  const PipeIO<T, TIn, TOut>& io, hipStream_t st) {
+                  const PipeIO<T, TIn, TOut>& io, hipStream_t st, const BasisDots* bd, double* dots_out) {
   // a mode without an instantiation for this type combination is an error,
   // never a silently skipped pass
   if (!has_pro<T, TIn, TOut>(pro) || !has_epi<T, TIn, TOut>(epi)) return hipErrorInvalidValue;
@@ -86,6 +118,15 @@ hipError_t run_nh(const Ctx& c, int pro, int epi, const SymArgs& sym, const Noda
     if ((e = launch_axis<T>(c, 1, 0, sym, spec, st)) != hipSuccess) return e;
     if ((e = launch_axis<T>(c, 2, 2, sym, spec, st)) != hipSuccess) return e;
     if ((e = launch_axis<T>(c, 1, 1, sym, spec, st)) != hipSuccess) return e;
+  }
+  if (bd && bd->nv > 0) {
+    // the Arnoldi inner products ride on the fused M^{-1} A pass only
+    if constexpr (std::is_same<TOut, double>::value && has_epi<T, TIn, TOut>(EPI_FUSED)) {
+      if (epi != EPI_FUSED) return hipErrorInvalidValue;
+      return launch_xinv_dots<T, TIn, TOut, NH, EPI_FUSED>(c, na, io, *bd, dots_out, st);
+    } else {
+      return hipErrorInvalidValue;
+    }
   }
   switch (epi) {
     case EPI_STORE3: launch_xinv<T, TIn, TOut, NH, EPI_STORE3>(c, na, io, st); break;
@@ -143,28 +184,15 @@ hipError_t run_apply_matvec_nh(const Ctx& c, const SymArgs& sym_ap, const SymArg
     return hipGetLastError();
   }
   // matvec with the Arnoldi inner products of w (out[q] = u_q . w, q < nv)
-  if (bd->nv > kBasisDotsMax) return hipErrorInvalidValue;
-  const long long lines = (long long)c.ny * c.nz;
-  const unsigned grid = (unsigned)((lines + C::LX - 1) / C::LX);
-  if (grid > (unsigned)kRedBlocksMax) return hipErrorInvalidValue;
-  BasisDots kd = *bd;
-  kd.partial = c.partial;
-  {
-    const double node_b = 4.0 * 4 + 3.0 * 4 + 4.0 * 8 + 4.0 * 8 * bd->nv;
-    ProfScope ps(c.prof, st, KK_XINV_DOTS, double(c.ng) * node_b + double(c.geom.cs) * lines * 2 * sizeof(float));
-    hipLaunchKernelGGL((k_xinv<float, float, double, NH, EPI_MATVEC, true>), dim3(grid), dim3(C::NT), 0, st, io_mv,
-                       reinterpret_cast<const cx<float>*>(c.spec), c.geom, na, c.tw_f[0], kd);
-    if ((e = hipGetLastError()) != hipSuccess) return e;
-  }
-  return reduce_partials_n(c, int(grid), bd->nv, dots_out, st);
+  return launch_xinv_dots<float, float, double, NH, EPI_MATVEC>(c, na, io_mv, *bd, dots_out, st);
 }
 
 template <typename T, typename TIn, typename TOut>
 hipError_t run_pipeline(const Ctx& c, int pro, int epi, const SymArgs& sym, const NodalArgs& na,
-                        const PipeIO<T, TIn, TOut>& io, hipStream_t st) {
+                        const PipeIO<T, TIn, TOut>& io, hipStream_t st, const BasisDots* bd, double* dots_out) {
   switch (c.geom.nh) {
 #define LLG_CASE(n) \
-  case n: return run_nh<T, TIn, TOut, n>(c, pro, epi, sym, na, io, st);
+  case n: return run_nh<T, TIn, TOut, n>(c, pro, epi, sym, na, io, st, bd, dots_out);
     LLG_FOR_NH(LLG_CASE)
 #undef LLG_CASE
     default: return hipErrorInvalidValue;
