@@ -82,7 +82,14 @@ hipError_t launch_xinv_dots(const Ctx& c, const NodalArgs& na, const PipeIO<T, T
   if (bd.nv < 1 || bd.nv > kBasisDotsMax || io.rhs) return hipErrorInvalidValue;
   const long long lines = (long long)c.ny * c.nz;
   const unsigned grid = (unsigned)((lines + C::LX - 1) / C::LX);
-  if (grid > (unsigned)kRedBlocksMax) return hipErrorInvalidValue;
+  if (grid > (unsigned)kRedBlocksMax) {
+    // more blocks than partial rows (the largest grids in float64): plain
+    // pass, then the separate inner-product pass over the output
+    launch_xinv<T, TIn, TOut, NH, EPI>(c, na, io, st);
+    const hipError_t e = hipGetLastError();
+    if (e != hipSuccess) return e;
+    return dcgs_dots(c, bd.u0, bd.U1, bd.ld, bd.nv - 1, io.out, 4 * c.ng, dots_out, st);
+  }
   const cx<T>* tw;
   if constexpr (std::is_same<T, double>::value) tw = c.tw_d[0]; else tw = c.tw_f[0];
   BasisDots kd = bd;
