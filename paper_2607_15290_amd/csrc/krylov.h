@@ -68,8 +68,6 @@ hipError_t lincomb(const Ctx& c, long long n, const Coefs& cf, const float* V, l
 hipError_t to_f32(const Ctx& c, long long n, const double* a, float* b, hipStream_t st);
 // out[0] = x.y (x.x if y null), out[1] = x.x
 hipError_t dot_and_norm(const Ctx& c, const double* x, const double* y, long long n, double* out, hipStream_t st);
-// out[0] = ||a - b||^2 (b may be null), out[1] = ||a||^2
-hipError_t diff_norms(const Ctx& c, const double* a, const double* b, long long n, double* out, hipStream_t st);
 
 // ---- nodal.hip ----
 // out[0] = min_i |m_i|^2, out[1] = 1 if any entry of m is non-finite

@@ -407,19 +407,6 @@ __global__ __launch_bounds__(kRedThreads) void k_dot2(const double* __restrict__
   block_store<2>(acc, 2, partial);
 }
 
-// sum (a - b)^2 and sum a^2
-__global__ __launch_bounds__(kRedThreads) void k_diffnorm(const double* __restrict__ a, const double* __restrict__ b,
-                                                         long long n, double* __restrict__ partial) {
-  double acc[2] = {0.0, 0.0};
-  const long long stride = (long long)gridDim.x * blockDim.x;
-  for (long long e = (long long)blockIdx.x * blockDim.x + threadIdx.x; e < n; e += stride) {
-    const double av = a[e], d = av - (b ? b[e] : 0.0);
-    acc[0] = fma(d, d, acc[0]);
-    acc[1] = fma(av, av, acc[1]);
-  }
-  block_store<2>(acc, 2, partial);
-}
-
 // ---- host launchers --------------------------------------------------------
 static inline unsigned grid_for(long long n) {
   long long g = (n + 255) / 256;
@@ -635,14 +622,6 @@ hipError_t dot_and_norm(const Ctx& c, const double* x, const double* y, long lon
   {
   ProfScope ps(c.prof, st, KK_DOT2, 8.0 * n * (y ? 2 : 1));
   hipLaunchKernelGGL(k_dot2, dim3(nodal_blocks(n)), dim3(kRedThreads), 0, st, x, y, n, c.partial);
-  }
-  return reduce_partials(c, nodal_blocks(n), 2, out, false, st);
-}
-
-hipError_t diff_norms(const Ctx& c, const double* a, const double* b, long long n, double* out, hipStream_t st) {
-  {
-  ProfScope ps(c.prof, st, KK_DOT2, 8.0 * n * (b ? 2 : 1));
-  hipLaunchKernelGGL(k_diffnorm, dim3(nodal_blocks(n)), dim3(kRedThreads), 0, st, a, b, n, c.partial);
   }
   return reduce_partials(c, nodal_blocks(n), 2, out, false, st);
 }
