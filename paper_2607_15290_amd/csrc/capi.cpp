@@ -482,6 +482,15 @@ llg_status cycle_dcgs2(const Ctx& c, const ArnoldiOp& op, bool op_dots, const do
 struct SolveResult {
   int iters = 0, cycles = 0, outer = 0, converged = 0;
   double rel_true = 0, rel_prec = 0;
+  double bnorm = -1;  // ||b||_2 as computed (or taken from the hints)
+};
+
+// What a caller that solves repeatedly (the midpoint Picard loop) already
+// knows about the inputs of the next solve.
+struct SolveHints {
+  double bnorm = -1;       // ||b||_2 of an unchanged b (< 0: unknown)
+  bool m_checked = false;  // m is finite with no zero node
+  bool m32_ready = false;  // the workspace's float32 m holds float(m)
 };
 
 // Left-preconditioned restarted GMRES (FP64) with true-residual acceptance.
@@ -491,13 +500,17 @@ struct SolveResult {
 using OpDots = std::function<hipError_t(const double* in, double* out, const BasisDots* bd)>;
 llg_status gmres_left(const Ctx& c, const ResidOp& RA, const Op& M, const Op& MA, const double* b, double* x,
                       const llg_solver_opts& o, Work& w, SolveResult& res, hipStream_t st,
-                      const OpDots* MAd = nullptr) {
+                      const OpDots* MAd = nullptr, const SolveHints& hints = {}) {
   const long long n4 = 4 * c.ng;
   const int R = o.restart;
-  double nb[2];
-  CHK(dot_and_norm(c, b, nullptr, n4, c.scal, st));
-  CHK_STATUS(fetch(c, c.scal, 2, st, nb));
-  const double bnorm = std::sqrt(nb[1]);
+  double bnorm = hints.bnorm;
+  if (bnorm < 0) {
+    double nb[2];
+    CHK(dot_and_norm(c, b, nullptr, n4, c.scal, st));
+    CHK_STATUS(fetch(c, c.scal, 2, st, nb));
+    bnorm = std::sqrt(nb[1]);
+  }
+  res.bnorm = bnorm;
   if (!is_fin(bnorm)) return fail(LLG_ENAN, "right-hand side is not finite");
   if (bnorm == 0.0) {
     CHK(hipMemsetAsync(x, 0, sizeof(double) * n4, st));
@@ -591,17 +604,21 @@ llg_status gmres_left(const Ctx& c, const ResidOp& RA, const Op& M, const Op& MA
 // or around left-preconditioned GMRES on the fused float32 M^{-1} A
 // (LLG_FP32_IR_LEFT, one float32 pipeline per inner iteration).
 llg_status gmres_ir(const Ctx& c, const llg_params* p, const double* m, const double* b, double* x,
-                    const llg_solver_opts& o, Work& w, SolveResult& res, hipStream_t st) {
+                    const llg_solver_opts& o, Work& w, SolveResult& res, hipStream_t st, const SolveHints& hints) {
   const long long n4 = 4 * c.ng;
   const int R = o.restart;
-  CHK(to_f32(c, 3 * c.ng, m, w.m32, st));
+  if (!hints.m32_ready) CHK(to_f32(c, 3 * c.ng, m, w.m32, st));
   const SymArgs sym_ap = sym_for(c, p->alpha + p->shift, hcoef(p), true);
   const SymArgs sym_mv = sym_for(c, p->alpha, hcoef(p), false);
   const NodalArgs na = nodal_for(p);
-  double nb[2];
-  CHK(dot_and_norm(c, b, nullptr, n4, c.scal, st));
-  CHK_STATUS(fetch(c, c.scal, 2, st, nb));
-  const double bnorm = std::sqrt(nb[1]);
+  double bnorm = hints.bnorm;
+  if (bnorm < 0) {
+    double nb[2];
+    CHK(dot_and_norm(c, b, nullptr, n4, c.scal, st));
+    CHK_STATUS(fetch(c, c.scal, 2, st, nb));
+    bnorm = std::sqrt(nb[1]);
+  }
+  res.bnorm = bnorm;
   if (!is_fin(bnorm)) return fail(LLG_ENAN, "right-hand side is not finite");
   if (bnorm == 0.0) {
     CHK(hipMemsetAsync(x, 0, sizeof(double) * n4, st));
@@ -735,9 +752,9 @@ llg_status check_m(const Ctx& c, const double* m, hipStream_t st) {
 }
 
 llg_status solve(const Ctx& c, const llg_params* p, const double* m, const double* b, double* x,
-                 const llg_solver_opts& o, Work& w, SolveResult& res, hipStream_t st) {
-  CHK_STATUS(check_m(c, m, st));
-  if (o.prec != LLG_FP64) return gmres_ir(c, p, m, b, x, o, w, res, st);
+                 const llg_solver_opts& o, Work& w, SolveResult& res, hipStream_t st, const SolveHints& hints = {}) {
+  if (!hints.m_checked) CHK_STATUS(check_m(c, m, st));
+  if (o.prec != LLG_FP64) return gmres_ir(c, p, m, b, x, o, w, res, st, hints);
   const ResidOp RA = resid_op(c, EPI_MATVEC, sym_for(c, p->alpha, hcoef(p), false), nodal_for(p), m, st);
   if (o.precond == 1) {  // symmetric part (lambda I + calH)^{-1}
     const SymArgs sa = sym_for(c, p->alpha + p->shift, hcoef(p), true);
@@ -747,7 +764,7 @@ llg_status solve(const Ctx& c, const llg_params* p, const double* m, const doubl
     Op MA = [&](const double* in, double* out) {
       return pipe_d(c, PRO_SMINUS, EPI_FUSED_SYM, sa, nodal_for(p), in, m, out, st);
     };
-    return gmres_left(c, RA, M, MA, b, x, o, w, res, st);
+    return gmres_left(c, RA, M, MA, b, x, o, w, res, st, nullptr, hints);
   }
   if (o.precond == 2) {  // no preconditioner
     const long long n4 = 4 * c.ng;
@@ -755,14 +772,14 @@ llg_status solve(const Ctx& c, const llg_params* p, const double* m, const doubl
       return hipMemcpyAsync(out, in, sizeof(double) * n4, hipMemcpyDeviceToDevice, st);
     };
     Op MA = [&](const double* in, double* out) { return op_matvec(c, p, m, in, out, false, st); };
-    return gmres_left(c, RA, M, MA, b, x, o, w, res, st);
+    return gmres_left(c, RA, M, MA, b, x, o, w, res, st, nullptr, hints);
   }
   Op M = [&](const double* in, double* out) { return op_apply(c, p, m, in, out, false, st); };
   Op MA = [&](const double* in, double* out) { return op_fused(c, p, m, in, out, st); };
   OpDots MAd = [&](const double* in, double* out, const BasisDots* bd) {
     return op_fused(c, p, m, in, out, st, bd);
   };
-  return gmres_left(c, RA, M, MA, b, x, o, w, res, st, &MAd);
+  return gmres_left(c, RA, M, MA, b, x, o, w, res, st, &MAd, hints);
 }
 
 void fill_stats(const SolveResult& r, llg_solver_stats* s) {
@@ -1106,18 +1123,31 @@ llg_status llg_step_midpoint(llg_ctx* ctx, const llg_params* prm, double* m, dou
   bool pconv = false, lconv = true;
   double change = 0;
   llg_status lin = LLG_OK;
+  // Later solves of the loop reuse what the previous iteration established:
+  // ||b|| (b is fixed within the step unless the lower-order field is
+  // refrozen), the zero-node test and the float32 copy of m_hat (both from
+  // the Picard update that formed m_hat).
+  SolveHints hints;
+  float* mh32 = opts->prec != LLG_FP64 ? w.m32 : nullptr;
   for (int p = 0; p < picard_max; ++p) {
-    if (low) CHK(op_field(c, fa_low, EPI_ADDF, na2, w.mh, w.b, st, nullptr, w.l0));
+    if (low) {
+      CHK(op_field(c, fa_low, EPI_ADDF, na2, w.mh, w.b, st, nullptr, w.l0));
+      hints.bnorm = -1;
+    }
     SolveResult r;
-    lin = solve(c, &p2, w.mh, w.b, w.x, o, w, r, st);
+    lin = solve(c, &p2, w.mh, w.b, w.x, o, w, r, st, hints);
     iters += r.iters;
     pic++;
     if (lin != LLG_OK && lin != LLG_ENOCONV) return lin;
     if (lin == LLG_ENOCONV) lconv = false;
-    // ||v^p - v^{p-1}||^2, ||v^p||^2, ||m_hat^{p+1}||^2; vold <- v^p, mh <- m_hat^{p+1}
-    double dn[3];
-    CHK(picard_update(c, w.m0, w.x, w.vold, w.mh, 0.5 * k, c.scal, st));
-    CHK_STATUS(fetch(c, c.scal, 3, st, dn));
+    if (!low) hints.bnorm = r.bnorm;
+    // ||v^p - v^{p-1}||^2, ||v^p||^2, ||m_hat^{p+1}||^2, zero nodes of m_hat^{p+1};
+    // vold <- v^p, mh <- m_hat^{p+1} (and its float32 copy)
+    double dn[4];
+    CHK(picard_update(c, w.m0, w.x, w.vold, w.mh, 0.5 * k, c.scal, st, mh32));
+    CHK_STATUS(fetch(c, c.scal, 4, st, dn));
+    hints.m_checked = true;
+    hints.m32_ready = mh32 != nullptr;
     const double dd = std::sqrt(dn[0]);
     const double num = opts->picard_norm == 0 ? 0.5 * k * dd : dd;
     const double ref = std::sqrt(opts->picard_norm == 0 ? dn[2] : dn[1]);
@@ -1127,6 +1157,7 @@ llg_status llg_step_midpoint(llg_ctx* ctx, const llg_params* prm, double* m, dou
       pconv = true;
       break;
     }
+    if (dn[3] > 0) return fail(LLG_EZERO_M, "some nodal midpoint magnetization is zero (Proposition 1 needs m_i != 0)");
   }
   CHK(nodal_axpy3(c, w.m0, k, w.x, m, st));
   if (v_half) CHK(hipMemcpyAsync(v_half, w.x, sizeof(double) * 3 * ng, hipMemcpyDeviceToDevice, st));

@@ -95,17 +95,26 @@ __global__ void k_axpy3(const double* __restrict__ m, double a, const double* __
 __global__ __launch_bounds__(kRedThreads) void k_picard_update(const double* __restrict__ m0,
                                                               const double* __restrict__ v,
                                                               double* __restrict__ vold, double* __restrict__ mh,
-                                                              double a, long long n, double* __restrict__ partial) {
-  double acc[3] = {0, 0, 0};
-  GRID_LOOP(i, n) {
-    const double vi = v[i], d = vi - vold[i], mi = m0[i] + a * vi;
-    acc[0] += d * d;
-    acc[1] += vi * vi;
-    acc[2] += mi * mi;
-    vold[i] = vi;
-    mh[i] = mi;
+                                                              float* __restrict__ mh32, double a, long long ng,
+                                                              double* __restrict__ partial) {
+  double acc[4] = {0, 0, 0, 0};
+  GRID_LOOP(i, ng) {
+    double mm = 0;
+#pragma unroll
+    for (int f = 0; f < 3; ++f) {
+      const long long j = f * ng + i;
+      const double vi = v[j], d = vi - vold[j], mi = m0[j] + a * vi;
+      acc[0] += d * d;
+      acc[1] += vi * vi;
+      mm += mi * mi;
+      vold[j] = vi;
+      mh[j] = mi;
+      if (mh32) mh32[j] = float(mi);
+    }
+    acc[2] += mm;
+    acc[3] += mm <= 1e-300 ? 1.0 : 0.0;
   }
-  bstore<3, 0>(acc, partial);
+  bstore<4, 0>(acc, partial);
 }
 
 __global__ __launch_bounds__(kRedThreads) void k_len_err(const double* __restrict__ m, long long ng,
@@ -298,13 +307,13 @@ hipError_t midpoint_diag(const Ctx& c, const NodalArgs& na, double alpha, double
 }
 
 hipError_t picard_update(const Ctx& c, const double* m0, const double* v, double* vold, double* mh, double a,
-                         double* out, hipStream_t st) {
+                         double* out, hipStream_t st, float* mh32) {
   hipError_t e_ = hipSuccess;
   {
   ProfScope ps(c.prof, st, KK_NODAL, 0.0);
-  hipLaunchKernelGGL(k_picard_update, dim3(nodal_blocks(3 * c.ng)), dim3(kRedThreads), 0, st, m0, v, vold, mh, a,
-                     3 * c.ng, c.partial);
-  e_ = reduce_partials(c, nodal_blocks(3 * c.ng), 3, out, false, st);
+  hipLaunchKernelGGL(k_picard_update, dim3(nodal_blocks(c.ng)), dim3(kRedThreads), 0, st, m0, v, vold, mh, mh32, a,
+                     c.ng, c.partial);
+  e_ = reduce_partials(c, nodal_blocks(c.ng), 4, out, false, st);
   }
   return e_;
 }
