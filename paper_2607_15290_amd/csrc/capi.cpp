@@ -178,9 +178,13 @@ hipError_t op_lap(const Ctx& c, const double* u, double* out, hipStream_t st) {
   NodalArgs na{};
   return pipe_d(c, PRO_COPY3, EPI_STORE3, sym_for(c, 0.0, 1.0, false), na, u, nullptr, out, st);
 }
-// b = (C_hat Delta_N m + (1+alpha^2) h_ext, 0)
-hipError_t op_rhs(const Ctx& c, const llg_params* p, const double* m, double* b, hipStream_t st) {
-  return pipe_d(c, PRO_COPY3, EPI_RHS, sym_for(c, 0.0, 1.0, false), nodal_for(p), m, nullptr, b, st);
+// b = (C_hat Delta_N m + (1+alpha^2) h_ext, 0); with lap, also (-Delta_N) m (as op_lap)
+hipError_t op_rhs(const Ctx& c, const llg_params* p, const double* m, double* b, hipStream_t st,
+                  double* lap = nullptr) {
+  PipeIO<double, double, double> io{m, nullptr, b, c.ng, nullptr, nullptr};
+  io.out_f = lap;
+  return run_pipeline<double, double, double>(c, PRO_COPY3, EPI_RHS, sym_for(c, 0.0, 1.0, false), nodal_for(p), io,
+                                              st);
 }
 // One lower-order field pipeline (3x3 multiplier fa, prologue PRO_COPY3).
 hipError_t op_field(const Ctx& c, const FieldArgs& fa, int epi, const NodalArgs& na, const double* in, double* out,
@@ -1105,7 +1109,9 @@ llg_status llg_step_midpoint(llg_ctx* ctx, const llg_params* prm, double* m, dou
   // With a lower-order field it is kept in l0 and (1+alpha^2) L_low m_hat^p is
   // added at every Picard iteration (the field frozen at the midpoint, eq. "C-N").
   const bool low = has_low(prm);
-  CHK(op_rhs(c, &p2, w.m0, w.b, st));
+  // without a lower-order field the diagnostics' (-Delta_N) m^n comes with the RHS
+  const bool lap0 = !low && stats;
+  CHK(op_rhs(c, &p2, w.m0, w.b, st, lap0 ? w.l0 : nullptr));
   if (low) CHK(hipMemcpyAsync(w.l0, w.b, sizeof(double) * 3 * ng, hipMemcpyDeviceToDevice, st));
   const FieldArgs fa_low = field_for(c, prm, 0.0, 0.0, 1.0);
   const NodalArgs na2 = nodal_for(&p2);
@@ -1178,7 +1184,7 @@ llg_status llg_step_midpoint(llg_ctx* ctx, const llg_params* prm, double* m, dou
       nd.chat = nd.hs;
       ecoef = 1.0;
     } else {
-      CHK(op_lap(c, w.m0, w.l0, st));
+      if (!lap0) CHK(op_lap(c, w.m0, w.l0, st));
       CHK(op_lap(c, w.x, w.l1, st));
     }
     double d[5], len;

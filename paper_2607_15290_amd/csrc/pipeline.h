@@ -130,6 +130,9 @@ struct PipeIO {
   // outputs at red[blockIdx.x].
   const TOut* rhs = nullptr;
   double* red = nullptr;
+  // EPI_RHS: when set, the filtered fields F = (-Delta_N) in (3 planes) are
+  // stored here as well.
+  T* out_f = nullptr;
 };
 
 // Arnoldi inner products taken by an x-inverse pass on its own output (the

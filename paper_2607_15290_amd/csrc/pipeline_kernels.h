@@ -523,6 +523,12 @@ __global__ __launch_bounds__(192) void k_xinv(PipeIO<T, TIn, TOut> io, const cx<
       const T F1[3] = {fz[0].y, fz[1].y, fz[2].y};
       epilogue_compute<T, TIn, TOut, EPI>(raw[b], 1, F1, na, o1);
     }
+    if constexpr (EPI == EPI_RHS) {
+      if (io.out_f && live) {
+#pragma unroll
+        for (int f = 0; f < 3; ++f) store2(io.out_f + f * io.ng + i, fz[f].x, fz[f].y);
+      }
+    }
     constexpr int NOUT = EPI == EPI_STORE3 ? 3 : 4;
     if (io.rhs) {
 #pragma unroll

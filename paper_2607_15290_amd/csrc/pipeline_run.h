@@ -48,7 +48,7 @@ template <typename T, typename TIn, typename TOut, int EPI>
 double xinv_node_bytes(const NodalArgs& na, const PipeIO<T, TIn, TOut>& io) {
   double node_b = 0;
   if (EPI == EPI_STORE3) node_b = 3.0 * sizeof(TOut);
-  else if (EPI == EPI_RHS) node_b = 4.0 * sizeof(TOut) + (na.hfield ? 24.0 : 0.0);
+  else if (EPI == EPI_RHS) node_b = 4.0 * sizeof(TOut) + (na.hfield ? 24.0 : 0.0) + (io.out_f ? 3.0 * sizeof(T) : 0.0);
   else if (EPI == EPI_APPLY) node_b = 1.0 * sizeof(TIn) + 3.0 * sizeof(T) + 4.0 * sizeof(TOut);
   else if (EPI == EPI_APPLY_SYM) node_b = 1.0 * sizeof(TIn) + 4.0 * sizeof(TOut);
   else if (EPI == EPI_JT) node_b = 4.0 * sizeof(TIn) + 7.0 * sizeof(T) + 4.0 * sizeof(TOut);
