@@ -487,6 +487,7 @@ struct SolveResult {
   int iters = 0, cycles = 0, outer = 0, converged = 0;
   double rel_true = 0, rel_prec = 0;
   double bnorm = -1;  // ||b||_2 as computed (or taken from the hints)
+  bool r_valid = false;  // the workspace's r holds b - A x for the returned x
 };
 
 // What a caller that solves repeatedly (the midpoint Picard loop) already
@@ -495,6 +496,8 @@ struct SolveHints {
   double bnorm = -1;       // ||b||_2 of an unchanged b (< 0: unknown)
   bool m_checked = false;  // m is finite with no zero node
   bool m32_ready = false;  // the workspace's float32 m holds float(m)
+  double rnorm = -1;       // >= 0: the workspace's r holds b - A x0 for the
+                           // initial guess x0, with this 2-norm
 };
 
 // Left-preconditioned restarted GMRES (FP64) with true-residual acceptance.
@@ -525,7 +528,9 @@ llg_status gmres_left(const Ctx& c, const ResidOp& RA, const Op& M, const Op& MA
   const double target = o.rtol * bnorm;
   double rn[2];
   double rho;
-  if (o.use_x0) {
+  if (o.use_x0 && hints.rnorm >= 0) {
+    rho = hints.rnorm;
+  } else if (o.use_x0) {
     CHK(RA(x, b, w.r));
     CHK_STATUS(fetch(c, c.scal, 1, st, rn));
     rho = std::sqrt(rn[0]);
@@ -534,6 +539,7 @@ llg_status gmres_left(const Ctx& c, const ResidOp& RA, const Op& M, const Op& MA
     CHK(hipMemcpyAsync(w.r, b, sizeof(double) * n4, hipMemcpyDeviceToDevice, st));
     rho = bnorm;
   }
+  res.r_valid = true;  // every later x update recomputes r
   double beta0 = -1.0;
   Hess hs(R);
   std::vector<double> col(R + 2);
@@ -634,7 +640,9 @@ llg_status gmres_ir(const Ctx& c, const llg_params* p, const double* m, const do
   const ResidOp RA = resid_op(c, EPI_MATVEC, sym_for(c, p->alpha, hcoef(p), false), na, m, st);
   double rn[2];
   double rho;
-  if (o.use_x0) {
+  if (o.use_x0 && hints.rnorm >= 0) {
+    rho = hints.rnorm;
+  } else if (o.use_x0) {
     CHK(RA(x, b, w.r));
     CHK_STATUS(fetch(c, c.scal, 1, st, rn));
     rho = std::sqrt(rn[0]);
@@ -643,6 +651,7 @@ llg_status gmres_ir(const Ctx& c, const llg_params* p, const double* m, const do
     CHK(hipMemcpyAsync(w.r, b, sizeof(double) * n4, hipMemcpyDeviceToDevice, st));
     rho = bnorm;
   }
+  res.r_valid = true;  // every later x update recomputes r
   Hess hs(R);
   std::vector<double> col(R + 2);
   while (true) {
@@ -1139,6 +1148,7 @@ llg_status llg_step_midpoint(llg_ctx* ctx, const llg_params* prm, double* m, dou
     if (low) {
       CHK(op_field(c, fa_low, EPI_ADDF, na2, w.mh, w.b, st, nullptr, w.l0));
       hints.bnorm = -1;
+      hints.rnorm = -1;
     }
     SolveResult r;
     lin = solve(c, &p2, w.mh, w.b, w.x, o, w, r, st, hints);
@@ -1148,12 +1158,17 @@ llg_status llg_step_midpoint(llg_ctx* ctx, const llg_params* prm, double* m, dou
     if (lin == LLG_ENOCONV) lconv = false;
     if (!low) hints.bnorm = r.bnorm;
     // ||v^p - v^{p-1}||^2, ||v^p||^2, ||m_hat^{p+1}||^2, zero nodes of m_hat^{p+1};
-    // vold <- v^p, mh <- m_hat^{p+1} (and its float32 copy)
-    double dn[4];
-    CHK(picard_update(c, w.m0, w.x, w.vold, w.mh, 0.5 * k, c.scal, st, mh32));
-    CHK_STATUS(fetch(c, c.scal, 4, st, dn));
+    // vold <- v^p, mh <- m_hat^{p+1} (and its float32 copy).  Without a
+    // lower-order field b is fixed, and only the nodal blocks of A change with
+    // m_hat, so the residual of the solution for the next system is the
+    // previous residual minus a nodal correction (updated in the same pass).
+    const bool upd_r = !low && r.r_valid;
+    double dn[5];
+    CHK(picard_update(c, w.m0, w.x, w.vold, w.mh, 0.5 * k, c.scal, st, mh32, upd_r ? w.r : nullptr));
+    CHK_STATUS(fetch(c, c.scal, 5, st, dn));
     hints.m_checked = true;
     hints.m32_ready = mh32 != nullptr;
+    hints.rnorm = upd_r ? std::sqrt(dn[4]) : -1;
     const double dd = std::sqrt(dn[0]);
     const double num = opts->picard_norm == 0 ? 0.5 * k * dd : dd;
     const double ref = std::sqrt(opts->picard_norm == 0 ? dn[2] : dn[1]);

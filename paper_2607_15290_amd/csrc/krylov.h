@@ -76,10 +76,13 @@ hipError_t m_check(const Ctx& c, const double* m, double* out, hipStream_t st);
 hipError_t euler_update(const Ctx& c, double* m, const double* v, double k, double* out, hipStream_t st);
 // out = m + a v  (3 planes)
 hipError_t nodal_axpy3(const Ctx& c, const double* m, double a, const double* v, double* out, hipStream_t st);
-// out = {||v - vold||^2, ||v||^2, ||m0 + a v||^2, number of nodes with |m0 + a v|^2 <= 1e-300};
-// then vold <- v, mh <- m0 + a v (3 planes) and, when mh32 is set, mh32 <- float(mh)
+// v = the velocity planes of the saddle unknown x = (v, lam) (4 planes).
+// out = {||v - vold||^2, ||v||^2, ||m0 + a v||^2, number of nodes with |m0 + a v|^2 <= 1e-300,
+// ||r_new||^2}; then vold <- v, mh <- m0 + a v (3 planes), mh32 <- float(mh) when set, and
+// when r is set (4 planes, r = b - A(mh) x on entry) r <- r - (dm x v + dm lam, -dm . v),
+// dm = a (v - vold): the residual of x for the system at the new mh.
 hipError_t picard_update(const Ctx& c, const double* m0, const double* v, double* vold, double* mh, double a,
-                         double* out, hipStream_t st, float* mh32 = nullptr);
+                         double* out, hipStream_t st, float* mh32 = nullptr, double* r = nullptr);
 // max_i | |m_i| - 1 |
 hipError_t len_err(const Ctx& c, const double* m, double* out, hipStream_t st);
 // Midpoint diagnostics (see nodal.hip); out[0..6]

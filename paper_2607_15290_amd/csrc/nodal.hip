@@ -93,28 +93,46 @@ __global__ void k_axpy3(const double* __restrict__ m, double a, const double* __
 // partial sums of ||v - vold||^2, ||v||^2 and ||m0 + a v||^2, then vold <- v
 // and mh <- m0 + a v (the next frozen midpoint).
 __global__ __launch_bounds__(kRedThreads) void k_picard_update(const double* __restrict__ m0,
-                                                              const double* __restrict__ v,
+                                                              const double* __restrict__ x,
                                                               double* __restrict__ vold, double* __restrict__ mh,
-                                                              float* __restrict__ mh32, double a, long long ng,
-                                                              double* __restrict__ partial) {
-  double acc[4] = {0, 0, 0, 0};
+                                                              float* __restrict__ mh32, double* __restrict__ r,
+                                                              double a, long long ng, double* __restrict__ partial) {
+  double acc[5] = {0, 0, 0, 0, 0};
   GRID_LOOP(i, ng) {
-    double mm = 0;
+    double mm = 0, dm[3], vv[3];
 #pragma unroll
     for (int f = 0; f < 3; ++f) {
       const long long j = f * ng + i;
-      const double vi = v[j], d = vi - vold[j], mi = m0[j] + a * vi;
+      const double vi = x[j], d = vi - vold[j], mi = m0[j] + a * vi;
       acc[0] += d * d;
       acc[1] += vi * vi;
       mm += mi * mi;
       vold[j] = vi;
       mh[j] = mi;
       if (mh32) mh32[j] = float(mi);
+      dm[f] = a * d;
+      vv[f] = vi;
     }
     acc[2] += mm;
     acc[3] += mm <= 1e-300 ? 1.0 : 0.0;
+    if (r) {
+      // r -= (dm x v + dm lam, -dm . v), dm = m_hat^{p+1} - m_hat^p
+      const double lam = x[3 * ng + i];
+      const double c0 = dm[1] * vv[2] - dm[2] * vv[1];
+      const double c1 = dm[2] * vv[0] - dm[0] * vv[2];
+      const double c2 = dm[0] * vv[1] - dm[1] * vv[0];
+      const double r0 = r[i] - (c0 + dm[0] * lam);
+      const double r1 = r[ng + i] - (c1 + dm[1] * lam);
+      const double r2 = r[2 * ng + i] - (c2 + dm[2] * lam);
+      const double r3 = r[3 * ng + i] + (dm[0] * vv[0] + dm[1] * vv[1] + dm[2] * vv[2]);
+      r[i] = r0;
+      r[ng + i] = r1;
+      r[2 * ng + i] = r2;
+      r[3 * ng + i] = r3;
+      acc[4] += r0 * r0 + r1 * r1 + r2 * r2 + r3 * r3;
+    }
   }
-  bstore<4, 0>(acc, partial);
+  bstore<5, 0>(acc, partial);
 }
 
 __global__ __launch_bounds__(kRedThreads) void k_len_err(const double* __restrict__ m, long long ng,
@@ -307,13 +325,13 @@ hipError_t midpoint_diag(const Ctx& c, const NodalArgs& na, double alpha, double
 }
 
 hipError_t picard_update(const Ctx& c, const double* m0, const double* v, double* vold, double* mh, double a,
-                         double* out, hipStream_t st, float* mh32) {
+                         double* out, hipStream_t st, float* mh32, double* r) {
   hipError_t e_ = hipSuccess;
   {
   ProfScope ps(c.prof, st, KK_NODAL, 0.0);
-  hipLaunchKernelGGL(k_picard_update, dim3(nodal_blocks(c.ng)), dim3(kRedThreads), 0, st, m0, v, vold, mh, mh32, a,
+  hipLaunchKernelGGL(k_picard_update, dim3(nodal_blocks(c.ng)), dim3(kRedThreads), 0, st, m0, v, vold, mh, mh32, r, a,
                      c.ng, c.partial);
-  e_ = reduce_partials(c, nodal_blocks(c.ng), 4, out, false, st);
+  e_ = reduce_partials(c, nodal_blocks(c.ng), 5, out, false, st);
   }
   return e_;
 }
