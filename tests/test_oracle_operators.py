@@ -89,3 +89,25 @@ def test_fused_preconditioned_operator_identity(shape, kw):
     fused = operators.m2_solve(m, prm, x + operators.m1_solve(g, prm, u))
     plain = operators.precond_op(g, prm, m, x)
     assert np.linalg.norm(fused - plain) <= 1e-13 * np.linalg.norm(plain)
+
+
+@pytest.mark.parametrize("shape,kw", CASES)
+def test_residual_under_a_nodal_block_change(shape, kw):
+    """A(m) depends on m only through its nodal blocks (Sec. 2.4, eq. "saddle
+    point system"), so for fixed b and x the residual at a new m follows from
+    the old one by a nodal correction: b - A(m + dm) x = (b - A(m) x)
+    - (dm x v + dm r, -dm . v).  The GPU midpoint loop carries its residual
+    from one Picard system to the next this way; here both sides come from
+    the dense matrix."""
+    g, prm, m, x = _setup(shape, kw, seed=3, unit=False)
+    dm = 1e-2 * np.random.default_rng(4).standard_normal(m.shape)
+    b = np.random.default_rng(5).standard_normal(x.shape)
+    A0 = dense.saddle_matrix(g, prm, m)
+    A1 = dense.saddle_matrix(g, prm, m + dm)
+    r0 = b.ravel() - A0 @ x.ravel()
+    r1 = b.ravel() - A1 @ x.ravel()
+    v, lam = x[:3], x[3]
+    corr = np.empty_like(x)
+    corr[:3] = nodal.cross(dm, v) + dm * lam
+    corr[3] = -nodal.dot(dm, v)
+    assert np.max(np.abs(r1 - (r0 - corr.ravel()))) <= 1e-13 * np.max(np.abs(r1))
