@@ -435,10 +435,10 @@ llg_status cycle_dcgs2(const Ctx& c, const ArnoldiOp& op, bool op_dots, const do
       CHK(dcgs_dots(c, u0, U1, n4, j, W, n4, c.dots, st));
     }
     CHK(dcgs_update(c, u0, U1, n4, cf, c.dots, W, U1 + size_t(j) * n4, n4, c.dots2, st));
-    // one round trip: pass-1 dots p and the pass-2 dots of u_{j+1}
-    CHK(hipMemcpyAsync(c.host, c.dots, sizeof(double) * 2 * kMaxDots, hipMemcpyDeviceToHost, st));
+    // one round trip: pass-1 dots p and the pass-2 dots of u_{j+1}, which their
+    // reductions also wrote into the mapped host mirror
     CHK(hipStreamSynchronize(st));
-    std::memcpy(vals.data(), c.host, sizeof(double) * 2 * kMaxDots);
+    std::memcpy(vals.data(), c.hmirror, sizeof(double) * 2 * kMaxDots);
     const double* p = vals.data();
     const double* s = vals.data() + kMaxDots;
     const double d = p[j];
@@ -876,6 +876,11 @@ llg_status llg_ctx_create_cell(llg_ctx** out, int nx, int ny, int nz, double lx,
   c.scal = c.dots + 2 * kMaxDots;
   if (hipMalloc(&c.tri, sizeof(double) * (kDcgsMaxCols * kDcgsMaxCols + kDcgsMaxCols)) != hipSuccess)
     return cleanup(LLG_ENOMEM, "reduction buffer allocation failed");
+  if (hipHostMalloc(reinterpret_cast<void**>(&c.hmirror), sizeof(double) * 2 * kMaxDots,
+                    hipHostMallocMapped | hipHostMallocCoherent) != hipSuccess)
+    return cleanup(LLG_ENOMEM, "pinned host buffer allocation failed");
+  if (hipHostGetDevicePointer(reinterpret_cast<void**>(&c.hmirror_dev), c.hmirror, 0) != hipSuccess)
+    return cleanup(LLG_EHIP, "device address of the pinned host buffer");
   if (hipHostMalloc(reinterpret_cast<void**>(&c.host), sizeof(double) * 4 * kMaxDots, hipHostMallocDefault) !=
       hipSuccess)
     return cleanup(LLG_ENOMEM, "pinned host buffer allocation failed");
@@ -925,6 +930,7 @@ llg_status llg_ctx_destroy(llg_ctx* ctx) {
   if (c.dots) (void)hipFree(c.dots);
   if (c.tri) (void)hipFree(c.tri);
   if (c.host) (void)hipHostFree(c.host);
+  if (c.hmirror) (void)hipHostFree(c.hmirror);
   if (c.prof) profiler_delete(c.prof);
   delete ctx;
   return LLG_OK;

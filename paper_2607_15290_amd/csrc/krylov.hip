@@ -104,7 +104,7 @@ __global__ __launch_bounds__(kRedThreads) void k_reduce_flat(const double* __res
 // out[i] = sum_b partial[i * nb + b]: value-major partials, one block of 1024
 // threads per value, four independent accumulators per thread (fixed order).
 __global__ __launch_bounds__(1024) void k_reduce_vmajor(const double* __restrict__ partial, int nb,
-                                                       double* __restrict__ out) {
+                                                       double* __restrict__ out, double* __restrict__ hout) {
   const double* p = partial + (long long)blockIdx.x * nb;
   double s0 = 0.0, s1 = 0.0, s2 = 0.0, s3 = 0.0;
   int b = threadIdx.x;
@@ -124,6 +124,7 @@ __global__ __launch_bounds__(1024) void k_reduce_vmajor(const double* __restrict
     double t = sm[0];
     for (int w = 1; w < 1024 / 64; ++w) t += sm[w];
     out[blockIdx.x] = t;
+    if (hout) hout[blockIdx.x] = t;
   }
 }
 
@@ -416,7 +417,10 @@ static inline unsigned grid_for(long long n) {
 
 hipError_t reduce_partials_n(const Ctx& c, int nb, int nv, double* out, hipStream_t st) {
   ProfScope ps(c.prof, st, KK_REDUCE, 8.0 * nb * nv);
-  hipLaunchKernelGGL(k_reduce_vmajor, dim3(nv), dim3(1024), 0, st, c.partial, nb, out);
+  // results landing in the Arnoldi slots are mirrored into host memory, so
+  // the host reads them after a stream synchronize without a copy
+  double* hout = (out >= c.dots && out < c.dots + 2 * kMaxDots) ? c.hmirror_dev + (out - c.dots) : nullptr;
+  hipLaunchKernelGGL(k_reduce_vmajor, dim3(nv), dim3(1024), 0, st, c.partial, nb, out, hout);
   return hipGetLastError();
 }
 

@@ -63,6 +63,8 @@ struct Ctx {
   double* dots2 = nullptr;    // second set (CGS2 re-orthogonalization)
   double* scal = nullptr;     // small device scalars
   double* host = nullptr;     // pinned host mirror (4 * kMaxDots doubles)
+  double* hmirror = nullptr;      // pinned, device-mapped host copy of dots and dots2
+  double* hmirror_dev = nullptr;  // its device address
   double* tri = nullptr;      // delayed-CGS2 T^{-1} (kDcgsMaxCols^2, column-major) + kDcgsMaxCols coefficients
 };
 
