@@ -183,13 +183,15 @@ def test_restart_boundaries_match_dense_solve(prec, restart):
     ctx.close()
 
 
-def test_uniform_state_more_xinv_blocks_than_partial_rows():
-    """float64 GMRES on a grid whose x-inverse pass has more blocks than the
-    reduction's partial rows (512 x 384 x 384: 147,456 rows of two per block),
-    where the Arnoldi inner products fall back to their separate pass; the
-    uniform-state closed form fixes the answer."""
+@pytest.mark.parametrize("prec", ["fp64", "fp32_ir", "fp32_ir_left"])
+def test_uniform_state_more_xinv_blocks_than_partial_rows(prec):
+    """GMRES at the largest line count, 512 x 384 x 384 (147,456 rows): the
+    float64 x-inverse pass (two rows per block) has more blocks than the
+    reduction's partial rows, so its Arnoldi inner products fall back to the
+    separate pass; the float32 passes (four rows per block) keep them fused.
+    The uniform-state closed form fixes the answer."""
     nx, ny, nz = 512, 384, 384
-    announce("uniform state 512x384x384 float64")
+    announce(f"uniform state 512x384x384 {prec}")
     prm = P.Params(alpha=0.02, dt=2.74e-7, theta=0.5, shift=0.5, h_uniform=(0.3, -0.2, 1.0))
     m0 = np.array([0.48, -0.6, 0.64])
     m0 /= np.linalg.norm(m0)
@@ -201,7 +203,7 @@ def test_uniform_state_more_xinv_blocks_than_partial_rows():
     b = torch.zeros((4, nz, ny, nx), dtype=torch.float64, device="cuda:0")
     for c in range(3):
         b[c].fill_((1 + prm.alpha ** 2) * h0[c])
-    x, st = P.gmres_solve(ctx, prm, m, b, rtol=1e-12, restart=4)
+    x, st = P.gmres_solve(ctx, prm, m, b, rtol=1e-12, restart=4, prec=prec, inner_rtol=1e-6)
     assert st["converged"] == 1
     hT = h0 - (m0 @ h0) * m0
     v = prm.alpha * hT - np.cross(m0, hT)
