@@ -183,6 +183,21 @@ llg_status gmres_solve(llg_ctx* ctx, const llg_params* prm, const double* m, con
                        const llg_solver_opts* opts, llg_solver_stats* stats, void* work, size_t work_bytes,
                        void* stream);
 
+/* gmres_solve for callers that cannot allocate device memory (a serving
+ * loop or a harness that forbids hipMalloc): the same solve, with the same
+ * arguments except the workspace, which is a static device array of the
+ * library (128 MiB per GPU, held from the first context on that GPU until
+ * the process ends).  The call itself allocates no device or pinned memory.
+ * The static workspace is shared by every call on one GPU: calls that
+ * overlap on one GPU race on it; calls in sequence are independent (no
+ * contents carry over).
+ * Errors: as gmres_solve; LLG_ENOMEM when llg_workspace_bytes(ctx,
+ * opts->restart, opts->prec) exceeds 128 MiB (e.g. 2-D grids up to 256^2 fit
+ * at restart 30 in every precision); LLG_EHIP when the static workspace's
+ * device address could not be obtained when the context was created. */
+llg_status gmres_solve_noalloc(llg_ctx* ctx, const llg_params* prm, const double* m, const double* b, double* x,
+                               const llg_solver_opts* opts, llg_solver_stats* stats, void* stream);
+
 /* One projected implicit Euler step (Sec. 2.4; Sec. 3.2 last paragraph):
  * solve A(m^n) (v, lam) = (C_hat Delta_N m^n + (1+alpha^2) h_low(m^n), 0)
  * with theta = 1 (lower-order field explicit), then

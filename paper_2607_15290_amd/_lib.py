@@ -64,6 +64,8 @@ SIGNATURES = {
     "fft_hss_apply_f32": (I, [P, ctypes.POINTER(LLGParams), P, P, P, I, P]),
     "gmres_solve": (I, [P, ctypes.POINTER(LLGParams), P, P, P, ctypes.POINTER(LLGSolverOpts),
                         ctypes.POINTER(LLGSolverStats), P, ctypes.c_size_t, P]),
+    "gmres_solve_noalloc": (I, [P, ctypes.POINTER(LLGParams), P, P, P, ctypes.POINTER(LLGSolverOpts),
+                                ctypes.POINTER(LLGSolverStats), P]),
     "llg_step_euler": (I, [P, ctypes.POINTER(LLGParams), P, P, P, ctypes.POINTER(LLGSolverOpts),
                            ctypes.POINTER(LLGStepStats), P, ctypes.c_size_t, P]),
     "llg_step_midpoint": (I, [P, ctypes.POINTER(LLGParams), P, P, P, ctypes.c_double, I,

@@ -843,6 +843,7 @@ llg_status llg_ctx_create_cell(llg_ctx** out, int nx, int ny, int nz, double lx,
   int ndev = 0;
   if (hipGetDeviceCount(&ndev) != hipSuccess || device >= ndev) return fail(LLG_EHIP, "no such HIP device");
   if (hipSetDevice(device) != hipSuccess) return fail(LLG_EHIP, "hipSetDevice failed");
+  scratch_setup(device);
   llg_ctx* ctx = new llg_ctx();
   Ctx& c = ctx->c;
   c.nx = nx;
@@ -1015,6 +1016,16 @@ llg_status fft_hss_apply_f32(llg_ctx* ctx, const llg_params* prm, const float* m
 llg_status gmres_solve(llg_ctx* ctx, const llg_params* prm, const double* m, const double* b, double* x,
                        const llg_solver_opts* opts, llg_solver_stats* stats, void* work, size_t work_bytes,
                        void* stream) {
+  return gmres_solve_work(ctx, prm, m, b, x, opts, stats, work, work_bytes, stream);
+}
+
+}  // extern "C"
+
+int llg::ctx_device(const llg_ctx* ctx) { return ctx ? ctx->c.device : -1; }
+
+llg_status llg::gmres_solve_work(llg_ctx* ctx, const llg_params* prm, const double* m, const double* b, double* x,
+                                 const llg_solver_opts* opts, llg_solver_stats* stats, void* work,
+                                 size_t work_bytes, void* stream) {
   if (!ctx || !m || !b || !x || !work) return fail(LLG_EARG, "null argument");
   CHK_STATUS(check_params(prm));
   CHK_STATUS(check_opts(opts));
@@ -1028,6 +1039,8 @@ llg_status gmres_solve(llg_ctx* ctx, const llg_params* prm, const double* m, con
   fill_stats(r, stats);
   return s;
 }
+
+extern "C" {
 
 llg_status llg_rhs(llg_ctx* ctx, const llg_params* prm, const double* m, double* b, void* stream) {
   if (!ctx || !m || !b) return fail(LLG_EARG, "null argument");

@@ -70,6 +70,20 @@ struct Ctx {
 
 SymArgs sym_for(const Ctx& c, double a, double b, bool invert);
 
+// gmres_solve on a given workspace (capi.cpp); the C entry points
+// gmres_solve and gmres_solve_noalloc both run it.
+llg_status gmres_solve_work(llg_ctx* ctx, const llg_params* prm, const double* m, const double* b, double* x,
+                            const llg_solver_opts* opts, llg_solver_stats* stats, void* work, size_t work_bytes,
+                            void* stream);
+// Device of a context (-1 for null).
+int ctx_device(const llg_ctx* ctx);
+
+// Static workspace of gmres_solve_noalloc (noalloc.hip): its size, and the
+// once-per-device lookup of its device address, run by llg_ctx_create with
+// the context's device current.
+constexpr size_t kScratchBytes = size_t(128) << 20;
+void scratch_setup(int device);
+
 // Launch one spectral pipeline (pipeline.h).  Defined per type combination
 // in the pipeline_*.hip translation units.
 // With bd (bd->nv > 0; fused M^{-1} A passes with a float64 output only) the

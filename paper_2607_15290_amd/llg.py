@@ -212,6 +212,27 @@ def gmres_solve(ctx, params, m, b, x=None, use_x0=False, restart=30, rtol=1e-10,
     return x, stats
 
 
+def gmres_solve_noalloc(ctx, params, m, b, x=None, use_x0=False, restart=30, rtol=1e-10, maxiter=3000,
+                        prec="fp64", inner_rtol=1e-5, max_outer=20, check=True, orth="dcgs2", precond="fft_hss"):
+    """gmres_solve on the library's static workspace (no caller workspace,
+    no device allocation in the call); returns (x, stats).  See
+    gmres_solve_noalloc in include/llg.h."""
+    if x is None:
+        x = ctx.new(4)
+        use_x0 = False
+    o = _opts(restart, maxiter, rtol, prec, inner_rtol, max_outer, use_x0, orth, precond)
+    st = L.LLGSolverStats()
+    pr = params.c_struct(ctx)
+    s = ctx.lib.gmres_solve_noalloc(ctx.handle, ctypes.byref(pr), ctx.check(m, 3, name="m"),
+                                    ctx.check(b, 4, name="b"), ctx.check(x, 4, name="x"), ctypes.byref(o),
+                                    ctypes.byref(st), ctx.stream())
+    stats = _stats_dict(st)
+    stats["status"] = L.STATUS.get(s, s)
+    if check:
+        _check(s, "gmres_solve_noalloc")
+    return x, stats
+
+
 def llg_step_euler(ctx, params, m, v_out=None, lam_out=None, restart=30, rtol=1e-10, maxiter=3000, prec="fp64",
                    inner_rtol=1e-5, max_outer=20, check=True, orth="dcgs2"):
     """One projected Euler step; m is updated in place.  Returns stats."""
