@@ -9,7 +9,7 @@ imports the product package: the two share no kernels, helpers, tables or
 constant generators.  Seeded inputs come from ``llg_workloads`` (which holds
 no arithmetic of the method) or from the caller.
 
-Everything is NumPy float64.  Arrays follow one layout throughout: a grid
+Everything is NumPy / SciPy float64.  Arrays follow one layout throughout: a grid
 function is an array of shape (nz, ny, nx) (nz = 1 in two dimensions), a
 vector field has shape (3, nz, ny, nx), and a saddle unknown x = (v, r) has
 shape (4, nz, ny, nx) with planes v1, v2, v3, r.  Flattened in C order this
@@ -18,7 +18,7 @@ is the node index x + nx*(y + ny*z).
 Two tiers:
   * ``dense``  -- naive DFT matrices and the assembled saddle matrix, for
     grids of at most a few hundred nodes (checks the FFT tier);
-  * everything else -- FFT-based (numpy.fft) matrix-free operators, GMRES,
+  * everything else -- FFT-based (scipy.fft) matrix-free operators, GMRES,
     the time steppers, energy diagnostics and the midpoint adjoint.
 
 Parity pins for every function live in tests/test_oracle_*.py.

@@ -24,10 +24,8 @@ Sec. 3.3 (Proposition "Nodal constraint and discrete energy law").
 
 import numpy as np
 
-from . import nodal
+from . import fourier, nodal
 from .grid import wavenumbers
-
-_AXES = (-3, -2, -1)
 
 
 def derivative_wavevector(g):
@@ -47,7 +45,7 @@ def derivative_wavevector(g):
 
 def demag_field(g, m):
     """Periodic demagnetizing field of m (3, nz, ny, nx), unit coefficient."""
-    mh = np.fft.fftn(m, axes=_AXES)
+    mh = fourier.fftn(m)
     xi = derivative_wavevector(g)
     s = g.s
     safe = np.where(s > 0, s, 1.0)
@@ -55,7 +53,7 @@ def demag_field(g, m):
     proj = np.where(s > 0, proj, 0.0)
     out = np.empty(m.shape)
     for c in range(3):
-        out[c] = -np.fft.ifftn(xi[c] * proj, axes=_AXES).real
+        out[c] = -fourier.ifftn(xi[c] * proj).real
     return out
 
 

@@ -4,20 +4,33 @@ Test infrastructure: part of the float64 CPU oracle (see the package docstring).
 
 -Delta_N u = iFFT(|xi|^2 FFT(u)) over the spatial axes, and the shifted
 exchange block (a + b(-Delta_N)) and its inverse are the same Fourier-diagonal
-multiplications.  numpy.fft serves as the library DFT; the dense tier checks it
-against an O(N_g^2) DFT.
+multiplications.  scipy.fft, the FFT library of the paper's own runs
+(Sec. 4.1), serves as the library DFT; the dense tier checks it against an
+O(N_g^2) DFT.  WORKERS sets its thread count (1 unless a caller that times
+the oracle on several host cores raises it).
 """
 
-import numpy as np
+import scipy.fft
 
 _AXES = (-3, -2, -1)
+
+WORKERS = 1
+
+
+def fftn(u):
+    """DFT over the three spatial axes (complex result)."""
+    return scipy.fft.fftn(u, axes=_AXES, workers=WORKERS)
+
+
+def ifftn(u):
+    """Inverse DFT over the three spatial axes (normalized by 1/N_g)."""
+    return scipy.fft.ifftn(u, axes=_AXES, workers=WORKERS)
 
 
 def fourier_multiply(u, mult):
     """Apply the real, even Fourier multiplier ``mult`` (shape (nz,ny,nx)) to
     each grid function in ``u`` (shape (..., nz, ny, nx))."""
-    uh = np.fft.fftn(u, axes=_AXES)
-    return np.fft.ifftn(uh * mult, axes=_AXES).real
+    return ifftn(fftn(u) * mult).real
 
 
 def neg_laplacian(g, u):
