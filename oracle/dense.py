@@ -75,6 +75,46 @@ def low_linear_matrix(g, prm):
     return L
 
 
+def derivative_matrix(n, length):
+    """First-derivative matrix of the trigonometric interpolant on an even
+    n-point periodic axis of length L, sampled at the nodes: the textbook
+    closed form D[i, j] = (pi / L) (-1)^(i-j) cot(pi (i-j) / n), D[i, i] = 0
+    (Trefethen, Spectral Methods in MATLAB, ch. 3), written out with no DFT.
+    Differentiating the interpolant of the Nyquist mode cos(pi x / h) gives
+    -(pi/h) sin(pi x / h), zero at every node, so D maps that mode to 0."""
+    if n % 2:
+        raise ValueError("derivative_matrix: even n only")
+    i = np.arange(n)
+    d = i[:, None] - i[None, :]
+    with np.errstate(divide="ignore", invalid="ignore"):
+        D = (np.pi / length) * np.where(d % 2 == 0, 1.0, -1.0) / np.tan(np.pi * d / n)
+    D[d == 0] = 0.0
+    return D
+
+
+def demag_matrix_interpolant(g):
+    """Dense periodic demagnetizing operator built from the interpolant
+    derivatives: h = G L^+ Div m, with G / Div the gradient / divergence of
+    the trigonometric interpolant (derivative_matrix along each axis), L =
+    -Delta_N from the naive DFT and L^+ its pseudo-inverse (zero-mean
+    potential).  Returns the 3 N_g x 3 N_g matrix in component-major order."""
+    n = g.ng
+    eye = lambda k: np.eye(k)
+    axes = []
+    if g.nx > 1:
+        axes.append(np.kron(eye(g.nz), np.kron(eye(g.ny), derivative_matrix(g.nx, g.lengths[2]))))
+    if g.ny > 1:
+        axes.append(np.kron(eye(g.nz), np.kron(derivative_matrix(g.ny, g.lengths[1]), eye(g.nx))))
+    if g.nz > 1:
+        axes.append(np.kron(derivative_matrix(g.nz, g.lengths[0]), np.kron(eye(g.ny), eye(g.nx))))
+    while len(axes) < 3:
+        axes.append(np.zeros((n, n)))
+    Lp = np.linalg.pinv(neg_laplacian_matrix(g), rcond=1e-12, hermitian=True)
+    div = np.hstack(axes)
+    grad = np.vstack(axes)
+    return grad @ Lp @ div
+
+
 def block_indices(g):
     n = g.ng
     return [np.arange(c * n, (c + 1) * n) for c in range(4)]

@@ -1,5 +1,6 @@
 """Pins of the lower-order field (oracle.fields) and of the midpoint stepper
-with it: the demagnetizing field of a single Fourier mode in closed form, the
+with it: the demagnetizing field of a single Fourier mode in closed form, its
+Nyquist reading against the textbook interpolant-derivative matrices, the
 dense DFT-matrix tier, the analytic energy of the paper's 3D initial field,
 the printed results of the 3D energy test (Sec. 4.6), the exact energy law
 with demagnetization and anisotropy, and the adjoint of a step with them."""
@@ -53,6 +54,50 @@ def test_demag_matches_dense_tier_and_is_negative_semidefinite():
     ev = np.linalg.eigvalsh(D)
     # -D is an orthogonal projection (onto gradient fields without Nyquist content)
     assert ev.max() < 1e-13 and ev.min() > -1 - 1e-13
+
+
+def test_derivative_matrix_closed_form():
+    """The interpolant-derivative matrix (written from its cot formula, no DFT)
+    differentiates every resolved mode exactly and is skew."""
+    n, length = 10, 1.7
+    x = np.arange(n) * length / n
+    D = dense.derivative_matrix(n, length)
+    for k in range(1, n // 2):
+        xi = 2 * np.pi * k / length
+        np.testing.assert_allclose(D @ np.sin(xi * x), xi * np.cos(xi * x), atol=1e-12)
+        np.testing.assert_allclose(D @ np.cos(xi * x), -xi * np.sin(xi * x), atol=1e-12)
+    np.testing.assert_allclose(D, -D.T, atol=1e-14)
+    np.testing.assert_allclose(D @ np.ones(n), 0.0, atol=1e-13)
+
+
+@pytest.mark.parametrize("shape,lengths", [((1, 4, 6), (1.0, 0.8, 1.2)), ((4, 4, 4), (1.0, 1.3, 0.8)),
+                                           ((2, 6, 4), (0.5, 1.1, 0.9)), ((6, 4, 8), (2.0, 1.0, 1.5))])
+def test_demag_nyquist_reading_matches_interpolant_derivatives(shape, lengths):
+    """Pin of the Nyquist reading of the demagnetizing field: grad and div are
+    the derivatives of the trigonometric interpolant sampled at the nodes
+    (the textbook cot matrices of dense.derivative_matrix, no DFT), the
+    Poisson solve the pseudo-inverse of the naive-DFT -Delta_N.  On random
+    fields, whose spectra fill every Nyquist plane, oracle.fields.demag_field
+    equals h = G L^+ Div m; keeping the Nyquist entries of xi~ would not."""
+    nz, ny, nx = shape
+    g = Grid(nx, ny, nz, lengths=lengths)
+    m = np.random.default_rng(11).standard_normal((3,) + g.shape)
+    want = (dense.demag_matrix_interpolant(g) @ m.ravel()).reshape(m.shape)
+    np.testing.assert_allclose(fields.demag_field(g, m), want, atol=1e-13)
+
+
+def test_demag_of_the_nyquist_mode_is_zero():
+    """m = (cos(pi x / h), 0, 0): the interpolant's divergence -(pi/h) sin(pi x/h)
+    vanishes at every node, so the discrete potential and field are zero (the
+    reading that kept the Nyquist entry would give h = -m instead)."""
+    for g in (Grid(8, 6, 1, lengths=(1.0, 0.75, 1.0)), Grid(6, 4, 8, lengths=(1.0, 0.5, 0.75))):
+        x, _, _ = _coords(g)
+        hx = g.lengths[2] / g.nx
+        m = np.zeros((3,) + g.shape)
+        m[0] = np.cos(np.pi * x / hx)
+        np.testing.assert_allclose(fields.demag_field(g, m), 0.0, atol=1e-13)
+        D = dense.demag_matrix_interpolant(g)
+        np.testing.assert_allclose(D @ m.ravel(), 0.0, atol=1e-12)
 
 
 def _energy_case(n):
