@@ -149,20 +149,73 @@ def fgmres_cycle(apply_a, apply_m, r, restart, inner_rtol):
     return (Z[:j_done].T @ y).reshape(shape), j_done
 
 
+def left_cycle(apply_a, apply_m, r, restart, inner_rtol):
+    """One left-preconditioned GMRES cycle on M^{-1} A d = M^{-1} r from d = 0:
+    stops when the preconditioned residual estimate |g_{j+1}| <= inner_rtol
+    ||M^{-1} r|| or after ``restart`` steps.  Returns (d, steps)."""
+    shape = r.shape
+    z = apply_m(r).ravel()
+    beta = np.linalg.norm(z)
+    if beta == 0.0:
+        return np.zeros(shape), 0
+    m = restart
+    V = np.zeros((m + 1, z.size))
+    H = np.zeros((m + 1, m))
+    cs = np.zeros(m)
+    sn = np.zeros(m)
+    gvec = np.zeros(m + 1)
+    gvec[0] = beta
+    V[0] = z / beta
+    j_done = 0
+    for j in range(m):
+        w = apply_m(apply_a(V[j].reshape(shape))).ravel()
+        for i in range(j + 1):
+            H[i, j] = np.dot(w, V[i])
+            w = w - H[i, j] * V[i]
+        H[j + 1, j] = np.linalg.norm(w)
+        if H[j + 1, j] > 0.0:
+            V[j + 1] = w / H[j + 1, j]
+        for i in range(j):
+            t = cs[i] * H[i, j] + sn[i] * H[i + 1, j]
+            H[i + 1, j] = -sn[i] * H[i, j] + cs[i] * H[i + 1, j]
+            H[i, j] = t
+        cs[j], sn[j] = _givens(H[j, j], H[j + 1, j])
+        H[j, j] = cs[j] * H[j, j] + sn[j] * H[j + 1, j]
+        H[j + 1, j] = 0.0
+        gvec[j + 1] = -sn[j] * gvec[j]
+        gvec[j] = cs[j] * gvec[j]
+        j_done = j + 1
+        if abs(gvec[j + 1]) <= inner_rtol * beta:
+            break
+    y = np.zeros(j_done)
+    for i in range(j_done - 1, -1, -1):
+        y[i] = (gvec[i] - np.dot(H[i, i + 1:j_done], y[i + 1:])) / H[i, i]
+    return (V[:j_done].T @ y).reshape(shape), j_done
+
+
 def fgmres_ir(apply_a, apply_m, b, x0=None, restart=30, rtol=1e-10, inner_rtol=1e-6,
-              max_outer=20):
-    """Iterative refinement: r = b - A x; A d = r by one FGMRES cycle;
-    x += d; until ||r|| <= rtol ||b||."""
+              max_outer=20, inner="flexible"):
+    """Iterative refinement: r = b - A x; A d = r by one inner Krylov cycle;
+    x += d; until ||r|| <= rtol ||b||.
+
+    inner = "flexible": a right-preconditioned flexible GMRES cycle (the
+    precision form); inner = "left": a left-preconditioned GMRES cycle (the
+    variant whose operator is M^{-1} A).  Reading of the inner tolerance
+    shared with the library: a cycle never asks for more than the outer
+    target needs, so it stops at the relative reduction
+    max(inner_rtol, rtol ||b|| / ||r||)."""
     bnorm = np.linalg.norm(b)
     x = np.zeros_like(b) if x0 is None else np.array(x0, dtype=np.float64)
     info = dict(iters=0, outer_steps=0, converged=False, rel_res_true=0.0)
     if bnorm == 0.0:
         info["converged"] = True
         return np.zeros_like(b), info
+    cycle = fgmres_cycle if inner == "flexible" else left_cycle
     r = b - apply_a(x)
     rho = np.linalg.norm(r)
     while rho > rtol * bnorm and info["outer_steps"] < max_outer:
-        d, steps = fgmres_cycle(apply_a, apply_m, r, restart, inner_rtol)
+        eta = max(inner_rtol, rtol * bnorm / rho)
+        d, steps = cycle(apply_a, apply_m, r, restart, eta)
         x = x + d
         info["iters"] += steps
         info["outer_steps"] += 1

@@ -43,8 +43,13 @@ def rhs(g, prm, m, forcing=None, m_low=None):
     return b
 
 
-def solve_saddle(g, prm, m, b, x0=None, restart=30, rtol=1e-10, maxiter=2000):
-    """GMRES on A(m) x = b, left-preconditioned by the split FFT-HSS M."""
+def solve_saddle(g, prm, m, b, x0=None, restart=30, rtol=1e-10, maxiter=2000, transpose=False):
+    """GMRES on A(m) x = b, left-preconditioned by the split FFT-HSS M; with
+    transpose, GMRES on A(m)^T x = b left-preconditioned by M^T."""
+    if transpose:
+        return gmres(lambda x: operators.matvec_transpose(g, prm, m, x),
+                     lambda x: operators.hss_apply(g, prm, m, x, transpose=True),
+                     b, x0=x0, restart=restart, rtol=rtol, maxiter=maxiter)
     return gmres(lambda x: operators.matvec(g, prm, m, x),
                  lambda x: operators.hss_apply(g, prm, m, x),
                  b, x0=x0, restart=restart, rtol=rtol, maxiter=maxiter)
