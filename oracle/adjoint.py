@@ -23,7 +23,16 @@ dL/dh = (1 + alpha^2) mu_v and
                       - (1 + alpha^2) L_low mu_v].
 
 The transposed solve is preconditioned with the transposed split FFT-HSS
-operator built on m_half.
+operator built on m_half, M^{-T} = (calH + lambda I)^{-1} (calS(m_half) +
+lambda I)^{-T}: on the left (GMRES on M^{-T} J^T), or on the right (GMRES on
+J^T M^{-T}, mu = M^{-T} y).  Without a lower-order field J^T = calH + N with
+N nodal (J^T's velocity block differs from H = alpha I + (k/2) C_hat (-Delta_N)
+only by node-wise terms), so
+
+    J^T M^{-T} = [I + (N - lambda I) (calH + lambda I)^{-1}] (calS + lambda I)^{-T},
+
+one nodal solve, one Fourier solve and one nodal combination: nodal_part
+gives N.
 """
 
 from dataclasses import replace
@@ -32,7 +41,7 @@ import numpy as np
 
 from . import dense as dense_mod
 from . import fields, fourier, nodal, operators
-from .gmres import gmres
+from .gmres import gmres, gmres_right
 
 
 def jacobian_transpose_apply(g, prm, m_n, v, r, mu):
@@ -62,8 +71,22 @@ def jacobian_apply(g, prm, m_n, v, r, du):
     return out
 
 
-def step_adjoint(g, prm, m_n, v, r, gbar, rtol=1e-12, restart=30, dense=False):
+def nodal_part(prm, m_n, v, r, mu):
+    """N mu = J^T mu - calH mu (no lower-order field): node-wise
+    (-m^n x mu_v + (k/2) r mu_v - m^{n+1} mu_r, m_half . mu_v)."""
+    k = prm.dt
+    m_half = m_n + 0.5 * k * v
+    m_next = m_n + k * v
+    mv, mr = mu[:3], mu[3]
+    out = np.empty_like(mu)
+    out[:3] = -nodal.cross(m_n, mv) + 0.5 * k * r * mv - m_next * mr
+    out[3] = nodal.dot(m_half, mv)
+    return out
+
+
+def step_adjoint(g, prm, m_n, v, r, gbar, rtol=1e-12, restart=30, dense=False, side="left"):
     """Back-propagate gbar = dL/dm^{n+1} through one converged midpoint step.
+    side: "left" (GMRES on M^{-T} J^T) or "right" (GMRES on J^T M^{-T}).
 
     Returns (gbar_n, hbar_field, hbar_uniform, mu, info)."""
     prm2 = replace(prm, theta=0.5)
@@ -76,9 +99,10 @@ def step_adjoint(g, prm, m_n, v, r, gbar, rtol=1e-12, restart=30, dense=False):
         info = dict(iters=0, converged=True)
     else:
         m_half = m_n + 0.5 * k * v
-        mu, info = gmres(lambda x: jacobian_transpose_apply(g, prm2, m_n, v, r, x),
-                         lambda x: operators.hss_apply(g, prm2, m_half, x, transpose=True),
-                         rhs, restart=restart, rtol=rtol)
+        solver = gmres if side == "left" else gmres_right
+        mu, info = solver(lambda x: jacobian_transpose_apply(g, prm2, m_n, v, r, x),
+                          lambda x: operators.hss_apply(g, prm2, m_half, x, transpose=True),
+                          rhs, restart=restart, rtol=rtol)
     muv, mur = mu[:3], mu[3]
     hbar_field = (1.0 + prm.alpha ** 2) * muv
     hbar_uniform = hbar_field.reshape(3, -1).sum(axis=1)

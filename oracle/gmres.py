@@ -102,6 +102,74 @@ def gmres(apply_a, apply_m, b, x0=None, restart=30, rtol=1e-10, maxiter=2000):
     return x.reshape(shape), info
 
 
+def gmres_right(apply_a, apply_m, b, x0=None, restart=30, rtol=1e-10, maxiter=2000):
+    """Right-preconditioned restarted GMRES (Saad, Alg. 9.5): A M^{-1} u = r
+    from u = 0 in each cycle, x += M^{-1} V y at the cycle's end.  The cycle's
+    residual estimate |g_{j+1}| is the true residual of the iterate (in exact
+    arithmetic), so a cycle stops when it reaches rtol ||b||; the solve is
+    accepted on the recomputed true residual, as in ``gmres``.
+    Returns (x, info) like ``gmres``."""
+    shape = b.shape
+    bv = b.ravel()
+    bnorm = np.linalg.norm(bv)
+    x = np.zeros_like(bv) if x0 is None else np.array(x0, dtype=np.float64).ravel().copy()
+    info = dict(iters=0, restarts=0, converged=False, rel_res_true=0.0, rel_res_prec=0.0, cycles=[])
+    if bnorm == 0.0:
+        info.update(converged=True)
+        return np.zeros(shape), info
+    target = rtol * bnorm
+    r = bv - apply_a(x.reshape(shape)).ravel() if x0 is not None else bv.copy()
+    rho = np.linalg.norm(r)
+    while True:
+        info["rel_res_true"] = rho / bnorm
+        if rho <= target:
+            info["converged"] = True
+            break
+        if info["iters"] >= maxiter:
+            break
+        if info["cycles"]:
+            info["restarts"] += 1
+        m = restart
+        V = np.zeros((m + 1, bv.size))
+        H = np.zeros((m + 1, m))
+        cs = np.zeros(m)
+        sn = np.zeros(m)
+        gvec = np.zeros(m + 1)
+        gvec[0] = rho
+        V[0] = r / rho
+        j_done = 0
+        for j in range(m):
+            w = apply_a(apply_m(V[j].reshape(shape))).ravel()
+            for i in range(j + 1):  # modified Gram-Schmidt
+                H[i, j] = np.dot(w, V[i])
+                w = w - H[i, j] * V[i]
+            H[j + 1, j] = np.linalg.norm(w)
+            if H[j + 1, j] > 0.0:
+                V[j + 1] = w / H[j + 1, j]
+            for i in range(j):
+                t = cs[i] * H[i, j] + sn[i] * H[i + 1, j]
+                H[i + 1, j] = -sn[i] * H[i, j] + cs[i] * H[i + 1, j]
+                H[i, j] = t
+            cs[j], sn[j] = _givens(H[j, j], H[j + 1, j])
+            H[j, j] = cs[j] * H[j, j] + sn[j] * H[j + 1, j]
+            H[j + 1, j] = 0.0
+            gvec[j + 1] = -sn[j] * gvec[j]
+            gvec[j] = cs[j] * gvec[j]
+            info["iters"] += 1
+            j_done = j + 1
+            if abs(gvec[j + 1]) <= target or info["iters"] >= maxiter:
+                break
+        y = np.zeros(j_done)
+        for i in range(j_done - 1, -1, -1):
+            y[i] = (gvec[i] - np.dot(H[i, i + 1:j_done], y[i + 1:])) / H[i, i]
+        x = x + apply_m((V[:j_done].T @ y).reshape(shape)).ravel()
+        info["rel_res_prec"] = abs(gvec[j_done]) / bnorm
+        info["cycles"].append(j_done)
+        r = bv - apply_a(x.reshape(shape)).ravel()
+        rho = np.linalg.norm(r)
+    return x.reshape(shape), info
+
+
 def fgmres_cycle(apply_a, apply_m, r, restart, inner_rtol):
     """One right-preconditioned flexible GMRES cycle on A d = r from d = 0.
 

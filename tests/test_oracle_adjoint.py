@@ -97,3 +97,47 @@ def test_adjoint_matches_central_differences(dense_solve):
         dm = rng.standard_normal(m0.shape)
         fd = (_loss(_forward(g, prm, m0 + eps * dm, hu, hf, nsteps)[0]) - _loss(_forward(g, prm, m0 - eps * dm, hu, hf, nsteps)[0])) / (2 * eps)
         assert float((gbar * dm).sum()) == pytest.approx(fd, rel=1e-5, abs=1e-9)
+
+
+def test_right_preconditioned_transposed_jacobian_identity():
+    """Without a lower-order field, J^T M^{-T} = [I + (N - lambda I) M1^{-1}] M2^{-T}
+    with M1 = calH + lambda I, M2 = calS(m_half) + lambda I and N = J^T - calH
+    node-wise: checked on the dense assembled matrices, and N against the
+    dense difference."""
+    g = Grid(4, 4, 1, h=0.25)
+    prm = Params(alpha=0.1, dt=0.05, theta=0.5, shift=0.5)
+    rng = np.random.default_rng(4)
+    m_n = _state(g, 2)
+    v = 0.3 * rng.standard_normal((3,) + g.shape)
+    r = rng.standard_normal(g.shape)
+    J = dense.midpoint_jacobian(g, prm, m_n, v, r)
+    m_half = m_n + 0.5 * prm.dt * v
+    M1, M2 = dense.hss_factors(g, prm, m_half)
+    calH = M1 - prm.shift * np.eye(M1.shape[0])
+    Nd = J.T - calH
+    n = g.ng
+    # N is node-wise: no coupling between different nodes (up to the rounding
+    # of the dense Laplacian's symmetry)
+    for i in range(n):
+        for j in range(n):
+            if i != j:
+                assert np.all(np.abs(Nd[np.ix_(np.arange(4) * n + i, np.arange(4) * n + j)]) <= 1e-13)
+    x = rng.standard_normal((4,) + g.shape)
+    np.testing.assert_allclose(adjoint.nodal_part(prm, m_n, v, r, x).ravel(), Nd @ x.ravel(), atol=1e-13)
+    lhs = J.T @ np.linalg.inv((M1 @ M2).T)
+    rhs = (np.eye(4 * n) + (Nd - prm.shift * np.eye(4 * n)) @ np.linalg.inv(M1)) @ np.linalg.inv(M2.T)
+    np.testing.assert_allclose(lhs, rhs, atol=1e-12 * np.abs(lhs).max())
+
+
+def test_right_preconditioned_adjoint_matches_dense():
+    """The adjoint solved with right preconditioning equals the dense one."""
+    g = Grid(8, 8, 1, h=1.0 / 8)
+    prm = Params(alpha=0.1, dt=1e-3, theta=0.5, shift=0.5, h_uniform=(0.0, 0.0, 0.5))
+    m_n = _state(g, 3)
+    m1, v, r, _ = steppers.midpoint_step(g, prm, m_n, rtol=1e-14, picard_tol=1e-13, picard_max=100)
+    gbar = np.random.default_rng(5).standard_normal(m1.shape)
+    want = adjoint.step_adjoint(g, prm, m_n, v, r, gbar, dense=True)
+    got = adjoint.step_adjoint(g, prm, m_n, v, r, gbar, rtol=1e-13, side="right")
+    assert got[4]["converged"]
+    for a, b in zip(got[:4], want[:4]):
+        np.testing.assert_allclose(a, b, atol=1e-9 * np.abs(b).max())
