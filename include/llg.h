@@ -22,8 +22,8 @@
  * is element x + nx (y + ny z), N_g = nx ny nz.
  *   m      magnetization, 3 planes (m1, m2, m3)
  *   x      saddle unknown, 4 planes (v1, v2, v3, lam)
- * Pointers must be 16-byte aligned.  The library never frees or retains a
- * caller buffer.
+ * Pointers must be 16-byte aligned (LLG_EARG otherwise).  The library never
+ * frees or retains a caller buffer.
  *
  * Execution.  Calls run on the caller's HIP stream (stream == NULL means the
  * null stream).  llg_matvec and fft_hss_apply are asynchronous.  gmres_solve
@@ -107,6 +107,8 @@ typedef struct {
                         midpoint, ||m_hat^{p+1} - m_hat^p|| <= tol ||m_hat^{p+1}||
                         (default), 1 = change of the velocity,
                         ||v^p - v^{p-1}|| <= tol ||v^p|| */
+  int transpose;     /* gmres_solve only: 1 solves A^T x = b, left-preconditioned
+                        by M^T (float64; the steppers ignore it) */
 } llg_solver_opts;
 
 typedef struct {
@@ -116,6 +118,9 @@ typedef struct {
   int converged;       /* 1 if the true residual test passed */
   double rel_res_true; /* ||b - A x||_2 / ||b||_2, recomputed in float64 */
   double rel_res_prec; /* last preconditioned residual estimate / ||M^{-1} b|| */
+  int restarts;        /* cycles - 1: restarts of the Krylov iteration */
+  double ms;           /* host wall time of the call in milliseconds (it
+                          synchronizes, so this covers the device work) */
 } llg_solver_stats;
 
 typedef struct {
@@ -164,19 +169,50 @@ llg_status llg_matvec(llg_ctx* ctx, const llg_params* prm, const double* m, cons
 llg_status fft_hss_apply(llg_ctx* ctx, const llg_params* prm, const double* m, const double* p, double* z,
                          int transpose, void* stream);
 
-/* The same two operators computed entirely in float32 (benchmarks and the
- * inner operators of the precision form). */
+/* The same two operators computed entirely in float32 (benchmarks; the
+ * precision form's inner operators are llg_precond_op_f32). */
 llg_status llg_matvec_f32(llg_ctx* ctx, const llg_params* prm, const float* m, const float* x, float* y,
                           int transpose, void* stream);
 llg_status fft_hss_apply_f32(llg_ctx* ctx, const llg_params* prm, const float* m, const float* p, float* z,
                              int transpose, void* stream);
 
+/* The preconditioned operator of left-preconditioned GMRES, y = M^{-1} A x,
+ * in one pipeline: the splitting A = (calH + shift I) + (calS - shift I) of
+ * Sec. 3.1 (eq. (HS)) gives the exact identity
+ *   M^{-1} A x = (calS + shift I)^{-1} [x + (calH + shift I)^{-1} (calS - shift I) x],
+ * one nodal prologue, Algorithm 1 and the closed-form nodal inverse (Sec. 3.2,
+ * eq. "inverse S"); the same values as fft_hss_apply(llg_matvec(x)) up to
+ * rounding.  m: 3 planes; x, y: 4 planes, y must not alias x.
+ * Optional Arnoldi products (the first projection of a Gram-Schmidt step,
+ * formed in the operator's last pass from the values it writes): with
+ * nbasis in [1, 32], basis points to nbasis vectors of 4 planes at stride
+ * ld >= 4 N_g doubles (ld even) and dots (device, nbasis doubles) receives
+ * dots[q] = basis_q . y; nbasis = 0 (basis, dots NULL) skips them.
+ * Asynchronous.  Errors: LLG_EARG. */
+llg_status llg_precond_op(llg_ctx* ctx, const llg_params* prm, const double* m, const double* x, double* y,
+                          const double* basis, int nbasis, long long ld, double* dots, void* stream);
+
+/* The float32 preconditioned operators of the precision form between float64
+ * Krylov vectors (the FFTs and nodal blocks run in float32 on m in float32):
+ *   side 0: y = M^{-1} A x by the fused identity above, one float32 pipeline
+ *           (the left variant LLG_FP32_IR_LEFT); z unused;
+ *   side 1: z = M^{-1} x (float32, stored: the flexible basis vector) and
+ *           y = A z (float64 output), the flexible precision form's inner
+ *           operator: two float32 pipelines joined in one x pass.
+ * x, y: 4 float64 planes; z: 4 float32 planes (side 1).  Arnoldi products as
+ * llg_precond_op.  Asynchronous.  Errors: LLG_EARG. */
+llg_status llg_precond_op_f32(llg_ctx* ctx, const llg_params* prm, const float* m, const double* x, double* y,
+                              float* z, int side, const double* basis, int nbasis, long long ld, double* dots,
+                              void* stream);
+
 /* Solve A(m) x = b (Sec. 3.2: GMRES left-preconditioned by the split
  * FFT-HSS operator; acceptance on the true relative residual).
  * b, x: 4 planes; x is the initial guess when opts->use_x0 = 1 and receives
- * the solution (the last iterate on LLG_ENOCONV).  work: device workspace of
- * at least llg_workspace_bytes(ctx, opts->restart, opts->prec) bytes.
- * stats may be NULL.  Synchronizes the stream.
+ * the solution (the last iterate on LLG_ENOCONV).  With opts->transpose = 1
+ * (float64 only) solves A(m)^T x = b with GMRES left-preconditioned by M^T
+ * (operator M^{-T} A^T, two pipelines per iteration).  work: device
+ * workspace of at least llg_workspace_bytes(ctx, opts->restart, opts->prec)
+ * bytes.  stats may be NULL.  Synchronizes the stream.
  * Errors: LLG_EARG, LLG_EZERO_M, LLG_ENOMEM (work too small), LLG_ENOCONV,
  * LLG_ENAN, LLG_EHIP. */
 llg_status gmres_solve(llg_ctx* ctx, const llg_params* prm, const double* m, const double* b, double* x,
@@ -233,7 +269,14 @@ llg_status llg_step_midpoint(llg_ctx* ctx, const llg_params* prm, double* m, dou
  *   hbar_field   += (1 + alpha^2) mu_v            (3 planes, may be NULL)
  *   hbar_uniform += (1 + alpha^2) sum_i mu_v,i    (3 host doubles, may be NULL)
  * m_n, v, lam: the forward step's input magnetization, velocity and
- * multiplier.  gbar: in dL/dm^{n+1}, out dL/dm^n.  Synchronizes. */
+ * multiplier.  gbar: in dL/dm^{n+1}, out dL/dm^n.
+ * The solve: without a lower-order field (demag = aniso_k = 0) and with
+ * opts->orth = 0, GMRES right-preconditioned by M^{-T} in one pipeline per
+ * iteration, using J^T = calH + N with N node-wise:
+ *   J^T M^{-T} = [I + (N - shift I)(calH + shift I)^{-1}] (calS + shift I)^{-T};
+ * otherwise left-preconditioned GMRES on M^{-T} J^T (two pipelines per
+ * iteration).  Either is accepted on the true residual ||(k gbar, 0) - J^T mu||.
+ * Synchronizes. */
 llg_status llg_step_midpoint_adjoint(llg_ctx* ctx, const llg_params* prm, const double* m_n, const double* v,
                                      const double* lam, double* gbar, double* hbar_field, double* hbar_uniform,
                                      const llg_solver_opts* opts, llg_solver_stats* stats, void* work,
@@ -250,7 +293,8 @@ llg_status llg_rhs(llg_ctx* ctx, const llg_params* prm, const double* m, double*
  *   - demag/2 m_i.h_dem[m]_i + aniso_k (1 - (e.m_i)^2) - m_i.h_i]
  * (exchange, demagnetization, anisotropy, Zeeman; Sec. 2.1 and Sec. 3.3,
  * Proposition on the energy law; divide by |Omega| for the normalized energy
- * of Sec. 4.6).  Result to the host double *energy.  Synchronizes. */
+ * of Sec. 4.6).  Result to the host double *energy.  One pipeline whose last
+ * pass reduces the energy density; allocates nothing.  Synchronizes. */
 llg_status llg_energy(llg_ctx* ctx, const llg_params* prm, const double* m, double* energy, void* stream);
 
 /* Instrumentation: per-kernel timing with HIP events.

@@ -28,12 +28,13 @@ class LLGSolverOpts(ctypes.Structure):
     _fields_ = [("restart", ctypes.c_int), ("maxiter", ctypes.c_int), ("max_outer", ctypes.c_int),
                 ("use_x0", ctypes.c_int), ("rtol", ctypes.c_double), ("inner_rtol", ctypes.c_double),
                 ("prec", ctypes.c_int), ("precond", ctypes.c_int), ("orth", ctypes.c_int),
-                ("picard_norm", ctypes.c_int)]
+                ("picard_norm", ctypes.c_int), ("transpose", ctypes.c_int)]
 
 
 class LLGSolverStats(ctypes.Structure):
     _fields_ = [("iters", ctypes.c_int), ("cycles", ctypes.c_int), ("outer_steps", ctypes.c_int),
-                ("converged", ctypes.c_int), ("rel_res_true", ctypes.c_double), ("rel_res_prec", ctypes.c_double)]
+                ("converged", ctypes.c_int), ("rel_res_true", ctypes.c_double), ("rel_res_prec", ctypes.c_double),
+                ("restarts", ctypes.c_int), ("ms", ctypes.c_double)]
 
 
 class LLGStepStats(ctypes.Structure):
@@ -62,6 +63,8 @@ SIGNATURES = {
     "fft_hss_apply": (I, [P, ctypes.POINTER(LLGParams), P, P, P, I, P]),
     "llg_matvec_f32": (I, [P, ctypes.POINTER(LLGParams), P, P, P, I, P]),
     "fft_hss_apply_f32": (I, [P, ctypes.POINTER(LLGParams), P, P, P, I, P]),
+    "llg_precond_op": (I, [P, ctypes.POINTER(LLGParams), P, P, P, P, I, ctypes.c_longlong, P, P]),
+    "llg_precond_op_f32": (I, [P, ctypes.POINTER(LLGParams), P, P, P, P, I, P, I, ctypes.c_longlong, P, P]),
     "gmres_solve": (I, [P, ctypes.POINTER(LLGParams), P, P, P, ctypes.POINTER(LLGSolverOpts),
                         ctypes.POINTER(LLGSolverStats), P, ctypes.c_size_t, P]),
     "gmres_solve_noalloc": (I, [P, ctypes.POINTER(LLGParams), P, P, P, ctypes.POINTER(LLGSolverOpts),

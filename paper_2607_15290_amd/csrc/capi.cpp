@@ -7,9 +7,12 @@
 // j + 2 scalars per Arnoldi step read back from the device.
 #include <hip/hip_runtime.h>
 
+#include <chrono>
 #include <cmath>
+#include <cstdint>
 #include <cstring>
 #include <functional>
+#include <initializer_list>
 #include <string>
 #include <vector>
 
@@ -51,8 +54,19 @@ llg_status fail(llg_status s, const std::string& msg) {
   return s;
 }
 
+// Every device pointer of the ABI must be 16-byte aligned (the kernels issue
+// 16-byte vector loads and stores on the Krylov vectors and plane pairs).
+bool aligned16(const void* p) { return (reinterpret_cast<uintptr_t>(p) & 15u) == 0; }
+
+llg_status check_aligned(std::initializer_list<const void*> ptrs) {
+  for (const void* q : ptrs)
+    if (q && !aligned16(q)) return fail(LLG_EARG, "device pointers must be 16-byte aligned");
+  return LLG_OK;
+}
+
 llg_status check_params(const llg_params* p) {
   if (!p) return fail(LLG_EARG, "params is null");
+  if (p->h_field && !aligned16(p->h_field)) return fail(LLG_EARG, "h_field must be 16-byte aligned");
   if (!is_fin(p->alpha) || p->alpha <= 0) return fail(LLG_EARG, "alpha must be finite and > 0");
   if (!is_fin(p->shift) || p->shift <= 0) return fail(LLG_EARG, "shift (HSS lambda) must be finite and > 0");
   if (!is_fin(p->dt) || p->dt < 0) return fail(LLG_EARG, "dt must be finite and >= 0");
@@ -82,6 +96,7 @@ llg_status check_opts(const llg_solver_opts* o) {
   if (o->precond != 0 && o->prec != LLG_FP64) return fail(LLG_EARG, "comparison preconditioners run in float64");
   if (o->orth == 0 && o->restart > 31) return fail(LLG_EARG, "delayed CGS2 supports restart <= 31");
   if (o->picard_norm != 0 && o->picard_norm != 1) return fail(LLG_EARG, "picard_norm must be 0 or 1");
+  if (o->transpose != 0 && o->transpose != 1) return fail(LLG_EARG, "transpose must be 0 or 1");
   if (o->prec != LLG_FP64) {
     if (o->max_outer < 1) return fail(LLG_EARG, "max_outer must be >= 1");
     if (!is_fin(o->inner_rtol) || o->inner_rtol <= 0 || o->inner_rtol >= 1)
@@ -609,6 +624,77 @@ llg_status gmres_left(const Ctx& c, const ResidOp& RA, const Op& M, const Op& MA
   return LLG_OK;
 }
 
+// Right-preconditioned restarted GMRES (FP64, delayed CGS2): GMRES on
+// A M^{-1} u = r from u = 0 in each cycle, x += M^{-1} (U y) at its end.  The
+// cycle's residual estimate is the true residual of the iterate, so a cycle
+// stops at the target itself; the solve is accepted on the recomputed true
+// residual.  AMd: the operator A M^{-1} in one pipeline, which also leaves the
+// delayed-CGS2 pass-1 products in c.dots when given the basis.
+llg_status gmres_right(const Ctx& c, const ResidOp& RA, const Op& M, const OpDots& AMd, const double* b, double* x,
+                       const llg_solver_opts& o, Work& w, SolveResult& res, hipStream_t st) {
+  const long long n4 = 4 * c.ng;
+  const int R = o.restart;
+  double nb[2];
+  CHK(dot_and_norm(c, b, nullptr, n4, c.scal, st));
+  CHK_STATUS(fetch(c, c.scal, 2, st, nb));
+  const double bnorm = std::sqrt(nb[1]);
+  res.bnorm = bnorm;
+  if (!is_fin(bnorm)) return fail(LLG_ENAN, "right-hand side is not finite");
+  if (bnorm == 0.0) {
+    CHK(hipMemsetAsync(x, 0, sizeof(double) * n4, st));
+    CHK(hipStreamSynchronize(st));
+    res.converged = 1;
+    return LLG_OK;
+  }
+  const double target = o.rtol * bnorm;
+  double rn[2];
+  double rho;
+  if (o.use_x0) {
+    CHK(RA(x, b, w.r));
+    CHK_STATUS(fetch(c, c.scal, 1, st, rn));
+    rho = std::sqrt(rn[0]);
+  } else {
+    CHK(hipMemsetAsync(x, 0, sizeof(double) * n4, st));
+    CHK(hipMemcpyAsync(w.r, b, sizeof(double) * n4, hipMemcpyDeviceToDevice, st));
+    rho = bnorm;
+  }
+  res.r_valid = true;
+  // u_0 = r (raw), u_1 .. u_R in columns 0 .. R - 1 of V, operator output in
+  // column R + 1 (also the preconditioned update at the cycle's end)
+  double* W = w.V + size_t(R + 1) * n4;
+  while (true) {
+    if (!is_fin(rho)) return fail(LLG_ENAN, "non-finite residual");
+    res.rel_true = rho / bnorm;
+    if (rho <= target) {
+      res.converged = 1;
+      break;
+    }
+    if (res.iters >= o.maxiter) break;
+    res.cycles++;
+    CycleResult cr;
+    auto op = [&](int, const double* u, double* wout, const BasisDots* bq) { return AMd(u, wout, bq); };
+    CHK_STATUS(cycle_dcgs2(c, op, LLG_FUSE_DOTS != 0, w.r, w.V, W, n4, rho * rho, R, target / rho, o.maxiter,
+                           res.iters, cr, st));
+    res.rel_prec = cr.gres / bnorm;
+    if (cr.k == 0) break;
+    // t = U y = y_0 u_0 + sum_{i >= 1} y_i u_i, then x += M^{-1} t
+    CHK(axpby(c, n4, cr.y.c[0], w.r, 0.0, w.r, w.t, st));
+    if (cr.k > 1) {
+      Coefs rest{};
+      rest.n = cr.k - 1;
+      for (int i = 1; i < cr.k; ++i) rest.c[i - 1] = cr.y.c[i];
+      CHK(lincomb(c, n4, rest, w.V, n4, w.t, st));
+    }
+    CHK(M(w.t, W));
+    CHK(axpby(c, n4, 1.0, x, 1.0, W, x, st));
+    CHK(RA(x, b, w.r));
+    CHK_STATUS(fetch(c, c.scal, 1, st, rn));
+    rho = std::sqrt(rn[0]);
+  }
+  if (!res.converged) return fail(LLG_ENOCONV, "GMRES reached maxiter before the tolerance");
+  return LLG_OK;
+}
+
 // Precision form: FP64 iterative refinement around right-preconditioned
 // flexible GMRES whose preconditioner and matvec run in float32 (LLG_FP32_IR),
 // or around left-preconditioned GMRES on the fused float32 M^{-1} A
@@ -767,6 +853,26 @@ llg_status check_m(const Ctx& c, const double* m, hipStream_t st) {
 llg_status solve(const Ctx& c, const llg_params* p, const double* m, const double* b, double* x,
                  const llg_solver_opts& o, Work& w, SolveResult& res, hipStream_t st, const SolveHints& hints = {}) {
   if (!hints.m_checked) CHK_STATUS(check_m(c, m, st));
+  if (o.transpose) {
+    // A^T x = b with GMRES left-preconditioned by M^T: operator M^{-T} A^T (a
+    // transposed matvec, then the transposed preconditioner; the symmetric
+    // comparison preconditioner is its own transpose)
+    const ResidOp RAT = resid_op(c, EPI_MATVEC_T, sym_for(c, p->alpha, hcoef(p), false), nodal_for(p), m, st);
+    const long long n4 = 4 * c.ng;
+    Op MT = [&](const double* in, double* out) -> hipError_t {
+      if (o.precond == 0) return op_apply(c, p, m, in, out, true, st);
+      if (o.precond == 1)
+        return pipe_d(c, PRO_COPY3, EPI_APPLY_SYM, sym_for(c, p->alpha + p->shift, hcoef(p), true), nodal_for(p),
+                      in, m, out, st);
+      return hipMemcpyAsync(out, in, sizeof(double) * n4, hipMemcpyDeviceToDevice, st);
+    };
+    Op MTAT = [&](const double* in, double* out) -> hipError_t {
+      hipError_t e = op_matvec(c, p, m, in, w.t, true, st);
+      if (e != hipSuccess) return e;
+      return MT(w.t, out);
+    };
+    return gmres_left(c, RAT, MT, MTAT, b, x, o, w, res, st, nullptr, hints);
+  }
   if (o.prec != LLG_FP64) return gmres_ir(c, p, m, b, x, o, w, res, st, hints);
   const ResidOp RA = resid_op(c, EPI_MATVEC, sym_for(c, p->alpha, hcoef(p), false), nodal_for(p), m, st);
   if (o.precond == 1) {  // symmetric part (lambda I + calH)^{-1}
@@ -803,15 +909,29 @@ void fill_stats(const SolveResult& r, llg_solver_stats* s) {
   s->converged = r.converged;
   s->rel_res_true = r.rel_true;
   s->rel_res_prec = r.rel_prec;
+  s->restarts = r.cycles > 0 ? r.cycles - 1 : 0;
+  s->ms = 0.0;
+}
+
+using Clock = std::chrono::steady_clock;
+double ms_since(Clock::time_point t0) {
+  return std::chrono::duration<double, std::milli>(Clock::now() - t0).count();
 }
 
 // g_N(m): with the lower-order field the nodal density is 1/2 m.F - m.h_ext + K,
 // F = -(h_exc + h_dem + h_ani)(m); without it 1/2 cexc m.(-Delta_N m) - m.h_ext.
-llg_status energy_of(const Ctx& c, const llg_params* p, const double* m, double* lm, double* e, hipStream_t st) {
+// One pipeline (the field pipeline with a lower-order field) whose last pass
+// reduces the density: no field is stored.
+llg_status energy_of(const Ctx& c, const llg_params* p, const double* m, double* e, hipStream_t st) {
   const bool low = has_low(p);
-  if (low) CHK(op_negfield(c, p, m, lm, st));
-  else CHK(op_lap(c, m, lm, st));
-  CHK(energy_sum(c, nodal_for(p), low ? 1.0 : p->cexc, m, lm, c.scal, st));
+  NodalArgs na = nodal_for(p);
+  na.chat = low ? 1.0 : p->cexc;
+  PipeIO<double, double, double> io{m, m, nullptr, c.ng, nullptr, nullptr};
+  io.red = c.partial;
+  if (low) CHK(run_field(c, field_for(c, p, 0.0, p->cexc, 1.0), EPI_ENERGY, na, io, st));
+  else CHK((run_pipeline<double, double, double>(c, PRO_COPY3, EPI_ENERGY, sym_for(c, 0.0, 1.0, false), na, io,
+                                                 st)));
+  CHK(reduce_flat(c, xinv_blocks(c), c.scal, st));
   double s;
   CHK_STATUS(fetch(c, c.scal, 1, st, &s));
   const double vol = c.Lx * c.Ly * (c.dim == 3 ? c.Lz : 1.0);
@@ -971,6 +1091,7 @@ llg_status llg_matvec(llg_ctx* ctx, const llg_params* prm, const double* m, cons
                       int transpose, void* stream) {
   if (!ctx || !m || !x || !y) return fail(LLG_EARG, "null argument");
   if (x == y) return fail(LLG_EARG, "llg_matvec: y must not alias x");
+  CHK_STATUS(check_aligned({m, x, y}));
   CHK_STATUS(check_params(prm));
   CHK_STATUS(ensure_device(ctx->c));
   CHK(op_matvec(ctx->c, prm, m, x, y, transpose != 0, as_stream(stream)));
@@ -980,6 +1101,7 @@ llg_status llg_matvec(llg_ctx* ctx, const llg_params* prm, const double* m, cons
 llg_status fft_hss_apply(llg_ctx* ctx, const llg_params* prm, const double* m, const double* p, double* z,
                          int transpose, void* stream) {
   if (!ctx || !m || !p || !z) return fail(LLG_EARG, "null argument");
+  CHK_STATUS(check_aligned({m, p, z}));
   CHK_STATUS(check_params(prm));
   CHK_STATUS(ensure_device(ctx->c));
   CHK(op_apply(ctx->c, prm, m, p, z, transpose != 0, as_stream(stream)));
@@ -990,6 +1112,7 @@ llg_status llg_matvec_f32(llg_ctx* ctx, const llg_params* prm, const float* m, c
                           int transpose, void* stream) {
   if (!ctx || !m || !x || !y) return fail(LLG_EARG, "null argument");
   if (x == y) return fail(LLG_EARG, "llg_matvec_f32: y must not alias x");
+  CHK_STATUS(check_aligned({m, x, y}));
   CHK_STATUS(check_params(prm));
   CHK_STATUS(ensure_device(ctx->c));
   const Ctx& c = ctx->c;
@@ -1003,6 +1126,7 @@ llg_status llg_matvec_f32(llg_ctx* ctx, const llg_params* prm, const float* m, c
 llg_status fft_hss_apply_f32(llg_ctx* ctx, const llg_params* prm, const float* m, const float* p, float* z,
                              int transpose, void* stream) {
   if (!ctx || !m || !p || !z) return fail(LLG_EARG, "null argument");
+  CHK_STATUS(check_aligned({m, p, z}));
   CHK_STATUS(check_params(prm));
   CHK_STATUS(ensure_device(ctx->c));
   const Ctx& c = ctx->c;
@@ -1010,6 +1134,79 @@ llg_status fft_hss_apply_f32(llg_ctx* ctx, const llg_params* prm, const float* m
   CHK((run_pipeline<float, float, float>(c, transpose ? PRO_M2T : PRO_COPY3, transpose ? EPI_APPLY_T : EPI_APPLY,
                                          sym_for(c, prm->alpha + prm->shift, hcoef(prm), true), nodal_for(prm), io,
                                          as_stream(stream))));
+  return LLG_OK;
+}
+
+}  // extern "C"
+
+namespace {
+// Arnoldi-product arguments of llg_precond_op(_f32): none, or nbasis in
+// [1, kBasisDotsMax] vectors at an even stride ld >= 4 N_g, and a device
+// output of nbasis doubles.
+llg_status basis_dots(const Ctx& c, const double* basis, int nbasis, long long ld, double* dots, BasisDots& bd) {
+  bd = BasisDots{};
+  if (nbasis == 0) {
+    if (basis || dots) return fail(LLG_EARG, "basis and dots must be NULL when nbasis = 0");
+    return LLG_OK;
+  }
+  if (nbasis < 0 || nbasis > kBasisDotsMax) return fail(LLG_EARG, "nbasis must be in [0, 32]");
+  if (!basis || !dots) return fail(LLG_EARG, "basis and dots are required when nbasis > 0");
+  if (ld < 4 * c.ng || ld % 2 != 0) return fail(LLG_EARG, "ld must be even and at least 4 N_g");
+  CHK_STATUS(check_aligned({basis, dots}));
+  bd.u0 = basis;
+  bd.U1 = basis + ld;
+  bd.ld = ld;
+  bd.nv = nbasis;
+  return LLG_OK;
+}
+}  // namespace
+
+extern "C" {
+
+llg_status llg_precond_op(llg_ctx* ctx, const llg_params* prm, const double* m, const double* x, double* y,
+                          const double* basis, int nbasis, long long ld, double* dots, void* stream) {
+  if (!ctx || !m || !x || !y) return fail(LLG_EARG, "null argument");
+  if (x == y) return fail(LLG_EARG, "llg_precond_op: y must not alias x");
+  CHK_STATUS(check_aligned({m, x, y}));
+  CHK_STATUS(check_params(prm));
+  const Ctx& c = ctx->c;
+  BasisDots bd;
+  CHK_STATUS(basis_dots(c, basis, nbasis, ld, dots, bd));
+  CHK_STATUS(ensure_device(c));
+  hipStream_t st = as_stream(stream);
+  PipeIO<double, double, double> io{x, m, y, c.ng, nullptr, nullptr};
+  CHK((run_pipeline<double, double, double>(c, PRO_SMINUS, EPI_FUSED, sym_for(c, prm->alpha + prm->shift, hcoef(prm),
+                                                                              true),
+                                            nodal_for(prm), io, st, bd.nv > 0 ? &bd : nullptr, dots)));
+  return LLG_OK;
+}
+
+llg_status llg_precond_op_f32(llg_ctx* ctx, const llg_params* prm, const float* m, const double* x, double* y,
+                              float* z, int side, const double* basis, int nbasis, long long ld, double* dots,
+                              void* stream) {
+  if (!ctx || !m || !x || !y) return fail(LLG_EARG, "null argument");
+  if (side != 0 && side != 1) return fail(LLG_EARG, "side must be 0 (left, fused) or 1 (flexible)");
+  if (side == 1 && !z) return fail(LLG_EARG, "side 1 needs the float32 output z");
+  if (x == y || (side == 1 && (static_cast<const void*>(z) == static_cast<const void*>(x) ||
+                               static_cast<const void*>(z) == static_cast<const void*>(y))))
+    return fail(LLG_EARG, "llg_precond_op_f32: x, y and z must not alias");
+  CHK_STATUS(check_aligned({m, x, y, z}));
+  CHK_STATUS(check_params(prm));
+  const Ctx& c = ctx->c;
+  BasisDots bd;
+  CHK_STATUS(basis_dots(c, basis, nbasis, ld, dots, bd));
+  CHK_STATUS(ensure_device(c));
+  hipStream_t st = as_stream(stream);
+  const SymArgs sym_ap = sym_for(c, prm->alpha + prm->shift, hcoef(prm), true);
+  const NodalArgs na = nodal_for(prm);
+  if (side == 0) {
+    PipeIO<float, double, double> io{x, m, y, c.ng, nullptr, nullptr};
+    CHK((run_pipeline<float, double, double>(c, PRO_SMINUS, EPI_FUSED, sym_ap, na, io, st,
+                                             bd.nv > 0 ? &bd : nullptr, dots)));
+  } else {
+    CHK(run_apply_matvec(c, sym_ap, sym_for(c, prm->alpha, hcoef(prm), false), na, x, m, z, y, st,
+                         bd.nv > 0 ? &bd : nullptr, dots));
+  }
   return LLG_OK;
 }
 
@@ -1026,10 +1223,13 @@ int llg::ctx_device(const llg_ctx* ctx) { return ctx ? ctx->c.device : -1; }
 llg_status llg::gmres_solve_work(llg_ctx* ctx, const llg_params* prm, const double* m, const double* b, double* x,
                                  const llg_solver_opts* opts, llg_solver_stats* stats, void* work,
                                  size_t work_bytes, void* stream) {
+  const auto t0 = Clock::now();
   if (!ctx || !m || !b || !x || !work) return fail(LLG_EARG, "null argument");
+  CHK_STATUS(check_aligned({m, b, x, work}));
   CHK_STATUS(check_params(prm));
   CHK_STATUS(check_opts(opts));
   if (x == b) return fail(LLG_EARG, "gmres_solve: x must not alias b");
+  if (opts->transpose && opts->prec != LLG_FP64) return fail(LLG_EARG, "transposed solves run in float64");
   const Ctx& c = ctx->c;
   Work w = carve(c, opts->restart, opts->prec, work);
   if (work_bytes < w.bytes) return fail(LLG_ENOMEM, "workspace smaller than llg_workspace_bytes()");
@@ -1037,6 +1237,7 @@ llg_status llg::gmres_solve_work(llg_ctx* ctx, const llg_params* prm, const doub
   SolveResult r;
   const llg_status s = solve(c, prm, m, b, x, *opts, w, r, as_stream(stream));
   fill_stats(r, stats);
+  if (stats) stats->ms = ms_since(t0);
   return s;
 }
 
@@ -1044,6 +1245,7 @@ extern "C" {
 
 llg_status llg_rhs(llg_ctx* ctx, const llg_params* prm, const double* m, double* b, void* stream) {
   if (!ctx || !m || !b) return fail(LLG_EARG, "null argument");
+  CHK_STATUS(check_aligned({m, b}));
   CHK_STATUS(check_params(prm));
   CHK_STATUS(ensure_device(ctx->c));
   CHK(op_rhs_low(ctx->c, prm, m, b, as_stream(stream)));
@@ -1054,18 +1256,15 @@ llg_status llg_energy(llg_ctx* ctx, const llg_params* prm, const double* m, doub
   if (!ctx || !m || !energy) return fail(LLG_EARG, "null argument");
   CHK_STATUS(check_params(prm));
   CHK_STATUS(ensure_device(ctx->c));
-  const Ctx& c = ctx->c;
-  double* lm = nullptr;
-  CHK(hipMalloc(&lm, sizeof(double) * 3 * c.ng));
-  const llg_status s = energy_of(c, prm, m, lm, energy, as_stream(stream));
-  (void)hipFree(lm);
-  return s;
+  CHK_STATUS(check_aligned({m}));
+  return energy_of(ctx->c, prm, m, energy, as_stream(stream));
 }
 
 llg_status llg_step_euler(llg_ctx* ctx, const llg_params* prm, double* m, double* v_out, double* lam_out,
                           const llg_solver_opts* opts, llg_step_stats* stats, void* work, size_t work_bytes,
                           void* stream) {
   if (!ctx || !m || !work) return fail(LLG_EARG, "null argument");
+  CHK_STATUS(check_aligned({m, v_out, lam_out, work}));
   CHK_STATUS(check_params(prm));
   CHK_STATUS(check_opts(opts));
   const Ctx& c = ctx->c;
@@ -1077,10 +1276,11 @@ llg_status llg_step_euler(llg_ctx* ctx, const llg_params* prm, double* m, double
   p1.theta = 1.0;
   llg_solver_opts o = *opts;
   o.use_x0 = 0;
+  o.transpose = 0;
   const long long ng = c.ng;
   if (stats) std::memset(stats, 0, sizeof(*stats));
   double e0 = 0;
-  if (stats) CHK_STATUS(energy_of(c, &p1, m, w.l0, &e0, st));
+  if (stats) CHK_STATUS(energy_of(c, &p1, m, &e0, st));
   CHK(op_rhs_low(c, &p1, m, w.b, st));
   SolveResult r;
   const llg_status s = solve(c, &p1, m, w.b, w.x, o, w, r, st);
@@ -1097,7 +1297,7 @@ llg_status llg_step_euler(llg_ctx* ctx, const llg_params* prm, double* m, double
   if (lam_out) CHK(hipMemcpyAsync(lam_out, w.x + 3 * ng, sizeof(double) * ng, hipMemcpyDeviceToDevice, st));
   if (stats) {
     double e1 = 0, vv[2];
-    CHK_STATUS(energy_of(c, &p1, m, w.l0, &e1, st));
+    CHK_STATUS(energy_of(c, &p1, m, &e1, st));
     CHK(dot_and_norm(c, w.x, nullptr, 3 * ng, c.scal, st));
     CHK_STATUS(fetch(c, c.scal, 2, st, vv));
     const double wq = c.Lx * c.Ly * (c.dim == 3 ? c.Lz : 1.0) / double(ng);
@@ -1116,6 +1316,7 @@ llg_status llg_step_midpoint(llg_ctx* ctx, const llg_params* prm, double* m, dou
                              double picard_tol, int picard_max, const llg_solver_opts* opts,
                              llg_step_stats* stats, void* work, size_t work_bytes, void* stream) {
   if (!ctx || !m || !work) return fail(LLG_EARG, "null argument");
+  CHK_STATUS(check_aligned({m, v_half, lam, work}));
   CHK_STATUS(check_params(prm));
   CHK_STATUS(check_opts(opts));
   if (!is_fin(picard_tol) || picard_tol <= 0 || picard_max < 1)
@@ -1130,6 +1331,7 @@ llg_status llg_step_midpoint(llg_ctx* ctx, const llg_params* prm, double* m, dou
   p2.theta = 0.5;
   llg_solver_opts o = *opts;
   o.use_x0 = 1;
+  o.transpose = 0;
   const double k = prm->dt;
   if (stats) std::memset(stats, 0, sizeof(*stats));
   CHK(hipMemcpyAsync(w.m0, m, sizeof(double) * 3 * ng, hipMemcpyDeviceToDevice, st));
@@ -1247,7 +1449,9 @@ llg_status llg_step_midpoint_adjoint(llg_ctx* ctx, const llg_params* prm, const 
                                      const double* lam, double* gbar, double* hbar_field, double* hbar_uniform,
                                      const llg_solver_opts* opts, llg_solver_stats* stats, void* work,
                                      size_t work_bytes, void* stream) {
+  const auto t0 = Clock::now();
   if (!ctx || !m_n || !v || !lam || !gbar || !work) return fail(LLG_EARG, "null argument");
+  CHK_STATUS(check_aligned({m_n, v, lam, gbar, hbar_field, work}));
   CHK_STATUS(check_params(prm));
   CHK_STATUS(check_opts(opts));
   if (opts->prec != LLG_FP64) return fail(LLG_EARG, "the adjoint solve runs in float64 only");
@@ -1284,6 +1488,7 @@ llg_status llg_step_midpoint_adjoint(llg_ctx* ctx, const llg_params* prm, const 
   };
   llg_solver_opts o = *opts;
   o.use_x0 = 0;
+  o.transpose = 0;
   ResidOp RJT = resid_op(c, EPI_JT, sym_h, na, m_n, st, v, lam);
   if (low) {
     RJT = [&c, fa_jt, na, m_n, st, v, lam](const double* x, const double* b, double* r) -> hipError_t {
@@ -1296,8 +1501,21 @@ llg_status llg_step_midpoint_adjoint(llg_ctx* ctx, const llg_params* prm, const 
     };
   }
   SolveResult r;
-  const llg_status s = gmres_left(c, RJT, MT, MTJT, w.b, w.x, o, w, r, st);
+  llg_status s;
+  if (!low && o.orth == 0) {
+    // one pipeline per iteration: J^T M^{-T} = [I + (N - lambda I)(calH + lambda I)^{-1}]
+    // (calS + lambda I)^{-T} with N node-wise, right preconditioning
+    const SymArgs sym_ap = sym_for(c, p2.alpha + p2.shift, hcoef(&p2), true);
+    OpDots JTMT = [&](const double* in, double* out, const BasisDots* bd) -> hipError_t {
+      PipeIO<double, double, double> io{in, w.mh, out, c.ng, v, lam};
+      return run_pipeline<double, double, double>(c, PRO_M2T, EPI_JT_RIGHT, sym_ap, na, io, st, bd, c.dots);
+    };
+    s = gmres_right(c, RJT, MT, JTMT, w.b, w.x, o, w, r, st);
+  } else {
+    s = gmres_left(c, RJT, MT, MTJT, w.b, w.x, o, w, r, st);
+  }
   fill_stats(r, stats);
+  if (stats) stats->ms = ms_since(t0);
   if (s != LLG_OK) return s;
   // gbar update and field gradients: gbar -= v x mu_v + chat F mu_v + r mu_v - v mu_r,
   // F = (-Delta_N) (chat = C_hat) or -(h_exc + h_dem + h_ani) (chat = 1 + alpha^2)

@@ -74,6 +74,7 @@ static hipError_t field_nh(const Ctx& c, const FieldArgs& fa, int epi, const Nod
     case EPI_RHS: launch_xinv<T, T, T, NH, EPI_RHS>(c, na, io, st); break;
     case EPI_ADDF: launch_xinv<T, T, T, NH, EPI_ADDF>(c, na, io, st); break;
     case EPI_JT: launch_xinv<T, T, T, NH, EPI_JT>(c, na, io, st); break;
+    case EPI_ENERGY: launch_xinv<T, T, T, NH, EPI_ENERGY>(c, na, io, st); break;
     default: return hipErrorInvalidValue;
   }
   return hipGetLastError();

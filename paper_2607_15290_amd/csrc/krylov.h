@@ -89,9 +89,6 @@ hipError_t len_err(const Ctx& c, const double* m, double* out, hipStream_t st);
 hipError_t midpoint_diag(const Ctx& c, const NodalArgs& na, double alpha, double cexc, double k, const double* m0,
                          const double* v, const double* r, const double* lm0, const double* lv, double* out,
                          hipStream_t st);
-// Energy sums: out[0] = sum [cexc/2 m.lm - m.h]
-hipError_t energy_sum(const Ctx& c, const NodalArgs& na, double cexc, const double* m, const double* lm, double* out,
-                      hipStream_t st);
 // Adjoint helpers (nodal.hip)
 hipError_t adjoint_finish(const Ctx& c, const NodalArgs& na, const double* v, const double* r, const double* mu,
                           const double* lmu, double* gbar, double* hbar_field, double* out_hsum, hipStream_t st);

@@ -198,18 +198,6 @@ __global__ __launch_bounds__(kRedThreads) void k_midpoint_diag(NodalArgs na, dou
   bstore<5, 0>(acc, partial);
 }
 
-__global__ __launch_bounds__(kRedThreads) void k_energy(NodalArgs na, double cexc, const double* __restrict__ m,
-                                                       const double* __restrict__ lm, long long ng,
-                                                       double* __restrict__ partial) {
-  double acc[1] = {0.0};
-  GRID_LOOP(i, ng) {
-    double h[3];
-    field_at(na, ng, i, h);
-    for (int c = 0; c < 3; ++c) acc[0] += 0.5 * cexc * m[c * ng + i] * lm[c * ng + i] - m[c * ng + i] * h[c];
-  }
-  bstore<1, 0>(acc, partial);
-}
-
 // gbar -= v x mu_v + C_hat L mu_v + r mu_v - v mu_r ; hbar_field += hs mu_v ; sums of hs mu_v
 __global__ __launch_bounds__(kRedThreads) void k_adjoint_finish(NodalArgs na, const double* __restrict__ v,
                                                                const double* __restrict__ r,
@@ -269,10 +257,12 @@ static inline unsigned grid_n(long long n) {
   return (unsigned)(g < 1 ? 1 : g);
 }
 
+// Profiler bytes of the nodal kernels: one read of every plane a kernel reads
+// and one write of every plane it writes (8 bytes per node and plane).
 hipError_t m_check(const Ctx& c, const double* m, double* out, hipStream_t st) {
   hipError_t e_ = hipSuccess;
   {
-  ProfScope ps(c.prof, st, KK_NODAL, 0.0);
+  ProfScope ps(c.prof, st, KK_NODAL, 24.0 * c.ng);
   const int nb = nodal_blocks(c.ng);
   hipLaunchKernelGGL(k_m_check, dim3(nb), dim3(kRedThreads), 0, st, m, c.ng, c.partial);
   hipLaunchKernelGGL((k_reduce_min_max), dim3(1), dim3(kRedThreads), 0, st, c.partial, nb, out);
@@ -284,7 +274,7 @@ hipError_t m_check(const Ctx& c, const double* m, double* out, hipStream_t st) {
 hipError_t euler_update(const Ctx& c, double* m, const double* v, double k, double* out, hipStream_t st) {
   hipError_t e_ = hipSuccess;
   {
-  ProfScope ps(c.prof, st, KK_NODAL, 0.0);
+  ProfScope ps(c.prof, st, KK_NODAL, 72.0 * c.ng);
   hipLaunchKernelGGL(k_euler_update, dim3(nodal_blocks(c.ng)), dim3(kRedThreads), 0, st, m, v, k, c.ng, c.partial);
   e_ = reduce_partials(c, nodal_blocks(c.ng), 1, out, true, st);
   }
@@ -294,7 +284,7 @@ hipError_t euler_update(const Ctx& c, double* m, const double* v, double k, doub
 hipError_t nodal_axpy3(const Ctx& c, const double* m, double a, const double* v, double* out, hipStream_t st) {
   hipError_t e_ = hipSuccess;
   {
-  ProfScope ps(c.prof, st, KK_NODAL, 0.0);
+  ProfScope ps(c.prof, st, KK_NODAL, 72.0 * c.ng);
   hipLaunchKernelGGL(k_axpy3, dim3(grid_n(3 * c.ng)), dim3(256), 0, st, m, a, v, out, 3 * c.ng);
   e_ = hipGetLastError();
   }
@@ -304,7 +294,7 @@ hipError_t nodal_axpy3(const Ctx& c, const double* m, double a, const double* v,
 hipError_t len_err(const Ctx& c, const double* m, double* out, hipStream_t st) {
   hipError_t e_ = hipSuccess;
   {
-  ProfScope ps(c.prof, st, KK_NODAL, 0.0);
+  ProfScope ps(c.prof, st, KK_NODAL, 24.0 * c.ng);
   hipLaunchKernelGGL(k_len_err, dim3(nodal_blocks(c.ng)), dim3(kRedThreads), 0, st, m, c.ng, c.partial);
   e_ = reduce_partials(c, nodal_blocks(c.ng), 1, out, true, st);
   }
@@ -316,7 +306,7 @@ hipError_t midpoint_diag(const Ctx& c, const NodalArgs& na, double alpha, double
                          hipStream_t st) {
   hipError_t e_ = hipSuccess;
   {
-  ProfScope ps(c.prof, st, KK_NODAL, 0.0);
+  ProfScope ps(c.prof, st, KK_NODAL, (104.0 + (na.hfield ? 24.0 : 0.0)) * c.ng);
   hipLaunchKernelGGL(k_midpoint_diag, dim3(nodal_blocks(c.ng)), dim3(kRedThreads), 0, st, na, alpha, cexc, k, m0, v,
                      r, lm0, lv, c.ng, c.partial);
   e_ = reduce_partials(c, nodal_blocks(c.ng), 5, out, false, st);
@@ -328,21 +318,11 @@ hipError_t picard_update(const Ctx& c, const double* m0, const double* v, double
                          double* out, hipStream_t st, float* mh32, double* r) {
   hipError_t e_ = hipSuccess;
   {
-  ProfScope ps(c.prof, st, KK_NODAL, 0.0);
+  // m0, v, vold read; vold, mh written; the float32 copy; r (4 planes) and lam read-modify-write
+  ProfScope ps(c.prof, st, KK_NODAL, (120.0 + (mh32 ? 12.0 : 0.0) + (r ? 72.0 : 0.0)) * c.ng);
   hipLaunchKernelGGL(k_picard_update, dim3(nodal_blocks(c.ng)), dim3(kRedThreads), 0, st, m0, v, vold, mh, mh32, r, a,
                      c.ng, c.partial);
   e_ = reduce_partials(c, nodal_blocks(c.ng), 5, out, false, st);
-  }
-  return e_;
-}
-
-hipError_t energy_sum(const Ctx& c, const NodalArgs& na, double cexc, const double* m, const double* lm, double* out,
-                      hipStream_t st) {
-  hipError_t e_ = hipSuccess;
-  {
-  ProfScope ps(c.prof, st, KK_NODAL, 0.0);
-  hipLaunchKernelGGL(k_energy, dim3(nodal_blocks(c.ng)), dim3(kRedThreads), 0, st, na, cexc, m, lm, c.ng, c.partial);
-  e_ = reduce_partials(c, nodal_blocks(c.ng), 1, out, false, st);
   }
   return e_;
 }
@@ -351,7 +331,8 @@ hipError_t adjoint_finish(const Ctx& c, const NodalArgs& na, const double* v, co
                           const double* lmu, double* gbar, double* hbar_field, double* out_hsum, hipStream_t st) {
   hipError_t e_ = hipSuccess;
   {
-  ProfScope ps(c.prof, st, KK_NODAL, 0.0);
+  // v, r, mu (4 planes), L mu read; gbar (and hbar) read and written
+  ProfScope ps(c.prof, st, KK_NODAL, (136.0 + (hbar_field ? 48.0 : 0.0)) * c.ng);
   hipLaunchKernelGGL(k_adjoint_finish, dim3(nodal_blocks(c.ng)), dim3(kRedThreads), 0, st, na, v, r, mu, lmu, gbar,
                      hbar_field, c.ng, c.partial);
   e_ = reduce_partials(c, nodal_blocks(c.ng), 3, out_hsum, false, st);

@@ -14,6 +14,9 @@
 //                             Algorithm 1
 //   fused       M^{-1} A x  : M2^{-1}[x + M1^{-1}((calS - lambda I) x)], an
 //                             identity because A = M1 + calS - lambda I
+//   adjoint     J^T M^{-T} y: [I + (N - lambda I) M1^{-1}] M2^{-T} y, N = J^T -
+//                             calH node-wise (the midpoint Jacobian, no
+//                             lower-order field); right preconditioning
 //   rhs         C_hat Delta_N m + (1+alpha^2) h (Sec. 2.4, eq. "total system")
 //
 // Grid planes are SoA, node index i = x + nx (y + ny z).  Between passes the
@@ -98,6 +101,9 @@ enum EpiMode : int {
   EPI_APPLY_SYM = 8, // out = (F, p_r / lambda): (lambda I + calH)^{-1} p alone
   EPI_FUSED_SYM = 9, // out = x + (F, (-m.v - lambda r) / lambda): (lambda I + calH)^{-1} A x
   EPI_ADDF = 10,     // out = (aux_v - (1+alpha^2) F, 0): right-hand side with the lower-order field
+  EPI_ENERGY = 11,   // no output: per-block partial sums of chat/2 m.F - m.h (discrete energy density)
+  EPI_JT_RIGHT = 12, // out = J^T M^{-T} y of the midpoint adjoint, right-preconditioned (one pipeline,
+                     // prologue PRO_M2T on m = m_half, F = (calH + lambda I)^{-1} of the prologue)
 };
 
 // Symmetric 3x3 Fourier multiplier of the lower-order field pipeline:
@@ -123,11 +129,12 @@ struct PipeIO {
   const T* m;        // 3 planes (may be null for modes that do not use it)
   TOut* out;         // 4 planes (3 for EPI_STORE3)
   long long ng;
-  const T* aux_v;    // EPI_JT: forward velocity v (3 planes)
-  const T* aux_r;    // EPI_JT: forward multiplier (1 plane)
+  const T* aux_v;    // EPI_JT, EPI_JT_RIGHT: forward velocity v (3 planes)
+  const T* aux_r;    // EPI_JT, EPI_JT_RIGHT: forward multiplier (1 plane)
   // Residual form: when rhs is set, the pipeline writes out = rhs - (operator
   // output) and each x-inverse block stores the partial sum of squares of its
-  // outputs at red[blockIdx.x].
+  // outputs at red[blockIdx.x].  EPI_ENERGY writes no output and stores the
+  // block's partial sum of the energy density at red[blockIdx.x].
   const TOut* rhs = nullptr;
   double* red = nullptr;
   // EPI_RHS: when set, the filtered fields F = (-Delta_N) in (3 planes) are

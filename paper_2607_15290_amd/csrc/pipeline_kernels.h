@@ -178,7 +178,7 @@ __device__ __forceinline__ void prologue_compute(const ProRaw<T, TIn, PRO>& r, c
 // ---------------------------------------------------------------------------
 template <typename T, typename TIn, typename TOut, int EPI>
 struct EpiRaw {
-  static constexpr bool NODAL = !(EPI == EPI_STORE3 || EPI == EPI_RHS || EPI == EPI_ADDF);
+  static constexpr bool NODAL = !(EPI == EPI_STORE3 || EPI == EPI_RHS || EPI == EPI_ADDF || EPI == EPI_ENERGY);
   TIn v[4][2];   // x or p planes (nodal modes)
   T m[3][2];     // magnetization (nodal modes)
   T av[3][2];    // forward velocity (EPI_JT)
@@ -206,7 +206,7 @@ __device__ __forceinline__ void epilogue_load(const PipeIO<T, TIn, TOut>& io, co
 #pragma unroll
       for (int f = 0; f < 3; ++f) r.m[f][0] = r.m[f][1] = T(0);
     }
-    if constexpr (EPI == EPI_JT) {
+    if constexpr (EPI == EPI_JT || EPI == EPI_JT_RIGHT) {
 #pragma unroll
       for (int f = 0; f < 3; ++f) load2(io.aux_v + f * ng + i, r.av[f][0], r.av[f][1]);
       load2(io.aux_r + i, r.ar[0], r.ar[1]);
@@ -214,7 +214,11 @@ __device__ __forceinline__ void epilogue_load(const PipeIO<T, TIn, TOut>& io, co
   } else if constexpr (EPI == EPI_ADDF) {
 #pragma unroll
     for (int f = 0; f < 3; ++f) load2(io.aux_v + f * ng + i, r.av[f][0], r.av[f][1]);
-  } else if constexpr (EPI == EPI_RHS) {
+  } else if constexpr (EPI == EPI_RHS || EPI == EPI_ENERGY) {
+    if constexpr (EPI == EPI_ENERGY) {
+#pragma unroll
+      for (int f = 0; f < 3; ++f) load2(io.m + f * ng + i, r.m[f][0], r.m[f][1]);
+    }
     if (na.hfield) {
 #pragma unroll
       for (int f = 0; f < 3; ++f) load2(na.hfield + f * ng + i, r.hf[f][0], r.hf[f][1]);
@@ -245,6 +249,14 @@ __device__ __forceinline__ void epilogue_compute(const EpiRaw<T, TIn, TOut, EPI>
     o[1] = r.av[1][h] - hs * F[1];
     o[2] = r.av[2][h] - hs * F[2];
     o[3] = T(0);
+  } else if constexpr (EPI == EPI_ENERGY) {
+    // energy density chat/2 m.F - m.h, F = (-Delta_N) m (chat = cexc) or minus
+    // the linear effective field (chat = 1); h = uniform + spatial field
+    const T c = T(na.chat);
+    const V3<T> m{r.m[0][h], r.m[1][h], r.m[2][h]};
+    const V3<T> hf{T(na.hu0) + T(r.hf[0][h]), T(na.hu1) + T(r.hf[1][h]), T(na.hu2) + T(r.hf[2][h])};
+    o[0] = T(0.5) * c * dot3(m, V3<T>{F[0], F[1], F[2]}) - dot3(m, hf);
+    o[1] = o[2] = o[3] = T(0);
   } else if constexpr (EPI == EPI_RHS) {
     const T c = T(na.chat), hs = T(na.hs);
     o[0] = -c * F[0] + hs * (T(na.hu0) + T(r.hf[0][h]));
@@ -290,6 +302,28 @@ __device__ __forceinline__ void epilogue_compute(const EpiRaw<T, TIn, TOut, EPI>
       o[1] = F[1] - c.y + hk * rf * v.y - m1.y * rr;
       o[2] = F[2] - c.z + hk * rf * v.z - m1.z * rr;
       o[3] = dot3(mh, v);
+    } else if constexpr (EPI == EPI_JT_RIGHT) {
+      // m = m_half, (v, rr) = y; u = (S~ + lambda I)^{-T} y (the prologue's
+      // nodal solve, recomputed), w = (F, u_r / lambda) = (calH + lambda I)^{-1} u;
+      // out = u + N w - lambda w with N w = (-m^n x w_v + (k/2) r_f w_v -
+      // m^{n+1} w_r, m_half . w_v), m^n = m_half - (k/2) v_f, m^{n+1} = m_half +
+      // (k/2) v_f; the multiplier row reduces to m_half . w_v.
+      const T hk = T(na.half_k);
+      const V3<T> vf{r.av[0][h], r.av[1][h], r.av[2][h]};
+      const T rf = r.ar[h];
+      V3<T> u;
+      T ur;
+      shift_solve_t(m, v, rr, lam, u, ur);
+      const V3<T> wv{F[0], F[1], F[2]};
+      const T wr = ur / lam;
+      const V3<T> mn{m.x - hk * vf.x, m.y - hk * vf.y, m.z - hk * vf.z};
+      const V3<T> m1{m.x + hk * vf.x, m.y + hk * vf.y, m.z + hk * vf.z};
+      const V3<T> c = cross3(mn, wv);
+      const T s = hk * rf - lam;
+      o[0] = u.x - c.x + s * wv.x - m1.x * wr;
+      o[1] = u.y - c.y + s * wv.y - m1.y * wr;
+      o[2] = u.z - c.z + s * wv.z - m1.z * wr;
+      o[3] = dot3(m, wv);
     } else if constexpr (EPI == EPI_APPLY_SYM) {
       o[0] = F[0];
       o[1] = F[1];
@@ -471,7 +505,8 @@ template <typename T, typename TIn, typename TOut, int NH, int EPI, bool DOTS = 
 __global__ __launch_bounds__(192) void k_xinv(PipeIO<T, TIn, TOut> io, const cx<T>* __restrict__ spec,
                                               SpecGeom g, NodalArgs na, const cx<T>* __restrict__ twx,
                                               BasisDots bd) {
-  static_assert(!DOTS || ((EPI == EPI_MATVEC || EPI == EPI_FUSED) && std::is_same<TOut, double>::value),
+  static_assert(!DOTS || ((EPI == EPI_MATVEC || EPI == EPI_FUSED || EPI == EPI_JT_RIGHT) &&
+                          std::is_same<TOut, double>::value),
                 "dots: float64 Krylov output of a matvec or fused pass");
   using C = XCfg<T, NH>;
   __shared__ cx<T> lds[3 * C::LX * C::SL];
@@ -529,7 +564,10 @@ __global__ __launch_bounds__(192) void k_xinv(PipeIO<T, TIn, TOut> io, const cx<
         for (int f = 0; f < 3; ++f) store2(io.out_f + f * io.ng + i, fz[f].x, fz[f].y);
       }
     }
-    constexpr int NOUT = EPI == EPI_STORE3 ? 3 : 4;
+    constexpr int NOUT = EPI == EPI_STORE3 ? 3 : (EPI == EPI_ENERGY ? 0 : 4);
+    if constexpr (EPI == EPI_ENERGY) {
+      if (live) rsum += double(o0[0]) + double(o1[0]);
+    }
     if (io.rhs) {
 #pragma unroll
       for (int f = 0; f < NOUT; ++f) {
@@ -585,8 +623,8 @@ __global__ __launch_bounds__(192) void k_xinv(PipeIO<T, TIn, TOut> io, const cx<
       bd.partial[(long long)tid * gridDim.x + blockIdx.x] = t;
     }
   }
-  if (io.rhs) {
-    // block partial of the residual norm (fixed order: deterministic)
+  if (io.red) {
+    // block partial of the residual norm or of the energy (fixed order: deterministic)
     __shared__ double rs[C::NT / 64];
 #pragma unroll
     for (int off = 32; off > 0; off >>= 1) rsum += __shfl_xor(rsum, off, 64);

@@ -21,7 +21,8 @@ constexpr bool has_pro(int pro) {
 }
 template <typename T, typename TIn, typename TOut>
 constexpr bool has_epi(int epi) {
-  if constexpr (std::is_same<T, TIn>::value && std::is_same<T, TOut>::value) return true;
+  if constexpr (std::is_same<T, TIn>::value && std::is_same<T, TOut>::value)
+    return (epi != EPI_ENERGY && epi != EPI_JT_RIGHT) || std::is_same<T, double>::value;
   else if constexpr (std::is_same<TIn, double>::value && std::is_same<TOut, double>::value)
     return epi == EPI_APPLY || epi == EPI_FUSED;
   else if constexpr (std::is_same<TIn, double>::value) return epi == EPI_APPLY;
@@ -51,8 +52,9 @@ double xinv_node_bytes(const NodalArgs& na, const PipeIO<T, TIn, TOut>& io) {
   else if (EPI == EPI_RHS) node_b = 4.0 * sizeof(TOut) + (na.hfield ? 24.0 : 0.0) + (io.out_f ? 3.0 * sizeof(T) : 0.0);
   else if (EPI == EPI_APPLY) node_b = 1.0 * sizeof(TIn) + 3.0 * sizeof(T) + 4.0 * sizeof(TOut);
   else if (EPI == EPI_APPLY_SYM) node_b = 1.0 * sizeof(TIn) + 4.0 * sizeof(TOut);
-  else if (EPI == EPI_JT) node_b = 4.0 * sizeof(TIn) + 7.0 * sizeof(T) + 4.0 * sizeof(TOut);
+  else if (EPI == EPI_JT || EPI == EPI_JT_RIGHT) node_b = 4.0 * sizeof(TIn) + 7.0 * sizeof(T) + 4.0 * sizeof(TOut);
   else if (EPI == EPI_ADDF) node_b = 3.0 * sizeof(T) + 4.0 * sizeof(TOut);
+  else if (EPI == EPI_ENERGY) node_b = 3.0 * sizeof(T) + (na.hfield ? 24.0 : 0.0);
   else node_b = 4.0 * sizeof(TIn) + 3.0 * sizeof(T) + 4.0 * sizeof(TOut);
   if (io.rhs) node_b += 4.0 * sizeof(TOut);
   return node_b;
@@ -127,10 +129,14 @@ hipError_t run_nh(const Ctx& c, int pro, int epi, const SymArgs& sym, const Noda
     if ((e = launch_axis<T>(c, 1, 1, sym, spec, st)) != hipSuccess) return e;
   }
   if (bd && bd->nv > 0) {
-    // the Arnoldi inner products ride on the fused M^{-1} A pass only
+    // the Arnoldi inner products ride on the fused preconditioned passes only
     if constexpr (std::is_same<TOut, double>::value && has_epi<T, TIn, TOut>(EPI_FUSED)) {
-      if (epi != EPI_FUSED) return hipErrorInvalidValue;
-      return launch_xinv_dots<T, TIn, TOut, NH, EPI_FUSED>(c, na, io, *bd, dots_out, st);
+      if (epi == EPI_FUSED) return launch_xinv_dots<T, TIn, TOut, NH, EPI_FUSED>(c, na, io, *bd, dots_out, st);
+      if constexpr (has_epi<T, TIn, TOut>(EPI_JT_RIGHT)) {
+        if (epi == EPI_JT_RIGHT)
+          return launch_xinv_dots<T, TIn, TOut, NH, EPI_JT_RIGHT>(c, na, io, *bd, dots_out, st);
+      }
+      return hipErrorInvalidValue;
     } else {
       return hipErrorInvalidValue;
     }
@@ -146,6 +152,8 @@ hipError_t run_nh(const Ctx& c, int pro, int epi, const SymArgs& sym, const Noda
     case EPI_JT: launch_xinv<T, TIn, TOut, NH, EPI_JT>(c, na, io, st); break;
     case EPI_APPLY_SYM: launch_xinv<T, TIn, TOut, NH, EPI_APPLY_SYM>(c, na, io, st); break;
     case EPI_FUSED_SYM: launch_xinv<T, TIn, TOut, NH, EPI_FUSED_SYM>(c, na, io, st); break;
+    case EPI_ENERGY: launch_xinv<T, TIn, TOut, NH, EPI_ENERGY>(c, na, io, st); break;
+    case EPI_JT_RIGHT: launch_xinv<T, TIn, TOut, NH, EPI_JT_RIGHT>(c, na, io, st); break;
     default: return hipErrorInvalidValue;
   }
   return hipGetLastError();

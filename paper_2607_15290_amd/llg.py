@@ -75,8 +75,9 @@ PICARD_NORM = {"midpoint": 0, "velocity": 1, 0: 0, 1: 1}
 
 
 def _opts(restart, maxiter, rtol, prec, inner_rtol, max_outer, use_x0, orth="dcgs2", precond="fft_hss",
-          picard_norm="midpoint"):
+          picard_norm="midpoint", transpose=False):
     o = L.LLGSolverOpts()
+    o.transpose = int(bool(transpose))
     o.orth = ORTH[orth]
     o.precond = PRECOND[precond]
     o.picard_norm = PICARD_NORM[picard_norm]
@@ -88,6 +89,14 @@ def _opts(restart, maxiter, rtol, prec, inner_rtol, max_outer, use_x0, orth="dcg
 
 def _stats_dict(s):
     return {name: getattr(s, name) for name, _ in s._fields_}
+
+
+def aligned_ptr(t, name="tensor"):
+    """Device address of a tensor, which the C ABI requires 16-byte aligned."""
+    ptr = t.data_ptr()
+    if ptr % 16:
+        raise ValueError(f"{name} must start at a 16-byte aligned address")
+    return ptr
 
 
 class Context:
@@ -149,7 +158,7 @@ class Context:
             raise ValueError(f"{name} must be a contiguous {dtype} tensor on {self.device}")
         if t.numel() != planes * self.ng:
             raise ValueError(f"{name} must hold {planes} planes of {self.ng} nodes")
-        return t.data_ptr()
+        return aligned_ptr(t, name)
 
     def new(self, planes, dtype=torch.float64):
         return torch.empty((planes, self.nz, self.ny, self.nx), dtype=dtype, device=self.device)
@@ -192,13 +201,61 @@ def fft_hss_apply_f32(ctx, params, m, p, z=None, transpose=False):
     return z
 
 
+def _basis_args(ctx, basis):
+    """(pointer, count, stride, dots tensor) of optional Arnoldi basis vectors:
+    a contiguous float64 tensor of nb vectors of 4 planes each."""
+    if basis is None:
+        return None, 0, 0, None
+    if basis.dtype != torch.float64 or not basis.is_contiguous() or basis.device != ctx.device:
+        raise ValueError(f"basis must be a contiguous float64 tensor on {ctx.device}")
+    if basis.numel() % (4 * ctx.ng):
+        raise ValueError("basis must hold whole vectors of 4 planes")
+    nb = basis.numel() // (4 * ctx.ng)
+    dots = torch.empty(max(nb, 1), dtype=torch.float64, device=ctx.device)
+    return aligned_ptr(basis, "basis"), nb, 4 * ctx.ng, dots
+
+
+def llg_precond_op(ctx, params, m, x, y=None, basis=None):
+    """y = M^{-1} A x in one pipeline; with basis (nb vectors of 4 planes) also
+    the Arnoldi products basis_q . y.  Returns y, or (y, dots) with a basis.
+    See llg_precond_op in include/llg.h."""
+    y = ctx.new(4) if y is None else y
+    pr = params.c_struct(ctx)
+    bp, nb, ld, dots = _basis_args(ctx, basis)
+    _check(ctx.lib.llg_precond_op(ctx.handle, ctypes.byref(pr), ctx.check(m, 3, name="m"), ctx.check(x, 4, name="x"),
+                                  ctx.check(y, 4, name="y"), bp, nb, ld,
+                                  aligned_ptr(dots, "dots") if dots is not None else None, ctx.stream()),
+           "llg_precond_op")
+    return y if basis is None else (y, dots)
+
+
+def llg_precond_op_f32(ctx, params, m, x, side=0, z=None, y=None, basis=None):
+    """float32 preconditioned operators between float64 vectors: side 0,
+    y = M^{-1} A x (one float32 pipeline); side 1, z = M^{-1} x (float32) and
+    y = A z.  m is float32.  Returns (y, dots) (dots None without a basis).
+    See llg_precond_op_f32 in include/llg.h."""
+    y = ctx.new(4) if y is None else y
+    if side == 1 and z is None:
+        z = ctx.new(4, torch.float32)
+    pr = params.c_struct(ctx)
+    bp, nb, ld, dots = _basis_args(ctx, basis)
+    f = torch.float32
+    _check(ctx.lib.llg_precond_op_f32(ctx.handle, ctypes.byref(pr), ctx.check(m, 3, f, "m"),
+                                      ctx.check(x, 4, name="x"), ctx.check(y, 4, name="y"),
+                                      ctx.check(z, 4, f, "z") if z is not None else None, int(side), bp, nb, ld,
+                                      aligned_ptr(dots, "dots") if dots is not None else None, ctx.stream()),
+           "llg_precond_op_f32")
+    return y, dots
+
+
 def gmres_solve(ctx, params, m, b, x=None, use_x0=False, restart=30, rtol=1e-10, maxiter=3000, prec="fp64",
-                inner_rtol=1e-5, max_outer=20, check=True, orth="dcgs2", precond="fft_hss"):
-    """Solve A(m) x = b; returns (x, stats).  See gmres_solve in include/llg.h."""
+                inner_rtol=1e-5, max_outer=20, check=True, orth="dcgs2", precond="fft_hss", transpose=False):
+    """Solve A(m) x = b (or A(m)^T x = b with transpose); returns (x, stats).
+    See gmres_solve in include/llg.h."""
     if x is None:
         x = ctx.new(4)
         use_x0 = False
-    o = _opts(restart, maxiter, rtol, prec, inner_rtol, max_outer, use_x0, orth, precond)
+    o = _opts(restart, maxiter, rtol, prec, inner_rtol, max_outer, use_x0, orth, precond, transpose=transpose)
     st = L.LLGSolverStats()
     work = ctx.workspace(restart, prec)
     pr = params.c_struct(ctx)

@@ -25,8 +25,21 @@ def unit_field(shape, seed, smooth=None):
     return m / np.sqrt((m * m).sum(0))
 
 
-def rel(a, b):
-    return float(np.linalg.norm(np.asarray(a) - np.asarray(b)) / np.linalg.norm(np.asarray(b)))
+def elem_err(a, ref):
+    """Element-wise parity measure: max_i |a_i - ref_i| / max_i |ref_i|.  One
+    element off by more than the bound fails, however many are right."""
+    a = np.asarray(a, dtype=np.float64).ravel()
+    ref = np.asarray(ref, dtype=np.float64).ravel()
+    assert a.shape == ref.shape, (a.shape, ref.shape)
+    scale = float(np.max(np.abs(ref)))
+    return float(np.max(np.abs(a - ref))) / (scale if scale > 0 else 1.0)
+
+
+def assert_elem(a, ref, tol, what=""):
+    """Assert elem_err(a, ref) <= tol and print the measured value."""
+    e = elem_err(a, ref)
+    print(f"  {what} elem_err {e:.3e} (bound {tol:.1e})", flush=True)
+    assert e <= tol, (what, e, tol)
 
 
 def both_params(**kw):

@@ -69,6 +69,20 @@ def test_entry_points_reject_null_context(lib):
                                  0, None) == 1
     assert lib.llg_workspace_bytes(None, 30, 0) == 0
     assert lib.llg_ctx_destroy(None) == 0
+    assert lib.llg_precond_op(None, ctypes.byref(p), None, None, None, None, 0, 0, None, None) == 1
+    assert lib.llg_precond_op_f32(None, ctypes.byref(p), None, None, None, None, 0, None, 0, 0, None, None) == 1
+    assert lib.gmres_solve_noalloc(None, ctypes.byref(p), None, None, None, ctypes.byref(o), None, None) == 1
+
+
+def test_binding_refuses_unaligned_tensors():
+    """The binding passes only 16-byte aligned device addresses to the C ABI
+    (the library also refuses others with LLG_EARG)."""
+    import torch
+    from paper_2607_15290_amd.llg import aligned_ptr
+    t = torch.zeros(64, dtype=torch.float64)
+    assert aligned_ptr(t) == t.data_ptr()
+    with pytest.raises(ValueError):
+        aligned_ptr(t[1:])
 
 
 def test_binding_structs_match_header_layout(tmp_path):

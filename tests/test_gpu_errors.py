@@ -13,7 +13,7 @@ import paper_2607_15290_amd as P
 from paper_2607_15290_amd import _lib as L
 from oracle import steppers
 from oracle.grid import Grid
-from tests.gpu_util import announce, both_params, dev, host, rel, unit_field
+from tests.gpu_util import announce, assert_elem, both_params, dev, host, unit_field
 
 pytestmark = pytest.mark.gpu
 
@@ -63,7 +63,8 @@ def test_status_codes_for_bad_inputs():
     # the context still solves correctly afterwards
     x, st = P.gmres_solve(ctx, prm, md, bd, rtol=1e-12)
     xref, _ = steppers.solve_saddle(g, op, m, b, rtol=1e-12)
-    assert st["converged"] == 1 and rel(host(x), xref) <= 1e-9
+    assert st["converged"] == 1
+    assert_elem(host(x), xref, 1e-9, "x")
     ctx.close()
 
 
@@ -117,6 +118,42 @@ def test_argument_errors():
                torch.zeros((3, 1, N, 2 * N), dtype=torch.float64, device="cuda:0")[..., ::2]):
         with pytest.raises(ValueError):
             P.llg_rhs(ctx, P.Params(alpha=0.1, dt=1e-3, h_field=hf), md)
+    # a device pointer that is not 16-byte aligned is refused before any kernel
+    # runs (the buffers are one element longer than the offset view needs, so
+    # every access would stay in bounds even if it were not refused)
+    mbig = torch.zeros(3 * N * N + 2, dtype=torch.float64, device="cuda:0")
+    mbig[1:1 + 3 * N * N] = md.reshape(-1)
+    xbig = torch.zeros(4 * N * N + 2, dtype=torch.float64, device="cuda:0")
+    y = torch.zeros_like(bd)
+    for (mp, xp) in ((mbig.data_ptr() + 8, bd.data_ptr()), (md.data_ptr(), xbig.data_ptr() + 8)):
+        s = ctx.lib.llg_matvec(ctx.handle, ctypes.byref(pr), mp, xp, y.data_ptr(), 0, None)
+        assert s == 1 and "aligned" in _last_error(ctx)
+        s = ctx.lib.fft_hss_apply(ctx.handle, ctypes.byref(pr), mp, xp, y.data_ptr(), 0, None)
+        assert s == 1 and "aligned" in _last_error(ctx)
+        s = ctx.lib.gmres_solve(ctx.handle, ctypes.byref(pr), mp, xp, x.data_ptr(), ctypes.byref(o), None,
+                                work.data_ptr(), work.numel(), None)
+        assert s == 1 and "aligned" in _last_error(ctx)
+    with pytest.raises(ValueError):
+        P.llg_matvec(ctx, prm, mbig[1:1 + 3 * N * N], bd)
+    # fused operator arguments: basis count, stride, side, aliasing
+    basis = torch.zeros((40, 4, 1, N, N), dtype=torch.float64, device="cuda:0")
+    dots = torch.zeros(40, dtype=torch.float64, device="cuda:0")
+    for nb, ld in ((33, 4 * N * N), (2, 4 * N * N - 2), (2, 4 * N * N + 1), (-1, 4 * N * N)):
+        s = ctx.lib.llg_precond_op(ctx.handle, ctypes.byref(pr), md.data_ptr(), bd.data_ptr(), y.data_ptr(),
+                                   basis.data_ptr(), nb, ld, dots.data_ptr(), None)
+        assert s == 1, (nb, ld)
+    s = ctx.lib.llg_precond_op(ctx.handle, ctypes.byref(pr), md.data_ptr(), bd.data_ptr(), bd.data_ptr(), None, 0,
+                               0, None, None)
+    assert s == 1 and "alias" in _last_error(ctx)
+    mf = md.float()
+    z = torch.zeros((4, 1, N, N), dtype=torch.float32, device="cuda:0")
+    for side, zp in ((2, z.data_ptr()), (1, None)):
+        s = ctx.lib.llg_precond_op_f32(ctx.handle, ctypes.byref(pr), mf.data_ptr(), bd.data_ptr(), y.data_ptr(),
+                                       zp, side, None, 0, 0, None, None)
+        assert s == 1, side
+    # transposed solves run in float64 only
+    _, st = P.gmres_solve(ctx, prm, md, bd, check=False, prec="fp32_ir", transpose=True)
+    assert st["status"] == "LLG_EARG"
     # unknown profiler kind
     assert ctx.lib.llg_profile_select(ctx.handle, b"no_such_kind") == 1
     assert ctx.lib.llg_profile_select(ctx.handle, None) == 0

@@ -16,7 +16,7 @@ import paper_2607_15290_amd as P
 from oracle import adjoint, steppers
 from oracle.grid import Grid
 from oracle.operators import Params as OP
-from tests.gpu_util import announce, dev, host, rel, unit_field
+from tests.gpu_util import announce, assert_elem, dev, host, unit_field
 
 pytestmark = pytest.mark.gpu
 GOLD = json.load(open(os.path.join(os.path.dirname(__file__), "golden", "paper_printed_values.json")))
@@ -46,7 +46,7 @@ def test_rhs_and_energy_match_oracle(shape, lengths):
     ctx = P.Context(nx, ny, nz, h, 0)
     b = P.llg_rhs(ctx, prm, dev(m))
     bref = steppers.rhs(g, op, m)
-    assert rel(host(b), bref) <= 1e-13
+    assert_elem(host(b), bref, 1e-13, "rhs")
     e = P.llg_energy(ctx, prm, dev(m))
     eref = steppers.energy(g, op, m)
     assert abs(e - eref) <= 1e-13 * abs(eref)
@@ -84,7 +84,7 @@ def test_euler_and_midpoint_steps_match_oracle():
             assert st["converged"] == 1
             assert st["picard_iters"] == info["picard_iters"]
             assert np.max(np.abs(host(md) - m_ref)) <= 1e-11
-            assert rel(host(vh), v_ref) <= 1e-9
+            assert_elem(host(vh), v_ref, 1e-9, "v")
             assert st["energy_after"] == pytest.approx(d["energy_after"], rel=1e-12)
             # length defect 2 k chi: the Picard tolerance 1e-12 leaves chi ~ 1e-13
             assert st["max_len_err"] <= 1e-11
@@ -115,8 +115,8 @@ def test_adjoint_with_lower_order_field_matches_oracle():
     hbf = torch.zeros_like(gb)
     hu, st = P.llg_step_midpoint_adjoint(ctx, prm, dev(m_n), dev(v), dev(r), gb, hbf, [0.0, 0.0, 0.0], rtol=1e-14)
     assert st["converged"] == 1
-    assert rel(host(gb), gb_ref) <= 1e-10
-    assert rel(host(hbf), hf_ref) <= 1e-10
+    assert_elem(host(gb), gb_ref, 1e-10, "gbar")
+    assert_elem(host(hbf), hf_ref, 1e-10, "hbar_field")
     np.testing.assert_allclose(hu, hu_ref, rtol=1e-10, atol=1e-14 * np.abs(hu_ref).max())
     ctx.close()
 

@@ -1,21 +1,37 @@
 """GPU parity of the operators behind the C ABI: the saddle matvec, the split
-FFT-HSS apply (plain and transposed) in float64 and float32, against the FP64
-oracle -- the dense assembled matrices on tiny grids and the FFT tier on
-grids that span several tiles with ragged column tiles, up to full workload
-sizes."""
+FFT-HSS apply (plain and transposed) and the fused preconditioned operators
+M^{-1} A, in float64 and float32, against the FP64 oracle -- the dense
+assembled matrices on tiny grids and the FFT tier on grids that span several
+tiles with ragged column tiles, including 256-point lines along x, y and z
+(the line lengths of the 256^3 workload's kernels).  Every comparison is
+element-wise: max |gpu - ref| <= tol * max |ref|."""
+
+import math
 
 import numpy as np
 import pytest
 import torch
 
+import llg_workloads as W
 import paper_2607_15290_amd as P
 from oracle import dense, operators
 from oracle.grid import Grid
-from tests.gpu_util import announce, both_params, dev, host, rel, unit_field
+from oracle.operators import Params as OP
+from tests.gpu_util import announce, assert_elem, both_params, dev, host, unit_field
 
 pytestmark = pytest.mark.gpu
 
 KW = dict(alpha=0.1, cexc=1.0, dt=2e-3, theta=1.0, shift=0.5)
+U32 = 2.0 ** -24  # float32 unit roundoff
+
+
+def fp32_bound(shape):
+    """Element-wise bound of a float32 pipeline relative to max |ref|: one unit
+    roundoff per butterfly level of each forward and inverse line DFT (2
+    log2 n per axis of length n > 1) plus 16 for the rounding of the inputs
+    and the nodal prologue / epilogue arithmetic."""
+    levels = sum(2 * math.ceil(math.log2(n)) for n in shape if n > 1)
+    return (levels + 16) * U32
 
 
 def _case(nx, ny, nz, seed, kw=KW, unit=True):
@@ -39,19 +55,20 @@ def test_apply_and_matvec_match_dense(shape, theta):
     A = dense.saddle_matrix(g, op, m)
     md, pd = dev(m), dev(p)
     z = host(P.fft_hss_apply(ctx, prm, md, pd)).ravel()
-    zref = np.linalg.solve(M2, np.linalg.solve(M1, p.ravel()))
-    assert rel(z, zref) <= 1e-12
+    assert_elem(z, np.linalg.solve(M2, np.linalg.solve(M1, p.ravel())), 1e-12, "apply")
     zt = host(P.fft_hss_apply(ctx, prm, md, pd, transpose=True)).ravel()
-    assert rel(zt, np.linalg.solve((M1 @ M2).T, p.ravel())) <= 1e-12
+    assert_elem(zt, np.linalg.solve((M1 @ M2).T, p.ravel()), 1e-12, "apply^T")
     y = host(P.llg_matvec(ctx, prm, md, pd)).ravel()
-    assert rel(y, A @ p.ravel()) <= 1e-12
+    assert_elem(y, A @ p.ravel(), 1e-12, "matvec")
     yt = host(P.llg_matvec(ctx, prm, md, pd, transpose=True)).ravel()
-    assert rel(yt, A.T @ p.ravel()) <= 1e-12
+    assert_elem(yt, A.T @ p.ravel(), 1e-12, "matvec^T")
+    w = host(P.llg_precond_op(ctx, prm, md, pd)).ravel()
+    assert_elem(w, np.linalg.solve(M2, np.linalg.solve(M1, A @ p.ravel())), 1e-12, "M^-1 A")
     ctx.close()
 
 
 SHAPES = [(16, 16, 1), (32, 64, 1), (128, 32, 1), (512, 8, 1), (16, 32, 8), (64, 16, 32), (32, 32, 32),
-          (8, 128, 16), (256, 8, 4)]
+          (8, 128, 16), (256, 8, 4), (256, 256, 8), (256, 8, 256), (8, 256, 256)]
 
 
 @pytest.mark.parametrize("shape", SHAPES)
@@ -62,31 +79,117 @@ def test_operators_match_fft_oracle(shape):
     md, pd = dev(m), dev(p)
     for tr in (False, True):
         z = host(P.fft_hss_apply(ctx, prm, md, pd, transpose=tr))
-        assert rel(z, operators.hss_apply(g, op, m, p, transpose=tr)) <= 1e-12
+        assert_elem(z, operators.hss_apply(g, op, m, p, transpose=tr), 1e-12, f"apply tr={tr}")
         y = host(P.llg_matvec(ctx, prm, md, pd, transpose=tr))
         ref = operators.matvec_transpose(g, op, m, p) if tr else operators.matvec(g, op, m, p)
-        assert rel(y, ref) <= 1e-12
+        assert_elem(y, ref, 1e-12, f"matvec tr={tr}")
     # in-place apply (z aliases p)
     q = pd.clone()
     P.fft_hss_apply(ctx, prm, md, q, z=q)
-    assert rel(host(q), operators.hss_apply(g, op, m, p)) <= 1e-12
+    assert_elem(host(q), operators.hss_apply(g, op, m, p), 1e-12, "apply in place")
     ctx.close()
 
 
-@pytest.mark.parametrize("shape", [(16, 16, 1), (64, 32, 1), (32, 16, 16), (64, 64, 64)])
+F32_SHAPES = [(16, 16, 1), (64, 32, 1), (32, 16, 16), (64, 64, 64), (256, 256, 8), (256, 8, 256), (8, 256, 256),
+              (256, 24, 20)]
+
+
+@pytest.mark.parametrize("shape", F32_SHAPES)
 def test_float32_operators(shape):
-    """float32 pipelines against the float64 oracle; bound: a few FFT passes
-    of float32 rounding, 2e-6 relative."""
+    """float32 pipelines against the float64 oracle evaluated on the same
+    float32 inputs, element-wise within fp32_bound(shape)."""
     nx, ny, nz = shape
     announce(f"fp32 parity {shape}")
     g, m, p, prm, op, ctx = _case(nx, ny, nz, 11)
     mf, pf = dev(m, torch.float32), dev(p, torch.float32)
+    m32, p32 = host(mf), host(pf)
+    tol = fp32_bound(shape)
     for tr in (False, True):
         z = host(P.fft_hss_apply_f32(ctx, prm, mf, pf, transpose=tr))
-        assert rel(z, operators.hss_apply(g, op, m, p, transpose=tr)) <= 2e-6
+        assert_elem(z, operators.hss_apply(g, op, m32, p32, transpose=tr), tol, f"apply tr={tr}")
         y = host(P.llg_matvec_f32(ctx, prm, mf, pf, transpose=tr))
-        ref = operators.matvec_transpose(g, op, m, p) if tr else operators.matvec(g, op, m, p)
-        assert rel(y, ref) <= 2e-6
+        ref = operators.matvec_transpose(g, op, m32, p32) if tr else operators.matvec(g, op, m32, p32)
+        assert_elem(y, ref, tol, f"matvec tr={tr}")
+    ctx.close()
+
+
+def _workload_params(nx, ny, nz):
+    """Midpoint saddle system of the 3D workloads' kind on this grid: alpha
+    0.02, dt 13.3 times the explicit exchange limit, lambda 0.5."""
+    dim = 2 if nz == 1 else 3
+    dt = W.dt_explicit_multiple(13.3, 0.02, max(nx, ny, nz), dim)
+    return dict(alpha=0.02, cexc=1.0, dt=dt, theta=0.5, shift=0.5, h_uniform=(0.0, 0.0, 1.0))
+
+
+PRECOND_SHAPES = [(16, 16, 1), (32, 16, 16), (48, 40, 24), (256, 256, 8), (256, 8, 256), (256, 256, 1)]
+
+
+@pytest.mark.parametrize("shape", PRECOND_SHAPES)
+def test_fused_preconditioned_operator_float64(shape):
+    """llg_precond_op: M^{-1} A x in one pipeline (the exact splitting identity)
+    against the oracle's unfused M^{-1}(A x), element-wise 1e-13, and the
+    Arnoldi products u_q . y it forms in the same pass against numpy's."""
+    nx, ny, nz = shape
+    announce(f"precond_op f64 {shape}")
+    kw = _workload_params(nx, ny, nz)
+    g = Grid(nx, ny, nz, h=1.0 / nx)
+    prm, op = both_params(**kw)
+    m = unit_field((nz, ny, nx), 21, smooth=40.0)
+    x = np.random.default_rng(22).standard_normal((4, nz, ny, nx))
+    ctx = P.Context(nx, ny, nz, 1.0 / nx, 0)
+    md, xd = dev(m), dev(x)
+    y = host(P.llg_precond_op(ctx, prm, md, xd))
+    assert_elem(y, operators.precond_op(g, op, m, x), 1e-13, "M^-1 A")
+    basis = torch.randn((5, 4, nz, ny, nx), dtype=torch.float64, device="cuda:0")
+    y2, dots = P.llg_precond_op(ctx, prm, md, xd, basis=basis)
+    yh = host(y2)
+    assert np.array_equal(yh, y)
+    bh = host(basis).reshape(5, -1)
+    want = bh @ yh.ravel()
+    scale = np.abs(bh) @ np.abs(yh.ravel())
+    assert np.all(np.abs(host(dots) - want) <= 1e-13 * scale), (host(dots), want)
+    ctx.close()
+
+
+@pytest.mark.parametrize("shape", PRECOND_SHAPES)
+def test_fused_preconditioned_operators_float32(shape):
+    """llg_precond_op_f32 between float64 Krylov vectors: side 0, M^{-1} A x in
+    one float32 pipeline; side 1, z = M^{-1} x (float32) and y = A z, the
+    precision form's inner operator (two float32 pipelines joined by one x
+    pass).  Each float32 half against the oracle on the same inputs within
+    fp32_bound; the Arnoldi products formed in the last pass against numpy's
+    products of the returned y."""
+    nx, ny, nz = shape
+    announce(f"precond_op f32 {shape}")
+    kw = _workload_params(nx, ny, nz)
+    g = Grid(nx, ny, nz, h=1.0 / nx)
+    prm, op = both_params(**kw)
+    m = unit_field((nz, ny, nx), 23, smooth=40.0)
+    x = np.random.default_rng(24).standard_normal((4, nz, ny, nx))
+    ctx = P.Context(nx, ny, nz, 1.0 / nx, 0)
+    mf, xd = dev(m, torch.float32), dev(x)
+    m32 = host(mf)
+    x32 = x.astype(np.float32).astype(np.float64)
+    tol = fp32_bound(shape)
+    basis = torch.randn((4, 4, nz, ny, nx), dtype=torch.float64, device="cuda:0")
+    bh = host(basis).reshape(4, -1)
+    # side 0: left fused operator
+    y, dots = P.llg_precond_op_f32(ctx, prm, mf, xd, side=0, basis=basis)
+    yh = host(y)
+    assert_elem(yh, operators.precond_op(g, op, m32, x32), 4 * tol, "f32 M^-1 A")
+    scale = np.abs(bh) @ np.abs(yh.ravel())
+    assert np.all(np.abs(host(dots) - bh @ yh.ravel()) <= 1e-13 * scale)
+    # side 1: z = M^{-1} x, y = A z
+    z = torch.empty((4, nz, ny, nx), dtype=torch.float32, device="cuda:0")
+    y, dots = P.llg_precond_op_f32(ctx, prm, mf, xd, side=1, z=z, basis=basis)
+    zh, yh = host(z), host(y)
+    assert_elem(zh, operators.hss_apply(g, op, m32, x32), tol, "f32 z = M^-1 x")
+    assert_elem(yh, operators.matvec(g, op, m32, zh), tol, "f32 y = A z")
+    scale = np.abs(bh) @ np.abs(yh.ravel())
+    assert np.all(np.abs(host(dots) - bh @ yh.ravel()) <= 1e-13 * scale)
+    # without the Arnoldi products the operator output is the same
+    y0, _ = P.llg_precond_op_f32(ctx, prm, mf, xd, side=1, z=z)
+    assert np.array_equal(host(y0), yh)
     ctx.close()
 
 

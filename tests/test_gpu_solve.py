@@ -8,7 +8,7 @@ import llg_workloads as W
 import paper_2607_15290_amd as P
 from oracle import dense, operators, steppers
 from oracle.grid import Grid
-from tests.gpu_util import announce, both_params, dev, host, rel, unit_field
+from tests.gpu_util import announce, assert_elem, both_params, dev, host, unit_field
 
 pytestmark = pytest.mark.gpu
 
@@ -26,7 +26,13 @@ def test_gmres_matches_dense_solve(shape, theta):
     ctx = P.Context(nx, ny, nz, h, 0)
     x, st = P.gmres_solve(ctx, prm, dev(m), dev(b), rtol=1e-14)
     assert st["converged"] == 1 and st["rel_res_true"] <= 1e-14
-    assert rel(host(x), xs) <= 1e-12
+    assert_elem(host(x), xs, 1e-12, "x")
+    assert st["restarts"] == st["cycles"] - 1 and st["ms"] > 0
+    # the transposed system A^T x = b, preconditioned by M^T
+    xt, stt = P.gmres_solve(ctx, prm, dev(m), dev(b), rtol=1e-14, transpose=True)
+    assert stt["converged"] == 1 and stt["rel_res_true"] <= 1e-14
+    assert_elem(host(xt), np.linalg.solve(dense.saddle_matrix(g, op, m).T, b.ravel()).reshape(b.shape), 1e-12,
+                "x (transposed)")
     ctx.close()
 
 
@@ -45,7 +51,60 @@ def test_gmres_matches_oracle_gmres(shape):
     assert st["converged"] == 1
     assert abs(st["iters"] - ir["iters"]) <= 1
     # both solutions within the tolerance-scaled distance of each other
-    assert rel(host(x), xr) <= 1e-8
+    assert_elem(host(x), xr, 1e-8, "x")
+    # transposed system against the oracle's transposed GMRES (left, M^T)
+    xtr, itr = steppers.solve_saddle(g, op, m, b, rtol=1e-10, transpose=True)
+    xt, stt = P.gmres_solve(ctx, prm, dev(m), dev(b), rtol=1e-10, transpose=True)
+    assert stt["converged"] == 1 and abs(stt["iters"] - itr["iters"]) <= 1
+    assert_elem(host(xt), xtr, 1e-8, "x (transposed)")
+    ctx.close()
+
+
+def _workload_system(nx, ny, nz, seed):
+    """First Picard system of a midpoint step of the 3D workloads' kind
+    (alpha 0.02, dt 13.3 times the explicit limit, h = (0, 0, 1), smooth field
+    with a 1% rough part) on an nx x ny x nz grid."""
+    h = 1.0 / nx
+    g = Grid(nx, ny, nz, h=h)
+    dt = W.dt_explicit_multiple(13.3, 0.02, max(nx, ny, nz), 3)
+    prm, op = both_params(alpha=0.02, cexc=1.0, dt=dt, theta=0.5, shift=0.5, h_uniform=(0.0, 0.0, 1.0))
+    m = unit_field((nz, ny, nx), seed, smooth=30.0)
+    m = m + 0.01 * unit_field((nz, ny, nx), seed + 1)
+    m = m / np.sqrt((m * m).sum(0))
+    return g, prm, op, m, steppers.rhs(g, op, m)
+
+
+@pytest.mark.parametrize("shape", [(256, 256, 8), (256, 8, 256)])
+def test_gmres_all_precisions_match_oracle_on_256_lines(shape):
+    """GMRES(30) to 1e-10 on grids whose lines are 256 points long (the
+    kernels of the 256^3 workload: x passes of half-length 128, 256-point
+    axis passes, the fused Arnoldi products of the matvec / M^{-1} A passes)
+    against the oracle's solvers: float64 left-preconditioned GMRES, the
+    flexible precision form (FP32 inner operator) and its left variant, each
+    with the same restart, tolerances and inner stopping rule.  Iteration
+    counts within one of the oracle's, solutions element-wise to the
+    tolerance-scaled distance 1e-8."""
+    from oracle import gmres as og
+    nx, ny, nz = shape
+    announce(f"gmres vs oracle on 256-point lines {shape}")
+    g, prm, op, m, b = _workload_system(nx, ny, nz, 31)
+    A = lambda v: operators.matvec(g, op, m, v)
+    M = lambda v: operators.hss_apply(g, op, m, v)
+    ctx = P.Context(nx, ny, nz, 1.0 / nx, 0)
+    md, bd = dev(m), dev(b)
+    xr, ir = steppers.solve_saddle(g, op, m, b, rtol=1e-10)
+    x, st = P.gmres_solve(ctx, prm, md, bd, rtol=1e-10)
+    print(f"  fp64 iters gpu {st['iters']} oracle {ir['iters']}", flush=True)
+    assert st["converged"] == 1 and abs(st["iters"] - ir["iters"]) <= 1
+    assert_elem(host(x), xr, 1e-8, "fp64 x")
+    for prec, inner in (("fp32_ir", "flexible"), ("fp32_ir_left", "left")):
+        xo, io = og.fgmres_ir(A, M, b, restart=30, rtol=1e-10, inner_rtol=1e-3, max_outer=20, inner=inner)
+        x, st = P.gmres_solve(ctx, prm, md, bd, rtol=1e-10, prec=prec, inner_rtol=1e-3)
+        print(f"  {prec} iters gpu {st['iters']} / {st['outer_steps']} oracle {io['iters']} / {io['outer_steps']}",
+              flush=True)
+        assert st["converged"] == 1 and io["converged"]
+        assert abs(st["iters"] - io["iters"]) <= 1 and st["outer_steps"] == io["outer_steps"], (prec, st, io)
+        assert_elem(host(x), xo, 1e-8, f"{prec} x")
     ctx.close()
 
 
@@ -93,7 +152,7 @@ def test_euler_step_matches_oracle_first_workload():
     st = P.llg_step_euler(ctx, prm, md, v, lam, rtol=1e-10)
     assert st["converged"] == 1
     assert abs(st["lin_iters_total"] - info["iters"]) <= 1
-    assert rel(host(v), v_ref) <= 1e-8
+    assert_elem(host(v), v_ref, 1e-8, "v")
     assert np.max(np.abs(host(md) - m_ref)) <= 1e-10
     assert st["max_len_err"] <= 1e-14
     ctx.close()
@@ -150,7 +209,7 @@ def test_fp32_ir_matches_fp64():
                                          orth=orth)
                 assert s32["converged"] == 1 and s32["rel_res_true"] <= 1e-10, (prec, orth)
                 assert s32["outer_steps"] >= 2
-                assert rel(host(x32), host(x64)) <= 1e-8
+                assert_elem(host(x32), host(x64), 1e-8, f"{prec} {orth} x")
                 # inner iterations comparable to the float64 solve's
                 assert s32["iters"] <= 2 * s64["iters"] + 10, (prec, orth, s32["iters"], s64["iters"])
         ctx.close()
@@ -179,7 +238,7 @@ def test_restart_boundaries_match_dense_solve(prec, restart):
     assert st["converged"] == 1 and st["rel_res_true"] <= 1e-12, st
     # at least one cycle was cut at the restart length
     assert st["iters"] > restart, st
-    assert rel(host(x), xs) <= 1e-9
+    assert_elem(host(x), xs, 1e-9, "x")
     ctx.close()
 
 

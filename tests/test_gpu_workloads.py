@@ -12,7 +12,7 @@ import paper_2607_15290_amd as P
 from oracle import operators, steppers
 from oracle.grid import Grid
 from oracle.operators import Params as OP
-from tests.gpu_util import announce, dev, host, rel
+from tests.gpu_util import announce, assert_elem, dev, host
 
 pytestmark = pytest.mark.gpu
 
@@ -43,7 +43,7 @@ def test_workload2_midpoint_512():
             assert abs(st["picard_iters"] - info["picard_iters"]) <= 1
             # both sides converge Picard and GMRES to 1e-10
             assert np.max(np.abs(host(m) - m_ref)) <= 1e-10
-            assert rel(host(vh), v_ref) <= 1e-8
+            assert_elem(host(vh), v_ref, 1e-8, "v")
             len_ref = steppers.midpoint_diagnostics(g, op, spec["m0"], m_ref, v_ref, l_ref)["max_len_err"]
             assert st["max_len_err"] <= 2 * len_ref + 1e-12
         assert st["converged"] == 1
@@ -73,7 +73,7 @@ def test_workload3_euler_128_fp32ir_vs_fp64():
         xr = host(x)
         r = b - operators.matvec(g, op, m0, xr)
         assert np.linalg.norm(r) <= 1.05e-10 * np.linalg.norm(b)
-    assert rel(host(x32), host(x64)) <= 1e-8
+    assert_elem(host(x32), host(x64), 1e-8, "x fp32-ir vs fp64")
     # two Euler steps in each precision agree
     ms = []
     for prec in ("fp64", "fp32_ir"):
@@ -96,16 +96,20 @@ def test_workload4_midpoint_256_first_solve_and_step():
     b = P.llg_rhs(ctx, prm, md)
     bh = host(b)
     # right-hand side against the oracle (one FFT Laplacian)
-    assert rel(bh, steppers.rhs(g, op, m0)) <= 1e-12
-    for prec in ("fp64", "fp32_ir"):
-        x, s = P.gmres_solve(ctx, prm, md, b, rtol=1e-10, prec=prec, inner_rtol=1e-5)
+    assert_elem(bh, steppers.rhs(g, op, m0), 1e-12, "rhs")
+    # the benchmark's inner tolerance (1e-3) and a tight one, each accepted on
+    # the oracle's own residual
+    for prec, inner in (("fp64", 1e-3), ("fp32_ir", 1e-3), ("fp32_ir", 1e-5), ("fp32_ir_left", 1e-3)):
+        x, s = P.gmres_solve(ctx, prm, md, b, rtol=1e-10, prec=prec, inner_rtol=inner)
         assert s["converged"] == 1
         r = bh - operators.matvec(g, op, m0, host(x))
+        print(f"  {prec} inner {inner}: iters {s['iters']} oracle residual "
+              f"{np.linalg.norm(r) / np.linalg.norm(bh):.2e}", flush=True)
         assert np.linalg.norm(r) <= 1.05e-10 * np.linalg.norm(bh), prec
         del x
     vh = torch.zeros_like(md)
     lam = torch.zeros((1,) + tuple(md.shape[1:]), dtype=torch.float64, device="cuda:0")
-    st = P.llg_step_midpoint(ctx, prm, md, vh, lam, picard_tol=1e-10, rtol=1e-10, prec="fp32_ir", inner_rtol=1e-5)
+    st = P.llg_step_midpoint(ctx, prm, md, vh, lam, picard_tol=1e-10, rtol=1e-10, prec="fp32_ir", inner_rtol=1e-3)
     assert st["converged"] == 1 and st["max_len_err"] <= 1e-9
     assert abs(st["dissipation_defect"] - st["inexact_correction"]) <= 1e-13 * abs(st["energy_before"])
     ctx.close()
