@@ -132,7 +132,7 @@ def profiled_timing(P, ctx, run, log_label):
     run()
     P.llg_profile_enable(ctx, False)
     prof_all = P.llg_profile_read(ctx)
-    dom_kind = max(prof_all.items(), key=lambda kv: kv[1]["total_ms"])[0]
+    dom_kind = dominant_kind(prof_all)
     log(f"{log_label}: timed pass (events around {dom_kind} only)")
     P.llg_profile_select(ctx, [dom_kind])
     torch.cuda.synchronize()
@@ -147,8 +147,17 @@ def profiled_timing(P, ctx, run, log_label):
     return t, out, prof_all, prof
 
 
+def dominant_kind(prof):
+    """The kernel kind with the largest total time among those that stream
+    the grid (the value reductions, a few kilobytes each, are excluded: on
+    small grids their launch latency would otherwise rank first)."""
+    cands = {k: v for k, v in prof.items() if k != "reduce"} or prof
+    return max(cands.items(), key=lambda kv: kv[1]["total_ms"])[0]
+
+
 def roofline_of(prof, footprint_bytes, traffic_kernel=None):
-    dom_name, dom = max(prof.items(), key=lambda kv: kv[1]["total_ms"])
+    dom_name = dominant_kind(prof)
+    dom = prof[dom_name]
     achieved = dom["bytes"] / (dom["total_ms"] * 1e-3) / 1e9
     bpl = dom["bytes"] / dom["launches"]
     traffic = measured_traffic(dom_name, bpl) if traffic_kernel is None or traffic_kernel == dom_name else None
@@ -597,6 +606,37 @@ def run_solver_workload(args, P, W, torch, wid):
     return line
 
 
+def adjoint_step_comparison(P, ctx, spec, prm, m0, hf0, torch):
+    """The adjoint of the workload's first step, solved with GMRES
+    right-preconditioned by M^{-T} in one pipeline per iteration (orth dcgs2,
+    the default) and left-preconditioned on M^{-T} J^T in two (orth cgs2):
+    iterations and median time of 3 after one warm-up each."""
+    m = m0.clone()
+    vh = torch.zeros_like(m)
+    lam = torch.zeros((1,) + tuple(m.shape[1:]), dtype=torch.float64, device=ctx.device)
+    prm_f = P.Params(alpha=prm.alpha, cexc=1.0, dt=prm.dt, theta=0.5, shift=prm.shift,
+                     h_uniform=spec["h_uniform"], h_field=hf0)
+    P.llg_step_midpoint(ctx, prm_f, m, vh, lam, picard_tol=spec["picard_tol"], rtol=spec["rtol"])
+    gbar0 = torch.zeros_like(m)
+    gbar0[2] = 2 * m[2]
+    out = {}
+    for label, orth in (("right_one_pipeline", "dcgs2"), ("left_two_pipelines", "cgs2")):
+        times = []
+        for i in range(4):
+            gb = gbar0.clone()
+            torch.cuda.synchronize()
+            t0 = time.perf_counter()
+            _, st = P.llg_step_midpoint_adjoint(ctx, prm_f, m0, vh, lam, gb, None, None, rtol=1e-10, orth=orth)
+            torch.cuda.synchronize()
+            if i:
+                times.append(time.perf_counter() - t0)
+        out[label] = dict(iters=st["iters"], median_ms=round(1e3 * statistics.median(times), 3),
+                          rel_res_true=st["rel_res_true"])
+    out["speedup_right_vs_left"] = round(out["left_two_pipelines"]["median_ms"] /
+                                         out["right_one_pipeline"]["median_ms"], 3)
+    return out
+
+
 def run_adjoint_workload(args, P, W, torch):
     """Workload 5: forward (20 midpoint steps, checkpoints every 5) and
     backward (recompute each segment, one transposed saddle solve per step)
@@ -634,6 +674,8 @@ def run_adjoint_workload(args, P, W, torch):
 
     t, out, prof_all, prof = profiled_timing(P, ctx, run, "trajectory forward + backward")
     loss, gm, ghf, ghu = out
+    log("one adjoint step: right-preconditioned one-pipeline solve vs the left two-pipeline form")
+    adj = adjoint_step_comparison(P, ctx, spec, prm, m0, hf0, torch)
     line = base_line(args, f"differentiable trajectories/s (forward + backward), 2D {n}^2 midpoint, {nsteps} "
                            f"steps, checkpoints every {spec['ckpt_every']}", 1.0 / t,
                      "trajectories/s", 1e3 * t / nsteps, nsteps, "f64", {
@@ -641,7 +683,7 @@ def run_adjoint_workload(args, P, W, torch):
                          "dt": spec["dt"], "shift": spec["shift"], "h_uniform": list(spec["h_uniform"]),
                          "h_field": "N(0, 0.1^2)", "loss": "sum m_z^2 at the last step", "rtol": spec["rtol"],
                          "adjoint_rtol": 1e-10, "ckpt_every": spec["ckpt_every"], "parallelism": "1 GPU"})
-    line.update({"forward_s": times["fwd"], "backward_s": times["bwd"], "loss": loss,
+    line.update({"forward_s": times["fwd"], "backward_s": times["bwd"], "loss": loss, "adjoint_step": adj,
                  "grad_norms": {"m0": gm, "h_field": ghf, "h_uniform": ghu}, "ops": ops,
                  "roofline": roofline_of(prof, footprint(spec, "fp64")), "kernels": kernel_table(prof_all)})
     if not args.no_cpu_baseline:

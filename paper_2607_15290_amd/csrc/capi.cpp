@@ -263,6 +263,7 @@ struct Work {
   double* t = nullptr;   // n4 temporary
   float* Z = nullptr;    // R x n4 (precision form)
   float* m32 = nullptr;  // 3 ng   (precision form)
+  float* W32 = nullptr;  // n4     (precision form: the float32 operator output of an Arnoldi step)
   double* b = nullptr;   // n4  stepper right-hand side
   double* x = nullptr;   // n4  stepper unknown
   double* m0 = nullptr;  // 3 ng
@@ -288,6 +289,7 @@ Work carve(const Ctx& c, int R, int prec, void* base) {
   w.t = reinterpret_cast<double*>(take(sizeof(double) * n4));
   if (prec == LLG_FP32_IR) w.Z = reinterpret_cast<float*>(take(sizeof(float) * n4 * R));
   if (prec != LLG_FP64) w.m32 = reinterpret_cast<float*>(take(sizeof(float) * n3));
+  if (prec != LLG_FP64) w.W32 = reinterpret_cast<float*>(take(sizeof(float) * n4));
   w.b = reinterpret_cast<double*>(take(sizeof(double) * n4));
   w.x = reinterpret_cast<double*>(take(sizeof(double) * n4));
   w.m0 = reinterpret_cast<double*>(take(sizeof(double) * n3));
@@ -396,8 +398,13 @@ struct CycleResult {
 #ifndef LLG_FUSE_DOTS
 #define LLG_FUSE_DOTS 1
 #endif
-using ArnoldiOp = std::function<hipError_t(int, const double*, double*, const BasisDots*)>;
-llg_status cycle_dcgs2(const Ctx& c, const ArnoldiOp& op, bool op_dots, const double* u0, double* U1, double* W,
+// The operator output W is float64, or float32 for the precision form's
+// float32 operators (exact: their values are float32).
+template <typename TW>
+using ArnoldiOpT = std::function<hipError_t(int, const double*, TW*, const BasisDots*)>;
+using ArnoldiOp = ArnoldiOpT<double>;
+template <typename TW>
+llg_status cycle_dcgs2(const Ctx& c, const ArnoldiOpT<TW>& op, bool op_dots, const double* u0, double* U1, TW* W,
                        long long n4, double c0, int R, double eta, int maxiter, int& iters, CycleResult& out,
                        hipStream_t st) {
   if (R >= kDcgsMaxCols) return fail(LLG_EARG, "delayed CGS2 needs restart <= 31");
@@ -417,6 +424,23 @@ llg_status cycle_dcgs2(const Ctx& c, const ArnoldiOp& op, bool op_dots, const do
     out.k = 0;
     return LLG_OK;
   }
+  // Operator of step jj on u_jj into W, its pass-1 products into pslot.
+  hipError_t op_err = hipSuccess;
+  auto launch_op = [&](int jj, double* pslot) {
+    const double* ujj = jj == 0 ? u0 : U1 + size_t(jj - 1) * n4;
+    hipError_t e;
+    if (op_dots) {
+      BasisDots bq{u0, U1, n4, jj + 1, nullptr};
+      bq.out = pslot;
+      e = op(jj, ujj, W, &bq);
+    } else {
+      e = op(jj, ujj, W, nullptr);
+      if (e == hipSuccess) e = dcgs_dots(c, u0, U1, n4, jj, W, n4, pslot, st);
+    }
+    if (e != hipSuccess && op_err == hipSuccess) op_err = e;
+  };
+  const bool speculate = c.ng <= kSpeculateMaxNodes;
+  bool ahead = false;  // step j's operator was launched during step j - 1
   for (int j = 0;; ++j) {
     if (j > 0) {
       for (int i = 0; i < j; ++i) col[i] = hprev[i] + a[i];
@@ -441,19 +465,29 @@ llg_status cycle_dcgs2(const Ctx& c, const ArnoldiOp& op, bool op_dots, const do
     for (int i = 0; i <= j; ++i) cf.minv[i] = MI(i, j);
     cf.inv_beta = 1.0 / beta;
     cf.j = j;
-    const double* uj = j == 0 ? u0 : U1 + size_t(j - 1) * n4;
-    if (op_dots) {
-      const BasisDots bq{u0, U1, n4, j + 1, nullptr};
-      CHK(op(j, uj, W, &bq));
-    } else {
-      CHK(op(j, uj, W, nullptr));
-      CHK(dcgs_dots(c, u0, U1, n4, j, W, n4, c.dots, st));
-    }
-    CHK(dcgs_update(c, u0, U1, n4, cf, c.dots, W, U1 + size_t(j) * n4, n4, c.dots2, st));
+    // pass-1 products of step j go to slot j % 2 (c.dots or c.dots_b), so the
+    // operator of step j + 1, launched ahead, cannot overwrite them
+    double* pslot = (j & 1) ? c.dots_b : c.dots;
+    if (!ahead) launch_op(j, pslot);
+    CHK(dcgs_update(c, u0, U1, n4, cf, pslot, W, U1 + size_t(j) * n4, n4, c.dots2, st));
     // one round trip: pass-1 dots p and the pass-2 dots of u_{j+1}, which their
-    // reductions also wrote into the mapped host mirror
-    CHK(hipStreamSynchronize(st));
-    std::memcpy(vals.data(), c.hmirror, sizeof(double) * 2 * kMaxDots);
+    // reductions also wrote into the mapped host mirror.  On small grids the
+    // next step's operator (on u_{j+1}, which no host decision changes) is
+    // queued first, and the host waits only for this step's passes; when the
+    // cycle then ends, that work is discarded.
+    ahead = speculate && j + 1 < R && iters + 1 < maxiter;
+    if (ahead) {
+      CHK(hipEventRecord(c.ev, st));
+      launch_op(j + 1, ((j + 1) & 1) ? c.dots_b : c.dots);
+      CHK(hipEventSynchronize(c.ev));
+    } else {
+      CHK(hipStreamSynchronize(st));
+    }
+    if (op_err != hipSuccess) {
+      CHK(op_err);
+    }
+    std::memcpy(vals.data(), c.hmirror + (pslot - c.dots), sizeof(double) * kMaxDots);
+    std::memcpy(vals.data() + kMaxDots, c.hmirror + kMaxDots, sizeof(double) * kMaxDots);
     const double* p = vals.data();
     const double* s = vals.data() + kMaxDots;
     const double d = p[j];
@@ -579,7 +613,7 @@ llg_status gmres_left(const Ctx& c, const ResidOp& RA, const Op& M, const Op& MA
       auto op = [&](int, const double* u, double* wout, const BasisDots* bq) {
         return MAd ? (*MAd)(u, wout, bq) : MA(u, wout);
       };
-      CHK_STATUS(cycle_dcgs2(c, op, MAd != nullptr && LLG_FUSE_DOTS != 0, U0, U0 + n4, W, n4, un[1], R,
+      CHK_STATUS(cycle_dcgs2<double>(c, op, MAd != nullptr && LLG_FUSE_DOTS != 0, U0, U0 + n4, W, n4, un[1], R,
                              target / rho, o.maxiter, res.iters, cr, st));
       if (!is_fin(cr.beta0)) return fail(LLG_ENAN, "non-finite preconditioned residual");
       if (beta0 < 0) beta0 = cr.beta0;
@@ -673,7 +707,7 @@ llg_status gmres_right(const Ctx& c, const ResidOp& RA, const Op& M, const OpDot
     res.cycles++;
     CycleResult cr;
     auto op = [&](int, const double* u, double* wout, const BasisDots* bq) { return AMd(u, wout, bq); };
-    CHK_STATUS(cycle_dcgs2(c, op, LLG_FUSE_DOTS != 0, w.r, w.V, W, n4, rho * rho, R, target / rho, o.maxiter,
+    CHK_STATUS(cycle_dcgs2<double>(c, op, LLG_FUSE_DOTS != 0, w.r, w.V, W, n4, rho * rho, R, target / rho, o.maxiter,
                            res.iters, cr, st));
     res.rel_prec = cr.gres / bnorm;
     if (cr.k == 0) break;
@@ -770,8 +804,13 @@ llg_status gmres_ir(const Ctx& c, const llg_params* p, const double* m, const do
       };
       CycleResult cr;
       if (o.orth == 0) {
-        CHK_STATUS(cycle_dcgs2(c, opl, LLG_FUSE_DOTS != 0, Q, Q + n4, W, n4, un[1], R, eta, o.maxiter, res.iters,
-                               cr, st));
+        // delayed CGS2: the fused float32 operator's output goes to W32 in float32
+        ArnoldiOpT<float> opl32 = [&](int, const double* u, float* wout, const BasisDots* bq) -> hipError_t {
+          PipeIO<float, double, float> io{u, w.m32, wout, c.ng, nullptr, nullptr};
+          return run_pipeline<float, double, float>(c, PRO_SMINUS, EPI_FUSED, sym_ap, na, io, st, bq, c.dots);
+        };
+        CHK_STATUS(cycle_dcgs2<float>(c, opl32, LLG_FUSE_DOTS != 0, Q, Q + n4, w.W32, n4, un[1], R, eta,
+                                      o.maxiter, res.iters, cr, st));
       } else {
         const double beta = std::sqrt(un[1]);
         if (!is_fin(beta)) return fail(LLG_ENAN, "non-finite preconditioned residual");
@@ -801,13 +840,13 @@ llg_status gmres_ir(const Ctx& c, const llg_params* p, const double* m, const do
     if (o.orth == 0) {
       // u_0 = r (the residual buffer is consumed as the cycle's start vector),
       // u_1 .. u_R in columns 0 .. R - 1 of V, Op output in column R + 1
-      double* W = w.V + size_t(R + 1) * n4;
-      auto op = [&](int j, const double* u, double* wout, const BasisDots* bq) -> hipError_t {
+      // operator output in float32 (W32): the float32 matvec's values exactly
+      ArnoldiOpT<float> op = [&](int j, const double* u, float* wout, const BasisDots* bq) -> hipError_t {
         return run_apply_matvec(c, sym_ap, sym_mv, na, u, w.m32, w.Z + size_t(j) * n4, wout, st, bq, c.dots);
       };
       CycleResult cr;
-      CHK_STATUS(cycle_dcgs2(c, op, LLG_FUSE_DOTS != 0, w.r, w.V, W, n4, rho * rho, R, eta, o.maxiter, res.iters,
-                             cr, st));
+      CHK_STATUS(cycle_dcgs2<float>(c, op, LLG_FUSE_DOTS != 0, w.r, w.V, w.W32, n4, rho * rho, R, eta, o.maxiter,
+                                    res.iters, cr, st));
       res.rel_prec = cr.gres / bnorm;
       if (cr.k == 0) break;
       CHK(lincomb(c, n4, cr.y, w.Z, n4, x, st));
@@ -991,13 +1030,16 @@ llg_status llg_ctx_create_cell(llg_ctx** out, int nx, int ny, int nz, double lx,
   if (hipMalloc(&c.spec, c.spec_bytes) != hipSuccess) return cleanup(LLG_ENOMEM, "spectral scratch allocation failed");
   if (hipMalloc(&c.partial, sizeof(double) * kRedBlocksMax * kMaxDots) != hipSuccess)
     return cleanup(LLG_ENOMEM, "reduction buffer allocation failed");
-  if (hipMalloc(&c.dots, sizeof(double) * 4 * kMaxDots) != hipSuccess)
+  if (hipMalloc(&c.dots, sizeof(double) * kDotsSlots * kMaxDots) != hipSuccess)
     return cleanup(LLG_ENOMEM, "reduction buffer allocation failed");
   c.dots2 = c.dots + kMaxDots;
   c.scal = c.dots + 2 * kMaxDots;
+  c.dots_b = c.dots + 4 * kMaxDots;
+  if (hipEventCreateWithFlags(&c.ev, hipEventDisableTiming) != hipSuccess)
+    return cleanup(LLG_EHIP, "event creation failed");
   if (hipMalloc(&c.tri, sizeof(double) * (kDcgsMaxCols * kDcgsMaxCols + kDcgsMaxCols)) != hipSuccess)
     return cleanup(LLG_ENOMEM, "reduction buffer allocation failed");
-  if (hipHostMalloc(reinterpret_cast<void**>(&c.hmirror), sizeof(double) * 2 * kMaxDots,
+  if (hipHostMalloc(reinterpret_cast<void**>(&c.hmirror), sizeof(double) * kDotsSlots * kMaxDots,
                     hipHostMallocMapped | hipHostMallocCoherent) != hipSuccess)
     return cleanup(LLG_ENOMEM, "pinned host buffer allocation failed");
   if (hipHostGetDevicePointer(reinterpret_cast<void**>(&c.hmirror_dev), c.hmirror, 0) != hipSuccess)
@@ -1052,6 +1094,7 @@ llg_status llg_ctx_destroy(llg_ctx* ctx) {
   if (c.tri) (void)hipFree(c.tri);
   if (c.host) (void)hipHostFree(c.host);
   if (c.hmirror) (void)hipHostFree(c.hmirror);
+  if (c.ev) (void)hipEventDestroy(c.ev);
   if (c.prof) profiler_delete(c.prof);
   delete ctx;
   return LLG_OK;

@@ -20,8 +20,11 @@ struct DcgsCoef {
   int j;
 };
 
-// Pass 1: out = [U_i.w (i <= j)].  j < kDcgsMaxCols.
+// Pass 1: out = [U_i.w (i <= j)].  j < kDcgsMaxCols.  w is float64, or the
+// float32 output of a float32 operator (its values convert exactly).
 hipError_t dcgs_dots(const Ctx& c, const double* u0, const double* U1, long long ld, int j, const double* w,
+                     long long n, double* out, hipStream_t st);
+hipError_t dcgs_dots(const Ctx& c, const double* u0, const double* U1, long long ld, int j, const float* w,
                      long long n, double* out, hipStream_t st);
 // Pass 2 (p = pass-1 output on the device): with gamma = T_{j+1}^{-1} [b; e_j],
 // b = T_j^{-T} p_{<j}, e_j = (p_j - a.b) / beta_j (computed on the device),
@@ -29,6 +32,8 @@ hipError_t dcgs_dots(const Ctx& c, const double* u0, const double* U1, long long
 // unew must not alias w or a basis column 0..j.
 hipError_t dcgs_update(const Ctx& c, const double* u0, const double* U1, long long ld, const DcgsCoef& cf,
                        const double* p, const double* w, double* unew, long long n, double* out, hipStream_t st);
+hipError_t dcgs_update(const Ctx& c, const double* u0, const double* U1, long long ld, const DcgsCoef& cf,
+                       const double* p, const float* w, double* unew, long long n, double* out, hipStream_t st);
 
 // out[i] = sum (or max) of the nb value-major partials of value i, i < nv
 hipError_t reduce_partials(const Ctx& c, int nb, int nv, double* out, bool is_max, hipStream_t st);

@@ -12,6 +12,7 @@
 //   A: h = V^T w;   B: w -= V h, s = V^T w;   C: w -= V s, ||w||^2.
 #include <cmath>
 #include <cstdint>
+#include <type_traits>
 #include <utility>
 
 #include "krylov.h"
@@ -40,6 +41,13 @@ __device__ __forceinline__ double2 ldnt(const double2* p) {
 __device__ __forceinline__ void stnt(double2* p, double2 v) {
   __builtin_nontemporal_store(v.x, &p->x);
   __builtin_nontemporal_store(v.y, &p->y);
+}
+// The operator output w of an Arnoldi step, as a pair of float64 values: a
+// float64 vector, or the float32 output of the precision form's operators
+// (whose float32 values convert to float64 exactly).
+__device__ __forceinline__ double2 ldw(const double2* p) { return ldnt(p); }
+__device__ __forceinline__ double2 ldw(const float2* p) {
+  return double2{double(__builtin_nontemporal_load(&p->x)), double(__builtin_nontemporal_load(&p->y))};
 }
 
 // Reduce acc[0..nv) over the block and store partial[i * gridDim.x + blockIdx.x]
@@ -236,18 +244,19 @@ __device__ __forceinline__ void dcgs_block_store(const double (&acc)[NV], double
   }
 }
 
-// Pass 1: out = [U_i.w (i <= J)], value-major partials.
-template <int J>
+// Pass 1: out = [U_i.w (i <= J)], value-major partials.  W2: double2 or
+// float2 (w stored in float32).
+template <int J, typename W2>
 __global__ __launch_bounds__(kDcgsThreads) void k_dcgs_dots(const double2* __restrict__ u0,
                                                           const double2* __restrict__ U1, long long ld2,
-                                                          const double2* __restrict__ w, long long n2,
+                                                          const W2* __restrict__ w, long long n2,
                                                           double* __restrict__ partial) {
   double acc[J + 1];
 #pragma unroll
   for (int i = 0; i <= J; ++i) acc[i] = 0.0;
   const long long stride = (long long)gridDim.x * blockDim.x;
   for (long long e = (long long)blockIdx.x * blockDim.x + threadIdx.x; e < n2; e += stride) {
-    const double2 ww = ldnt(w + e);
+    const double2 ww = ldw(w + e);
     double2 q[J + 1];
     q[0] = ldnt(u0 + e);
 #pragma unroll
@@ -286,11 +295,11 @@ __global__ __launch_bounds__(64) void k_dcgs_coef(DcgsCoef cf, const double* __r
 
 // Pass 2: unew = (w - U gamma) / beta_j, and, for the next step,
 // out = [U_i.unew (i <= J), unew.unew], value-major partials.
-template <int J>
+template <int J, typename W2>
 __global__ __launch_bounds__(kDcgsThreads) void k_dcgs_update(const double2* __restrict__ u0,
                                                             const double2* __restrict__ U1, long long ld2,
                                                             const double* __restrict__ gamma, double inv_beta,
-                                                            const double2* __restrict__ w,
+                                                            const W2* __restrict__ w,
                                                             double2* __restrict__ unew, long long n2,
                                                             double* __restrict__ partial) {
   double gm[J + 1];
@@ -301,7 +310,7 @@ __global__ __launch_bounds__(kDcgsThreads) void k_dcgs_update(const double2* __r
   for (int i = 0; i < J + 2; ++i) acc[i] = 0.0;
   const long long stride = (long long)gridDim.x * blockDim.x;
   for (long long e = (long long)blockIdx.x * blockDim.x + threadIdx.x; e < n2; e += stride) {
-    double2 se = ldnt(w + e);
+    double2 se = ldw(w + e);
     double2 q[J + 1];
     q[0] = ldnt(u0 + e);
 #pragma unroll
@@ -419,7 +428,7 @@ hipError_t reduce_partials_n(const Ctx& c, int nb, int nv, double* out, hipStrea
   ProfScope ps(c.prof, st, KK_REDUCE, 8.0 * nb * nv);
   // results landing in the Arnoldi slots are mirrored into host memory, so
   // the host reads them after a stream synchronize without a copy
-  double* hout = (out >= c.dots && out < c.dots + 2 * kMaxDots) ? c.hmirror_dev + (out - c.dots) : nullptr;
+  double* hout = (out >= c.dots && out < c.dots + kDotsSlots * kMaxDots) ? c.hmirror_dev + (out - c.dots) : nullptr;
   hipLaunchKernelGGL(k_reduce_vmajor, dim3(nv), dim3(1024), 0, st, c.partial, nb, out, hout);
   return hipGetLastError();
 }
@@ -492,20 +501,24 @@ hipError_t cgs_update_norm(const Ctx& c, const double* V, long long ld, int nv, 
 }
 
 
-template <int J>
-static void dd_t(const Ctx& c, const double* u0, const double* U1, long long ld, const double* w, long long n,
+// float2 / double2 view of a float32 / float64 operator output
+template <typename TW>
+using pair_of = typename std::conditional<std::is_same<TW, float>::value, float2, double2>::type;
+
+template <int J, typename TW>
+static void dd_t(const Ctx& c, const double* u0, const double* U1, long long ld, const TW* w, long long n,
                  hipStream_t st) {
-  hipLaunchKernelGGL((k_dcgs_dots<J>), dim3(red_blocks(n / 2)), dim3(kDcgsThreads), 0, st,
+  hipLaunchKernelGGL((k_dcgs_dots<J, pair_of<TW>>), dim3(red_blocks(n / 2)), dim3(kDcgsThreads), 0, st,
                      reinterpret_cast<const double2*>(u0), reinterpret_cast<const double2*>(U1), ld / 2,
-                     reinterpret_cast<const double2*>(w), n / 2, c.partial);
+                     reinterpret_cast<const pair_of<TW>*>(w), n / 2, c.partial);
 }
 
-template <int J>
+template <int J, typename TW>
 static void du_t(const Ctx& c, const double* u0, const double* U1, long long ld, const double* gamma,
-                 double inv_beta, const double* w, double* unew, long long n, hipStream_t st) {
-  hipLaunchKernelGGL((k_dcgs_update<J>), dim3(red_blocks(n / 2)), dim3(kDcgsThreads), kDcgsUpdateLds, st,
-                     reinterpret_cast<const double2*>(u0), reinterpret_cast<const double2*>(U1), ld / 2, gamma,
-                     inv_beta, reinterpret_cast<const double2*>(w), reinterpret_cast<double2*>(unew), n / 2,
+                 double inv_beta, const TW* w, double* unew, long long n, hipStream_t st) {
+  hipLaunchKernelGGL((k_dcgs_update<J, pair_of<TW>>), dim3(red_blocks(n / 2)), dim3(kDcgsThreads), kDcgsUpdateLds,
+                     st, reinterpret_cast<const double2*>(u0), reinterpret_cast<const double2*>(U1), ld / 2, gamma,
+                     inv_beta, reinterpret_cast<const pair_of<TW>*>(w), reinterpret_cast<double2*>(unew), n / 2,
                      c.partial);
 }
 
@@ -529,18 +542,29 @@ struct UpdF {
   static void go(A&&... a) { du_t<J>(std::forward<A>(a)...); }
 };
 
-hipError_t dcgs_dots(const Ctx& c, const double* u0, const double* U1, long long ld, int j, const double* w,
-                     long long n, double* out, hipStream_t st) {
+template <typename TW>
+static hipError_t dcgs_dots_t(const Ctx& c, const double* u0, const double* U1, long long ld, int j, const TW* w,
+                              long long n, double* out, hipStream_t st) {
   if (j < 0 || j >= kDcgsMaxCols) return hipErrorInvalidValue;
   {
-    ProfScope ps(c.prof, st, KK_CGS_DOTS, 8.0 * n * (j + 2));
+    ProfScope ps(c.prof, st, KK_CGS_DOTS, double(n) * (8.0 * (j + 1) + sizeof(TW)));
     JDispatch<DotsF>::run(j, c, u0, U1, ld, w, n, st);
   }
   return reduce_partials_n(c, red_blocks(n / 2), j + 1, out, st);
 }
+hipError_t dcgs_dots(const Ctx& c, const double* u0, const double* U1, long long ld, int j, const double* w,
+                     long long n, double* out, hipStream_t st) {
+  return dcgs_dots_t(c, u0, U1, ld, j, w, n, out, st);
+}
+hipError_t dcgs_dots(const Ctx& c, const double* u0, const double* U1, long long ld, int j, const float* w,
+                     long long n, double* out, hipStream_t st) {
+  return dcgs_dots_t(c, u0, U1, ld, j, w, n, out, st);
+}
 
-hipError_t dcgs_update(const Ctx& c, const double* u0, const double* U1, long long ld, const DcgsCoef& cf,
-                       const double* p, const double* w, double* unew, long long n, double* out, hipStream_t st) {
+template <typename TW>
+static hipError_t dcgs_update_t(const Ctx& c, const double* u0, const double* U1, long long ld, const DcgsCoef& cf,
+                                const double* p, const TW* w, double* unew, long long n, double* out,
+                                hipStream_t st) {
   if (cf.j < 0 || cf.j >= kDcgsMaxCols) return hipErrorInvalidValue;
   double* gamma = c.tri + kDcgsMaxCols * kDcgsMaxCols;
   {
@@ -548,10 +572,19 @@ hipError_t dcgs_update(const Ctx& c, const double* u0, const double* U1, long lo
     hipLaunchKernelGGL(k_dcgs_coef, dim3(1), dim3(64), 0, st, cf, p, c.tri, gamma);
   }
   {
-    ProfScope ps(c.prof, st, KK_CGS_UPDATE_DOTS, 8.0 * n * (cf.j + 3));
+    // j + 1 directions read, w read, u_new written
+    ProfScope ps(c.prof, st, KK_CGS_UPDATE_DOTS, double(n) * (8.0 * (cf.j + 2) + sizeof(TW)));
     JDispatch<UpdF>::run(cf.j, c, u0, U1, ld, gamma, cf.inv_beta, w, unew, n, st);
   }
   return reduce_partials_n(c, red_blocks(n / 2), cf.j + 2, out, st);
+}
+hipError_t dcgs_update(const Ctx& c, const double* u0, const double* U1, long long ld, const DcgsCoef& cf,
+                       const double* p, const double* w, double* unew, long long n, double* out, hipStream_t st) {
+  return dcgs_update_t(c, u0, U1, ld, cf, p, w, unew, n, out, st);
+}
+hipError_t dcgs_update(const Ctx& c, const double* u0, const double* U1, long long ld, const DcgsCoef& cf,
+                       const double* p, const float* w, double* unew, long long n, double* out, hipStream_t st) {
+  return dcgs_update_t(c, u0, U1, ld, cf, p, w, unew, n, out, st);
 }
 
 hipError_t scale_invnorm(const Ctx& c, double* y, const double* x, const double* nrm2, long long n, hipStream_t st) {

@@ -27,6 +27,11 @@ constexpr int kRedBlocksMax = 65536;  // partial buffer rows (large dot passes)
 constexpr int kRedThreads = 256;
 constexpr int kMaxDots = 64;
 constexpr int kDcgsMaxCols = 32;  // delayed-CGS2 basis columns (restart <= 31)
+constexpr int kDotsSlots = 5;     // kMaxDots-sized slots of Ctx::dots (see Ctx)
+// Grids of at most this many nodes launch the next Arnoldi step's operator
+// before the host round trip of the current step (its work is short next to
+// the round trip, and it is discarded when the cycle ends).
+constexpr long long kSpeculateMaxNodes = 1 << 20;
 
 // Kernel kinds known to the event profiler.
 enum KernelKind : int {
@@ -59,12 +64,17 @@ struct Ctx {
   void* spec = nullptr;  // spectral scratch (complex double capacity)
   size_t spec_bytes = 0;
   double* partial = nullptr;  // kRedBlocksMax x kMaxDots reduction partials
-  double* dots = nullptr;     // kMaxDots reduced values (device)
-  double* dots2 = nullptr;    // second set (CGS2 re-orthogonalization)
-  double* scal = nullptr;     // small device scalars
+  // Reduced values (device), kDotsSlots x kMaxDots doubles: dots (slot 0),
+  // dots2 (CGS2 re-orthogonalization), scal (two slots of small scalars),
+  // dots_b (the second Arnoldi pass-1 slot, for the step launched ahead).
+  double* dots = nullptr;
+  double* dots2 = nullptr;
+  double* scal = nullptr;
+  double* dots_b = nullptr;
   double* host = nullptr;     // pinned host mirror (4 * kMaxDots doubles)
-  double* hmirror = nullptr;      // pinned, device-mapped host copy of dots and dots2
+  double* hmirror = nullptr;      // pinned, device-mapped host copy of the reduced values (same layout)
   double* hmirror_dev = nullptr;  // its device address
+  hipEvent_t ev = nullptr;    // marks the end of an Arnoldi step's second pass
   double* tri = nullptr;      // delayed-CGS2 T^{-1} (kDcgsMaxCols^2, column-major) + kDcgsMaxCols coefficients
 };
 
@@ -99,6 +109,11 @@ hipError_t run_pipeline(const Ctx& c, int pro, int epi, const SymArgs& sym, cons
 // Arnoldi inner products dots_out[q] = u_q . w, q < bd->nv (device).
 hipError_t run_apply_matvec(const Ctx& c, const SymArgs& sym_ap, const SymArgs& sym_mv, const NodalArgs& na,
                             const double* v, const float* m32, float* z, double* w, hipStream_t st,
+                            const BasisDots* bd = nullptr, double* dots_out = nullptr);
+// The same with a float32 w (the flexible cycle's operator output: the
+// float32 matvec's values, read exactly by the Arnoldi pass).
+hipError_t run_apply_matvec(const Ctx& c, const SymArgs& sym_ap, const SymArgs& sym_mv, const NodalArgs& na,
+                            const double* v, const float* m32, float* z, float* w, hipStream_t st,
                             const BasisDots* bd = nullptr, double* dots_out = nullptr);
 
 // Lower-order field pipeline (field.hip, float64): forward DFTs of three

@@ -153,6 +153,7 @@ struct BasisDots {
   long long ld = 0;
   int nv = 0;
   double* partial = nullptr;
+  double* out = nullptr;  // when set, the reduced products go here instead of the caller's default
 };
 
 }  // namespace llg

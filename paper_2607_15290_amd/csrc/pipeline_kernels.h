@@ -505,9 +505,8 @@ template <typename T, typename TIn, typename TOut, int NH, int EPI, bool DOTS = 
 __global__ __launch_bounds__(192) void k_xinv(PipeIO<T, TIn, TOut> io, const cx<T>* __restrict__ spec,
                                               SpecGeom g, NodalArgs na, const cx<T>* __restrict__ twx,
                                               BasisDots bd) {
-  static_assert(!DOTS || ((EPI == EPI_MATVEC || EPI == EPI_FUSED || EPI == EPI_JT_RIGHT) &&
-                          std::is_same<TOut, double>::value),
-                "dots: float64 Krylov output of a matvec or fused pass");
+  static_assert(!DOTS || EPI == EPI_MATVEC || EPI == EPI_FUSED || EPI == EPI_JT_RIGHT,
+                "dots: Krylov output of a matvec or fused pass");
   using C = XCfg<T, NH>;
   __shared__ cx<T> lds[3 * C::LX * C::SL];
   const int tid = threadIdx.x;

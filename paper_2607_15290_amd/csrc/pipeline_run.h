@@ -10,22 +10,20 @@ namespace llg {
 
 // Which (prologue, epilogue) modes exist for a type combination.  The mixed
 // combinations serve only the precision form: float32 apply reading float64
-// Krylov vectors, float32 matvec writing float64 Krylov vectors, and float32
-// apply / fused M^{-1} A between float64 Krylov vectors.
+// Krylov vectors (and the fused M^{-1} A of the left variant, whose float32
+// output goes to the Arnoldi pass), float32 matvec writing float64 Krylov
+// vectors, and float32 apply / fused M^{-1} A between float64 Krylov vectors.
 template <typename T, typename TIn, typename TOut>
 constexpr bool has_pro(int pro) {
   if constexpr (std::is_same<T, TIn>::value && std::is_same<T, TOut>::value) return true;
-  else if constexpr (std::is_same<TIn, double>::value && std::is_same<TOut, double>::value)
-    return pro == PRO_COPY3 || pro == PRO_SMINUS;
+  else if constexpr (std::is_same<TIn, double>::value) return pro == PRO_COPY3 || pro == PRO_SMINUS;
   else return pro == PRO_COPY3;
 }
 template <typename T, typename TIn, typename TOut>
 constexpr bool has_epi(int epi) {
   if constexpr (std::is_same<T, TIn>::value && std::is_same<T, TOut>::value)
     return (epi != EPI_ENERGY && epi != EPI_JT_RIGHT) || std::is_same<T, double>::value;
-  else if constexpr (std::is_same<TIn, double>::value && std::is_same<TOut, double>::value)
-    return epi == EPI_APPLY || epi == EPI_FUSED;
-  else if constexpr (std::is_same<TIn, double>::value) return epi == EPI_APPLY;
+  else if constexpr (std::is_same<TIn, double>::value) return epi == EPI_APPLY || epi == EPI_FUSED;
   else return epi == EPI_MATVEC;
 }
 
@@ -129,8 +127,9 @@ hipError_t run_nh(const Ctx& c, int pro, int epi, const SymArgs& sym, const Noda
     if ((e = launch_axis<T>(c, 1, 1, sym, spec, st)) != hipSuccess) return e;
   }
   if (bd && bd->nv > 0) {
+    if (bd->out) dots_out = bd->out;
     // the Arnoldi inner products ride on the fused preconditioned passes only
-    if constexpr (std::is_same<TOut, double>::value && has_epi<T, TIn, TOut>(EPI_FUSED)) {
+    if constexpr (has_epi<T, TIn, TOut>(EPI_FUSED)) {
       if (epi == EPI_FUSED) return launch_xinv_dots<T, TIn, TOut, NH, EPI_FUSED>(c, na, io, *bd, dots_out, st);
       if constexpr (has_epi<T, TIn, TOut>(EPI_JT_RIGHT)) {
         if (epi == EPI_JT_RIGHT)
@@ -174,13 +173,16 @@ hipError_t run_axes(const Ctx& c, const SymArgs& sym, hipStream_t st) {
 // One inner iteration's operator of the precision form: z = M^{-1} v in
 // float32 (z kept as the flexible basis vector) and w = A z in float32 with a
 // float64 result; the junction of the two pipelines is the fused k_xmid pass.
-template <int NH>
+// The matvec's output w is float64 (a Krylov vector) or float32 (the Arnoldi
+// operator output of the precision form, whose float32 values convert to
+// float64 exactly when the Arnoldi pass reads them).
+template <int NH, typename TW>
 hipError_t run_apply_matvec_nh(const Ctx& c, const SymArgs& sym_ap, const SymArgs& sym_mv, const NodalArgs& na,
-                               const double* v, const float* m32, float* z, double* w, const BasisDots* bd,
+                               const double* v, const float* m32, float* z, TW* w, const BasisDots* bd,
                                double* dots_out, hipStream_t st) {
   using C = XCfg<float, NH>;
   PipeIO<float, double, float> io_ap{v, m32, z, c.ng, nullptr, nullptr};
-  PipeIO<float, float, double> io_mv{z, m32, w, c.ng, nullptr, nullptr};
+  PipeIO<float, float, TW> io_mv{z, m32, w, c.ng, nullptr, nullptr};
   launch_xfwd<float, double, float, NH, PRO_COPY3>(c, na, io_ap, st);
   hipError_t e;
   if ((e = run_axes<float>(c, sym_ap, st)) != hipSuccess) return e;
@@ -195,11 +197,12 @@ hipError_t run_apply_matvec_nh(const Ctx& c, const SymArgs& sym_ap, const SymArg
   }
   if ((e = run_axes<float>(c, sym_mv, st)) != hipSuccess) return e;
   if (!bd || bd->nv == 0) {
-    launch_xinv<float, float, double, NH, EPI_MATVEC>(c, na, io_mv, st);
+    launch_xinv<float, float, TW, NH, EPI_MATVEC>(c, na, io_mv, st);
     return hipGetLastError();
   }
+  if (bd->out) dots_out = bd->out;
   // matvec with the Arnoldi inner products of w (out[q] = u_q . w, q < nv)
-  return launch_xinv_dots<float, float, double, NH, EPI_MATVEC>(c, na, io_mv, *bd, dots_out, st);
+  return launch_xinv_dots<float, float, TW, NH, EPI_MATVEC>(c, na, io_mv, *bd, dots_out, st);
 }
 
 template <typename T, typename TIn, typename TOut>
