@@ -167,7 +167,7 @@ def roofline_of(prof, footprint_bytes, traffic_kernel=None):
              kernel=dom_name, avg_launch_us=round(1e3 * dom["total_ms"] / dom["launches"], 2),
              launches=dom["launches"], bytes_per_launch=round(bpl))
     if footprint_bytes < INFINITY_CACHE_BYTES:
-        r["note"] = (f"working set {footprint_bytes / 2**20:.0f} MiB fits the 256 MiB Infinity Cache: the rate "
+        r["note"] = (f"working set {footprint_bytes / 2**20:.3g} MiB fits the 256 MiB Infinity Cache: the rate "
                      f"is cache/latency bound, not an HBM figure; quote applies/s and solves/s")
     return r
 

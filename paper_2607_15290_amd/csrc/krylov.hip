@@ -216,15 +216,19 @@ __global__ __launch_bounds__(kRedThreads) void k_update_norm(const double* __res
 // elements' loads per thread, whose extra streams in flight lower the DRAM
 // efficiency).
 constexpr int kDcgsThreads = 512;
-// Unused dynamic LDS of the update pass: it caps the pass at two 512-thread
-// blocks per CU (16 waves).  Fewer concurrent vector streams keep the DRAM
-// pages of the j + 3 streams open longer: measured 3% faster than the
-// uncapped pass at 256^3 (one block per CU is 40% slower; the read-only
-// pass 1 gains nothing from the cap).
+// Unused dynamic LDS of the update pass caps the blocks per CU.  With a
+// float64 operator output w it caps the pass at two 512-thread blocks per CU
+// (16 waves): fewer concurrent vector streams keep the DRAM pages of the
+// j + 3 streams open longer, measured 3% faster than the uncapped pass at
+// 256^3 (one block per CU is 40% slower; the read-only pass 1 gains nothing
+// from a cap).  With the float32 w of the precision form three blocks per CU
+// are fastest (421 us against 433 us with two and 427 us uncapped, 256^3).
 #ifndef LLG_DCGS_UPDATE_LDS
 #define LLG_DCGS_UPDATE_LDS 65536
 #endif
-constexpr unsigned kDcgsUpdateLds = LLG_DCGS_UPDATE_LDS;
+#ifndef LLG_DCGS_UPDATE_LDS_F32W
+#define LLG_DCGS_UPDATE_LDS_F32W 40960
+#endif
 
 template <int NV>
 __device__ __forceinline__ void dcgs_block_store(const double (&acc)[NV], double* __restrict__ partial) {
@@ -516,8 +520,8 @@ static void dd_t(const Ctx& c, const double* u0, const double* U1, long long ld,
 template <int J, typename TW>
 static void du_t(const Ctx& c, const double* u0, const double* U1, long long ld, const double* gamma,
                  double inv_beta, const TW* w, double* unew, long long n, hipStream_t st) {
-  hipLaunchKernelGGL((k_dcgs_update<J, pair_of<TW>>), dim3(red_blocks(n / 2)), dim3(kDcgsThreads), kDcgsUpdateLds,
-                     st, reinterpret_cast<const double2*>(u0), reinterpret_cast<const double2*>(U1), ld / 2, gamma,
+  constexpr unsigned lds = std::is_same<TW, float>::value ? LLG_DCGS_UPDATE_LDS_F32W : LLG_DCGS_UPDATE_LDS;
+  hipLaunchKernelGGL((k_dcgs_update<J, pair_of<TW>>), dim3(red_blocks(n / 2)), dim3(kDcgsThreads), lds, st, reinterpret_cast<const double2*>(u0), reinterpret_cast<const double2*>(U1), ld / 2, gamma,
                      inv_beta, reinterpret_cast<const pair_of<TW>*>(w), reinterpret_cast<double2*>(unew), n / 2,
                      c.partial);
 }
