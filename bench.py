@@ -117,28 +117,33 @@ def set_oracle_threads(n):
 # ---------------------------------------------------------------------------
 # timing helpers
 # ---------------------------------------------------------------------------
-def profiled_timing(P, ctx, run, log_label):
-    """Three passes of ``run()`` from the same state: an untimed warm-up, an
-    untimed pass with every kernel bracketed by HIP events (per-kind table),
-    and the timed pass with events around the dominant kind only.  Returns
-    (seconds of the timed pass, its result, per-kind table, dominant-kind
-    record of the timed pass)."""
+def profiled_timing(P, ctx, runner, log_label):
+    """Three passes of a StepsRunner from the same initial state (each after
+    its untimed prepare(): m0 and the W warm-up steps): an untimed warm-up
+    pass, an untimed pass with every kernel of the K steps bracketed by HIP
+    events (per-kind table), and the timed pass of the K steps with events
+    around the dominant kind only.  Returns (seconds of the timed pass, its
+    result, per-kind table, dominant-kind record of the timed pass)."""
     import torch
     log(f"{log_label}: untimed warm-up pass")
-    run()
+    runner.prepare()
+    runner.run()
     log(f"{log_label}: untimed pass with every kernel profiled")
+    runner.prepare()
+    torch.cuda.synchronize()
     P.llg_profile_select(ctx, None)
     P.llg_profile_enable(ctx, True)
-    run()
+    runner.run()
     P.llg_profile_enable(ctx, False)
     prof_all = P.llg_profile_read(ctx)
     dom_kind = dominant_kind(prof_all)
     log(f"{log_label}: timed pass (events around {dom_kind} only)")
+    runner.prepare()
     P.llg_profile_select(ctx, [dom_kind])
     torch.cuda.synchronize()
     P.llg_profile_enable(ctx, True)
     t0 = time.perf_counter()
-    out = run()
+    out = runner.run()
     torch.cuda.synchronize()
     t = time.perf_counter() - t0
     P.llg_profile_enable(ctx, False)
@@ -239,32 +244,64 @@ def op_bandwidth(P, ctx, prm, m0_dev, reps):
     return out
 
 
-def steps_runner(P, ctx, prm, m0_dev, spec, prec, warmup, steps, inner_rtol, orth, picard_norm="midpoint"):
-    """A callable that runs ``warmup`` then ``steps`` steps of the workload's
-    scheme from m0 and returns the per-step statistics of the last ``steps``."""
+class StepsRunner:
+    """The workload's scheme from m0.  prepare() restarts from m0 and runs the
+    W untimed warm-up steps; run() then runs the K steps that are timed and
+    returns their statistics."""
+
+    def __init__(self, P, ctx, prm, m0_dev, spec, prec, warmup, steps, inner_rtol, orth, picard_norm="midpoint"):
+        self.P, self.ctx, self.prm, self.m0, self.spec = P, ctx, prm, m0_dev, spec
+        self.prec, self.warmup, self.steps = prec, warmup, steps
+        self.inner_rtol, self.orth, self.picard_norm = inner_rtol, orth, picard_norm
+
+    def _step(self):
+        P, spec = self.P, self.spec
+        if spec["scheme"] == "midpoint":
+            return P.llg_step_midpoint(self.ctx, self.prm, self.m, self.vh, self.lam, picard_tol=spec["picard_tol"],
+                                       picard_max=spec["picard_max"], restart=spec["restart"], rtol=spec["rtol"],
+                                       prec=self.prec, inner_rtol=self.inner_rtol, max_outer=20, orth=self.orth,
+                                       picard_norm=self.picard_norm)
+        if spec["wid"] == 1:
+            self.m.copy_(self.m0)  # the workload is one step: every timed step repeats it
+        return P.llg_step_euler(self.ctx, self.prm, self.m, restart=spec["restart"], rtol=spec["rtol"],
+                                prec=self.prec, inner_rtol=self.inner_rtol, max_outer=20, orth=self.orth)
+
+    def prepare(self):
+        import torch
+        self.m = self.m0.clone()
+        self.vh = torch.zeros_like(self.m)
+        self.lam = torch.zeros((1,) + tuple(self.m.shape[1:]), dtype=torch.float64, device=self.ctx.device)
+        for _ in range(self.warmup):
+            self._step()
+
+    def run(self):
+        return [self._step() for _ in range(self.steps)]
+
+
+class CallRunner:
+    """A whole timed unit with no warm-up part (the differentiation
+    workload's trajectory), in the StepsRunner interface."""
+
+    def __init__(self, fn):
+        self.fn = fn
+
+    def prepare(self):
+        pass
+
+    def run(self):
+        return self.fn()
+
+
+def timed_steps(runner):
+    """prepare() untimed, then (seconds, statistics) of run() bracketed by
+    device synchronizations."""
     import torch
-
-    def run():
-        m = m0_dev.clone()
-        vh = torch.zeros_like(m)
-        lam = torch.zeros((1,) + tuple(m.shape[1:]), dtype=torch.float64, device=ctx.device)
-        out = []
-        for i in range(warmup + steps):
-            if spec["scheme"] == "midpoint":
-                st = P.llg_step_midpoint(ctx, prm, m, vh, lam, picard_tol=spec["picard_tol"],
-                                         picard_max=spec["picard_max"], restart=spec["restart"], rtol=spec["rtol"],
-                                         prec=prec, inner_rtol=inner_rtol, max_outer=20, orth=orth,
-                                         picard_norm=picard_norm)
-            else:
-                if spec["wid"] == 1:
-                    m.copy_(m0_dev)  # the workload is one step: every timed step repeats it
-                st = P.llg_step_euler(ctx, prm, m, restart=spec["restart"], rtol=spec["rtol"], prec=prec,
-                                      inner_rtol=inner_rtol, max_outer=20, orth=orth)
-            if i >= warmup:
-                out.append(st)
-        return out
-
-    return run
+    runner.prepare()
+    torch.cuda.synchronize()
+    t0 = time.perf_counter()
+    out = runner.run()
+    torch.cuda.synchronize()
+    return time.perf_counter() - t0, out
 
 
 def summarize(stats, t, steps):
@@ -476,35 +513,27 @@ def run_headline(args, P, W, torch):
     log("operator bandwidth")
     ops = op_bandwidth(P, ctx, prm, m0_dev, args.op_reps)
 
-    run32 = steps_runner(P, ctx, prm, m0_dev, spec, "fp32_ir", args.warmup, steps, args.inner_rtol, args.orth)
+    run32 = StepsRunner(P, ctx, prm, m0_dev, spec, "fp32_ir", args.warmup, steps, args.inner_rtol, args.orth)
     t32, st32, prof_all, prof = profiled_timing(P, ctx, run32, "FP32-IR midpoint steps")
     log_steps("fp32_ir", st32)
     fp32 = summarize(st32, t32, steps)
     res = {}
     if not args.no_fp64:
         log("FP64 midpoint steps (one untimed step first to load its kernels)")
-        steps_runner(P, ctx, prm, m0_dev, spec, "fp64", 0, 1, args.inner_rtol, args.orth)()
-        torch.cuda.synchronize()
-        t0 = time.perf_counter()
-        st64 = steps_runner(P, ctx, prm, m0_dev, spec, "fp64", args.warmup, steps, args.inner_rtol, args.orth)()
-        torch.cuda.synchronize()
-        res["fp64"] = summarize(st64, time.perf_counter() - t0, steps)
+        timed_steps(StepsRunner(P, ctx, prm, m0_dev, spec, "fp64", 0, 1, args.inner_rtol, args.orth))
+        t64, st64 = timed_steps(StepsRunner(P, ctx, prm, m0_dev, spec, "fp64", args.warmup, steps, args.inner_rtol,
+                                            args.orth))
+        res["fp64"] = summarize(st64, t64, steps)
     if not args.no_variant:
         log("FP32-IR variant with left-preconditioned inner GMRES (one fused float32 pipeline per iteration)")
-        steps_runner(P, ctx, prm, m0_dev, spec, "fp32_ir_left", 0, 1, args.inner_rtol, args.orth)()
-        torch.cuda.synchronize()
-        t0 = time.perf_counter()
-        stl = steps_runner(P, ctx, prm, m0_dev, spec, "fp32_ir_left", args.warmup, steps, args.inner_rtol,
-                           args.orth)()
-        torch.cuda.synchronize()
-        res["fp32_ir_left"] = summarize(stl, time.perf_counter() - t0, steps)
+        timed_steps(StepsRunner(P, ctx, prm, m0_dev, spec, "fp32_ir_left", 0, 1, args.inner_rtol, args.orth))
+        tl, stl = timed_steps(StepsRunner(P, ctx, prm, m0_dev, spec, "fp32_ir_left", args.warmup, steps,
+                                          args.inner_rtol, args.orth))
+        res["fp32_ir_left"] = summarize(stl, tl, steps)
         log("FP32-IR with the velocity-based Picard test (length-error trade)")
-        torch.cuda.synchronize()
-        t0 = time.perf_counter()
-        stv = steps_runner(P, ctx, prm, m0_dev, spec, "fp32_ir", args.warmup, steps, args.inner_rtol, args.orth,
-                           picard_norm="velocity")()
-        torch.cuda.synchronize()
-        res["fp32_ir_velocity_picard"] = summarize(stv, time.perf_counter() - t0, steps)
+        tv, stv = timed_steps(StepsRunner(P, ctx, prm, m0_dev, spec, "fp32_ir", args.warmup, steps, args.inner_rtol,
+                                          args.orth, picard_norm="velocity"))
+        res["fp32_ir_velocity_picard"] = summarize(stv, tv, steps)
         log_steps("fp32_ir velocity-Picard", stv)
     comparison = None
     if not args.no_comparison:
@@ -565,19 +594,16 @@ def run_solver_workload(args, P, W, torch, wid):
     ops = op_bandwidth(P, ctx, prm, m0_dev, args.op_reps)
     precs = list(spec["prec"])
     head = precs[0]
-    runh = steps_runner(P, ctx, prm, m0_dev, spec, head, args.warmup, steps, args.inner_rtol, args.orth)
+    runh = StepsRunner(P, ctx, prm, m0_dev, spec, head, args.warmup, steps, args.inner_rtol, args.orth)
     th, sth, prof_all, prof = profiled_timing(P, ctx, runh, f"{head} steps")
     log_steps(head, sth)
     summ = {head: summarize(sth, th, steps)}
     for prec in precs[1:]:
         log(f"{prec} steps")
-        runp = steps_runner(P, ctx, prm, m0_dev, spec, prec, args.warmup, steps, args.inner_rtol, args.orth)
-        runp()
-        torch.cuda.synchronize()
-        t0 = time.perf_counter()
-        stp = runp()
-        torch.cuda.synchronize()
-        summ[prec] = summarize(stp, time.perf_counter() - t0, steps)
+        runp = StepsRunner(P, ctx, prm, m0_dev, spec, prec, args.warmup, steps, args.inner_rtol, args.orth)
+        timed_steps(runp)
+        tp, stp = timed_steps(runp)
+        summ[prec] = summarize(stp, tp, steps)
     pp = {}
     if not args.no_paper_protocol:
         log("paper protocol (median of 3 after 1 warm-up)")
@@ -672,7 +698,7 @@ def run_adjoint_workload(args, P, W, torch):
         times["fwd"], times["bwd"] = t1 - t0, t2 - t1
         return float(loss.item()), float(m.grad.norm().item()), float(hf.grad.norm().item()), list(hu.grad.tolist())
 
-    t, out, prof_all, prof = profiled_timing(P, ctx, run, "trajectory forward + backward")
+    t, out, prof_all, prof = profiled_timing(P, ctx, CallRunner(run), "trajectory forward + backward")
     loss, gm, ghf, ghu = out
     log("one adjoint step: right-preconditioned one-pipeline solve vs the left two-pipeline form")
     adj = adjoint_step_comparison(P, ctx, spec, prm, m0, hf0, torch)

@@ -109,6 +109,14 @@ typedef struct {
                         ||v^p - v^{p-1}|| <= tol ||v^p|| */
   int transpose;     /* gmres_solve only: 1 solves A^T x = b, left-preconditioned
                         by M^T (float64; the steppers ignore it) */
+  int fuse_update;   /* delayed CGS2 (orth = 0): 0 = form each new basis
+                        direction inside the next operator's first x pass
+                        (one streaming pass fewer per iteration) on grids
+                        whose x pass has at least 4096 blocks (256^3), else
+                        in its own pass (default); 1 = fused on every grid;
+                        -1 = never.  Steps with more than 8 directions always
+                        use their own pass.  Results agree to rounding (the
+                        inner products are summed in another order) */
 } llg_solver_opts;
 
 typedef struct {

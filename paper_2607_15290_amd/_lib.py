@@ -28,7 +28,8 @@ class LLGSolverOpts(ctypes.Structure):
     _fields_ = [("restart", ctypes.c_int), ("maxiter", ctypes.c_int), ("max_outer", ctypes.c_int),
                 ("use_x0", ctypes.c_int), ("rtol", ctypes.c_double), ("inner_rtol", ctypes.c_double),
                 ("prec", ctypes.c_int), ("precond", ctypes.c_int), ("orth", ctypes.c_int),
-                ("picard_norm", ctypes.c_int), ("transpose", ctypes.c_int)]
+                ("picard_norm", ctypes.c_int), ("transpose", ctypes.c_int),
+                ("fuse_update", ctypes.c_int)]
 
 
 class LLGSolverStats(ctypes.Structure):

@@ -16,7 +16,7 @@ HERE = os.path.dirname(os.path.abspath(__file__))
 CSRC = os.path.join(HERE, "csrc")
 BUILD = os.path.join(HERE, "_build")
 LIB = os.path.join(HERE, "libllg.so")
-SOURCES = ["pipeline_f64.hip", "pipeline_f32.hip", "axis.hip", "field.hip", "krylov.hip", "nodal.hip", "noalloc.hip", "profiler.cpp",
+SOURCES = ["pipeline_f64.hip", "pipeline_f32.hip", "axis.hip", "field.hip", "krylov.hip", "nodal.hip", "noalloc.hip", "xfwd_upd.hip", "profiler.cpp",
            "capi.cpp"]
 ARCH = "gfx950"
 # packed fp32 ops are disabled for every device compile; hipcc's host pass

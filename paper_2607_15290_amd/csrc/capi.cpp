@@ -97,6 +97,7 @@ llg_status check_opts(const llg_solver_opts* o) {
   if (o->orth == 0 && o->restart > 31) return fail(LLG_EARG, "delayed CGS2 supports restart <= 31");
   if (o->picard_norm != 0 && o->picard_norm != 1) return fail(LLG_EARG, "picard_norm must be 0 or 1");
   if (o->transpose != 0 && o->transpose != 1) return fail(LLG_EARG, "transpose must be 0 or 1");
+  if (o->fuse_update < -1 || o->fuse_update > 1) return fail(LLG_EARG, "fuse_update must be -1, 0 or 1");
   if (o->prec != LLG_FP64) {
     if (o->max_outer < 1) return fail(LLG_EARG, "max_outer must be >= 1");
     if (!is_fin(o->inner_rtol) || o->inner_rtol <= 0 || o->inner_rtol >= 1)
@@ -184,9 +185,9 @@ hipError_t op_apply(const Ctx& c, const llg_params* p, const double* m, const do
 }
 // M^{-1} A x in one pipeline (with bd: also the Arnoldi inner products of z in c.dots)
 hipError_t op_fused(const Ctx& c, const llg_params* p, const double* m, const double* x, double* z, hipStream_t st,
-                    const BasisDots* bd = nullptr) {
-  return pipe_d(c, PRO_SMINUS, EPI_FUSED, sym_for(c, p->alpha + p->shift, hcoef(p), true), nodal_for(p), x, m, z,
-                st, nullptr, nullptr, bd);
+                    const BasisDots* bd = nullptr, bool spec_ready = false) {
+  return pipe_d(c, spec_ready ? PRO_NONE : PRO_SMINUS, EPI_FUSED, sym_for(c, p->alpha + p->shift, hcoef(p), true),
+                nodal_for(p), x, m, z, st, nullptr, nullptr, bd);
 }
 // (-Delta_N) u for 3 planes
 hipError_t op_lap(const Ctx& c, const double* u, double* out, hipStream_t st) {
@@ -399,14 +400,32 @@ struct CycleResult {
 #define LLG_FUSE_DOTS 1
 #endif
 // The operator output W is float64, or float32 for the precision form's
-// float32 operators (exact: their values are float32).
+// float32 operators (exact: their values are float32).  The last argument
+// (spec_ready) tells the operator that its first x pass already ran, fused
+// with the previous step's pass 2 (FirstUpd), so it starts at the next pass.
 template <typename TW>
-using ArnoldiOpT = std::function<hipError_t(int, const double*, TW*, const BasisDots*)>;
+using ArnoldiOpT = std::function<hipError_t(int, const double*, TW*, const BasisDots*, bool)>;
 using ArnoldiOp = ArnoldiOpT<double>;
+
+// Pass 2 of step j carried by the first x pass of the operator of step j + 1
+// (k_xfwd_upd): ok(j) says whether an instantiation covers step j; run forms
+// u_{j+1}, leaves the operator's x spectra in the spectral buffer and
+// reduces [U_{j+1}^T u_{j+1}, |u_{j+1}|^2] into out.  Used when a step j + 1
+// may follow (it saves the operator's read of u_{j+1} and one launch); when
+// the cycle then stops at step j, the spectra are discarded.
+#ifndef LLG_FUSE_UPDATE
+#define LLG_FUSE_UPDATE 1
+#endif
+template <typename TW>
+struct FirstUpd {
+  std::function<bool(int)> ok;
+  std::function<hipError_t(const UpdFirst&, const TW*, double*)> run;
+};
+
 template <typename TW>
 llg_status cycle_dcgs2(const Ctx& c, const ArnoldiOpT<TW>& op, bool op_dots, const double* u0, double* U1, TW* W,
                        long long n4, double c0, int R, double eta, int maxiter, int& iters, CycleResult& out,
-                       hipStream_t st) {
+                       hipStream_t st, const FirstUpd<TW>* fu = nullptr) {
   if (R >= kDcgsMaxCols) return fail(LLG_EARG, "delayed CGS2 needs restart <= 31");
   Hess hs(R);
   std::vector<double> Hraw(size_t(R + 1) * R, 0.0), T(size_t(R + 1) * (R + 1), 0.0),
@@ -426,21 +445,22 @@ llg_status cycle_dcgs2(const Ctx& c, const ArnoldiOpT<TW>& op, bool op_dots, con
   }
   // Operator of step jj on u_jj into W, its pass-1 products into pslot.
   hipError_t op_err = hipSuccess;
-  auto launch_op = [&](int jj, double* pslot) {
+  auto launch_op = [&](int jj, double* pslot, bool spec_ready) {
     const double* ujj = jj == 0 ? u0 : U1 + size_t(jj - 1) * n4;
     hipError_t e;
     if (op_dots) {
       BasisDots bq{u0, U1, n4, jj + 1, nullptr};
       bq.out = pslot;
-      e = op(jj, ujj, W, &bq);
+      e = op(jj, ujj, W, &bq, spec_ready);
     } else {
-      e = op(jj, ujj, W, nullptr);
+      e = op(jj, ujj, W, nullptr, spec_ready);
       if (e == hipSuccess) e = dcgs_dots(c, u0, U1, n4, jj, W, n4, pslot, st);
     }
     if (e != hipSuccess && op_err == hipSuccess) op_err = e;
   };
   const bool speculate = c.ng <= kSpeculateMaxNodes;
   bool ahead = false;  // step j's operator was launched during step j - 1
+  bool ready = false;  // step j's first x pass ran with pass 2 of step j - 1
   for (int j = 0;; ++j) {
     if (j > 0) {
       for (int i = 0; i < j; ++i) col[i] = hprev[i] + a[i];
@@ -468,17 +488,33 @@ llg_status cycle_dcgs2(const Ctx& c, const ArnoldiOpT<TW>& op, bool op_dots, con
     // pass-1 products of step j go to slot j % 2 (c.dots or c.dots_b), so the
     // operator of step j + 1, launched ahead, cannot overwrite them
     double* pslot = (j & 1) ? c.dots_b : c.dots;
-    if (!ahead) launch_op(j, pslot);
-    CHK(dcgs_update(c, u0, U1, n4, cf, pslot, W, U1 + size_t(j) * n4, n4, c.dots2, st));
+    if (!ahead) launch_op(j, pslot, ready);
+    const bool more = j + 1 < R && iters + 1 < maxiter;  // a step j + 1 may follow
+    const bool fuse = LLG_FUSE_UPDATE && fu && more && fu->ok(j);
+    if (fuse) {
+      UpdFirst ua;
+      ua.u0 = u0;
+      ua.U1 = U1;
+      ua.ld = n4;
+      ua.j = j;
+      ua.inv_beta = cf.inv_beta;
+      ua.unew = U1 + size_t(j) * n4;
+      ua.partial = c.partial;
+      CHK(dcgs_coef(c, cf, pslot, &ua.gamma, st));
+      CHK(fu->run(ua, W, c.dots2));
+    } else {
+      CHK(dcgs_update(c, u0, U1, n4, cf, pslot, W, U1 + size_t(j) * n4, n4, c.dots2, st));
+    }
     // one round trip: pass-1 dots p and the pass-2 dots of u_{j+1}, which their
     // reductions also wrote into the mapped host mirror.  On small grids the
     // next step's operator (on u_{j+1}, which no host decision changes) is
     // queued first, and the host waits only for this step's passes; when the
     // cycle then ends, that work is discarded.
-    ahead = speculate && j + 1 < R && iters + 1 < maxiter;
+    ahead = speculate && more;
+    ready = fuse;
     if (ahead) {
       CHK(hipEventRecord(c.ev, st));
-      launch_op(j + 1, ((j + 1) & 1) ? c.dots_b : c.dots);
+      launch_op(j + 1, ((j + 1) & 1) ? c.dots_b : c.dots, ready);
       CHK(hipEventSynchronize(c.ev));
     } else {
       CHK(hipStreamSynchronize(st));
@@ -552,11 +588,14 @@ struct SolveHints {
 // Left-preconditioned restarted GMRES (FP64) with true-residual acceptance.
 // A: true operator, M: preconditioner, MA: M^{-1} A.
 // MAd (optional): MA that also leaves the delayed-CGS2 pass-1 inner products
-// of its output in c.dots (run_pipeline's BasisDots).
-using OpDots = std::function<hipError_t(const double* in, double* out, const BasisDots* bd)>;
+// of its output in c.dots (run_pipeline's BasisDots), and starts after its
+// first x pass when spec_ready; fu (optional, with MAd): that first pass
+// fused with the previous step's pass 2.
+using OpDots = std::function<hipError_t(const double* in, double* out, const BasisDots* bd, bool spec_ready)>;
 llg_status gmres_left(const Ctx& c, const ResidOp& RA, const Op& M, const Op& MA, const double* b, double* x,
                       const llg_solver_opts& o, Work& w, SolveResult& res, hipStream_t st,
-                      const OpDots* MAd = nullptr, const SolveHints& hints = {}) {
+                      const OpDots* MAd = nullptr, const SolveHints& hints = {},
+                      const FirstUpd<double>* fu = nullptr) {
   const long long n4 = 4 * c.ng;
   const int R = o.restart;
   double bnorm = hints.bnorm;
@@ -610,11 +649,11 @@ llg_status gmres_left(const Ctx& c, const ResidOp& RA, const Op& M, const Op& MA
       CHK(dot_and_norm(c, U0, nullptr, n4, c.scal, st));
       CHK_STATUS(fetch(c, c.scal, 2, st, un));
       CycleResult cr;
-      auto op = [&](int, const double* u, double* wout, const BasisDots* bq) {
-        return MAd ? (*MAd)(u, wout, bq) : MA(u, wout);
+      auto op = [&](int, const double* u, double* wout, const BasisDots* bq, bool ready) {
+        return MAd ? (*MAd)(u, wout, bq, ready) : MA(u, wout);
       };
       CHK_STATUS(cycle_dcgs2<double>(c, op, MAd != nullptr && LLG_FUSE_DOTS != 0, U0, U0 + n4, W, n4, un[1], R,
-                             target / rho, o.maxiter, res.iters, cr, st));
+                                     target / rho, o.maxiter, res.iters, cr, st, MAd ? fu : nullptr));
       if (!is_fin(cr.beta0)) return fail(LLG_ENAN, "non-finite preconditioned residual");
       if (beta0 < 0) beta0 = cr.beta0;
       res.rel_prec = beta0 > 0 ? cr.gres / beta0 : 0.0;
@@ -665,7 +704,8 @@ llg_status gmres_left(const Ctx& c, const ResidOp& RA, const Op& M, const Op& MA
 // residual.  AMd: the operator A M^{-1} in one pipeline, which also leaves the
 // delayed-CGS2 pass-1 products in c.dots when given the basis.
 llg_status gmres_right(const Ctx& c, const ResidOp& RA, const Op& M, const OpDots& AMd, const double* b, double* x,
-                       const llg_solver_opts& o, Work& w, SolveResult& res, hipStream_t st) {
+                       const llg_solver_opts& o, Work& w, SolveResult& res, hipStream_t st,
+                       const FirstUpd<double>* fu = nullptr) {
   const long long n4 = 4 * c.ng;
   const int R = o.restart;
   double nb[2];
@@ -706,9 +746,11 @@ llg_status gmres_right(const Ctx& c, const ResidOp& RA, const Op& M, const OpDot
     if (res.iters >= o.maxiter) break;
     res.cycles++;
     CycleResult cr;
-    auto op = [&](int, const double* u, double* wout, const BasisDots* bq) { return AMd(u, wout, bq); };
+    auto op = [&](int, const double* u, double* wout, const BasisDots* bq, bool ready) {
+      return AMd(u, wout, bq, ready);
+    };
     CHK_STATUS(cycle_dcgs2<double>(c, op, LLG_FUSE_DOTS != 0, w.r, w.V, W, n4, rho * rho, R, target / rho, o.maxiter,
-                           res.iters, cr, st));
+                                   res.iters, cr, st, fu));
     res.rel_prec = cr.gres / bnorm;
     if (cr.k == 0) break;
     // t = U y = y_0 u_0 + sum_{i >= 1} y_i u_i, then x += M^{-1} t
@@ -805,12 +847,19 @@ llg_status gmres_ir(const Ctx& c, const llg_params* p, const double* m, const do
       CycleResult cr;
       if (o.orth == 0) {
         // delayed CGS2: the fused float32 operator's output goes to W32 in float32
-        ArnoldiOpT<float> opl32 = [&](int, const double* u, float* wout, const BasisDots* bq) -> hipError_t {
+        ArnoldiOpT<float> opl32 = [&](int, const double* u, float* wout, const BasisDots* bq,
+                                      bool ready) -> hipError_t {
           PipeIO<float, double, float> io{u, w.m32, wout, c.ng, nullptr, nullptr};
-          return run_pipeline<float, double, float>(c, PRO_SMINUS, EPI_FUSED, sym_ap, na, io, st, bq, c.dots);
+          return run_pipeline<float, double, float>(c, ready ? PRO_NONE : PRO_SMINUS, EPI_FUSED, sym_ap, na, io,
+                                                    st, bq, c.dots);
         };
+        const FirstUpd<float> fu{
+            [&](int j) { return xfwd_upd_supported(c, PRO_SMINUS, true, j, o.fuse_update); },
+            [&](const UpdFirst& ua, const float* wv, double* out) {
+              return run_xfwd_upd(c, PRO_SMINUS, na, ua, wv, w.m32, out, st);
+            }};
         CHK_STATUS(cycle_dcgs2<float>(c, opl32, LLG_FUSE_DOTS != 0, Q, Q + n4, w.W32, n4, un[1], R, eta,
-                                      o.maxiter, res.iters, cr, st));
+                                      o.maxiter, res.iters, cr, st, &fu));
       } else {
         const double beta = std::sqrt(un[1]);
         if (!is_fin(beta)) return fail(LLG_ENAN, "non-finite preconditioned residual");
@@ -841,12 +890,19 @@ llg_status gmres_ir(const Ctx& c, const llg_params* p, const double* m, const do
       // u_0 = r (the residual buffer is consumed as the cycle's start vector),
       // u_1 .. u_R in columns 0 .. R - 1 of V, Op output in column R + 1
       // operator output in float32 (W32): the float32 matvec's values exactly
-      ArnoldiOpT<float> op = [&](int j, const double* u, float* wout, const BasisDots* bq) -> hipError_t {
-        return run_apply_matvec(c, sym_ap, sym_mv, na, u, w.m32, w.Z + size_t(j) * n4, wout, st, bq, c.dots);
+      ArnoldiOpT<float> op = [&](int j, const double* u, float* wout, const BasisDots* bq,
+                                 bool ready) -> hipError_t {
+        return run_apply_matvec(c, sym_ap, sym_mv, na, u, w.m32, w.Z + size_t(j) * n4, wout, st, bq, c.dots,
+                                ready);
       };
+      const FirstUpd<float> fu{
+          [&](int j) { return xfwd_upd_supported(c, PRO_COPY3, true, j, o.fuse_update); },
+          [&](const UpdFirst& ua, const float* wv, double* out) {
+            return run_xfwd_upd(c, PRO_COPY3, na, ua, wv, w.m32, out, st);
+          }};
       CycleResult cr;
       CHK_STATUS(cycle_dcgs2<float>(c, op, LLG_FUSE_DOTS != 0, w.r, w.V, w.W32, n4, rho * rho, R, eta, o.maxiter,
-                                    res.iters, cr, st));
+                                    res.iters, cr, st, &fu));
       res.rel_prec = cr.gres / bnorm;
       if (cr.k == 0) break;
       CHK(lincomb(c, n4, cr.y, w.Z, n4, x, st));
@@ -934,10 +990,14 @@ llg_status solve(const Ctx& c, const llg_params* p, const double* m, const doubl
   }
   Op M = [&](const double* in, double* out) { return op_apply(c, p, m, in, out, false, st); };
   Op MA = [&](const double* in, double* out) { return op_fused(c, p, m, in, out, st); };
-  OpDots MAd = [&](const double* in, double* out, const BasisDots* bd) {
-    return op_fused(c, p, m, in, out, st, bd);
+  OpDots MAd = [&](const double* in, double* out, const BasisDots* bd, bool ready) {
+    return op_fused(c, p, m, in, out, st, bd, ready);
   };
-  return gmres_left(c, RA, M, MA, b, x, o, w, res, st, &MAd, hints);
+  const FirstUpd<double> fu{[&](int j) { return xfwd_upd_supported(c, PRO_SMINUS, false, j, o.fuse_update); },
+                            [&](const UpdFirst& ua, const double* wv, double* out) {
+                              return run_xfwd_upd(c, PRO_SMINUS, nodal_for(p), ua, wv, m, out, st);
+                            }};
+  return gmres_left(c, RA, M, MA, b, x, o, w, res, st, &MAd, hints, &fu);
 }
 
 void fill_stats(const SolveResult& r, llg_solver_stats* s) {
@@ -1549,11 +1609,16 @@ llg_status llg_step_midpoint_adjoint(llg_ctx* ctx, const llg_params* prm, const 
     // one pipeline per iteration: J^T M^{-T} = [I + (N - lambda I)(calH + lambda I)^{-1}]
     // (calS + lambda I)^{-T} with N node-wise, right preconditioning
     const SymArgs sym_ap = sym_for(c, p2.alpha + p2.shift, hcoef(&p2), true);
-    OpDots JTMT = [&](const double* in, double* out, const BasisDots* bd) -> hipError_t {
+    OpDots JTMT = [&](const double* in, double* out, const BasisDots* bd, bool ready) -> hipError_t {
       PipeIO<double, double, double> io{in, w.mh, out, c.ng, v, lam};
-      return run_pipeline<double, double, double>(c, PRO_M2T, EPI_JT_RIGHT, sym_ap, na, io, st, bd, c.dots);
+      return run_pipeline<double, double, double>(c, ready ? PRO_NONE : PRO_M2T, EPI_JT_RIGHT, sym_ap, na, io, st,
+                                                  bd, c.dots);
     };
-    s = gmres_right(c, RJT, MT, JTMT, w.b, w.x, o, w, r, st);
+    const FirstUpd<double> fu{[&](int j) { return xfwd_upd_supported(c, PRO_M2T, false, j, o.fuse_update); },
+                              [&](const UpdFirst& ua, const double* wv, double* out) {
+                                return run_xfwd_upd(c, PRO_M2T, na, ua, wv, w.mh, out, st);
+                              }};
+    s = gmres_right(c, RJT, MT, JTMT, w.b, w.x, o, w, r, st, &fu);
   } else {
     s = gmres_left(c, RJT, MT, MTJT, w.b, w.x, o, w, r, st);
   }

@@ -35,6 +35,10 @@ hipError_t dcgs_update(const Ctx& c, const double* u0, const double* U1, long lo
 hipError_t dcgs_update(const Ctx& c, const double* u0, const double* U1, long long ld, const DcgsCoef& cf,
                        const double* p, const float* w, double* unew, long long n, double* out, hipStream_t st);
 
+// The coefficient step of pass 2 alone (k_dcgs_coef): gamma (device, j + 1
+// values) for a pass 2 run elsewhere (k_xfwd_upd).
+hipError_t dcgs_coef(const Ctx& c, const DcgsCoef& cf, const double* p, const double** gamma, hipStream_t st);
+
 // out[i] = sum (or max) of the nb value-major partials of value i, i < nv
 hipError_t reduce_partials(const Ctx& c, int nb, int nv, double* out, bool is_max, hipStream_t st);
 // Blocks of a reducing streaming kernel over n elements: about four elements

@@ -565,16 +565,24 @@ hipError_t dcgs_dots(const Ctx& c, const double* u0, const double* U1, long long
   return dcgs_dots_t(c, u0, U1, ld, j, w, n, out, st);
 }
 
+hipError_t dcgs_coef(const Ctx& c, const DcgsCoef& cf, const double* p, const double** gamma, hipStream_t st) {
+  if (cf.j < 0 || cf.j >= kDcgsMaxCols) return hipErrorInvalidValue;
+  double* g = c.tri + kDcgsMaxCols * kDcgsMaxCols;
+  {
+    ProfScope ps(c.prof, st, KK_REDUCE, 8.0 * (cf.j + 1) * (cf.j + 3));
+    hipLaunchKernelGGL(k_dcgs_coef, dim3(1), dim3(64), 0, st, cf, p, c.tri, g);
+  }
+  *gamma = g;
+  return hipGetLastError();
+}
+
 template <typename TW>
 static hipError_t dcgs_update_t(const Ctx& c, const double* u0, const double* U1, long long ld, const DcgsCoef& cf,
                                 const double* p, const TW* w, double* unew, long long n, double* out,
                                 hipStream_t st) {
-  if (cf.j < 0 || cf.j >= kDcgsMaxCols) return hipErrorInvalidValue;
-  double* gamma = c.tri + kDcgsMaxCols * kDcgsMaxCols;
-  {
-    ProfScope ps(c.prof, st, KK_REDUCE, 8.0 * (cf.j + 1) * (cf.j + 3));
-    hipLaunchKernelGGL(k_dcgs_coef, dim3(1), dim3(64), 0, st, cf, p, c.tri, gamma);
-  }
+  const double* gamma = nullptr;
+  hipError_t e = dcgs_coef(c, cf, p, &gamma, st);
+  if (e != hipSuccess) return e;
   {
     // j + 1 directions read, w read, u_new written
     ProfScope ps(c.prof, st, KK_CGS_UPDATE_DOTS, double(n) * (8.0 * (cf.j + 2) + sizeof(TW)));

@@ -37,7 +37,7 @@ constexpr long long kSpeculateMaxNodes = 1 << 20;
 enum KernelKind : int {
   KK_XFWD = 0, KK_AXIS_FWD, KK_AXIS_FUSED, KK_AXIS_INV, KK_XINV, KK_CGS_DOTS, KK_CGS_UPDATE_DOTS,
   KK_CGS_UPDATE_NORM, KK_REDUCE, KK_SCALE, KK_AXPBY, KK_LINCOMB, KK_CONVERT, KK_DOT2, KK_NODAL, KK_FIELD3,
-  KK_XMID, KK_XINV_DOTS, KK_COUNT
+  KK_XMID, KK_XINV_DOTS, KK_XFWD_UPD, KK_COUNT
 };
 const char* kernel_kind_name(int k);
 
@@ -107,14 +107,32 @@ hipError_t run_pipeline(const Ctx& c, int pro, int epi, const SymArgs& sym, cons
 // stored) and w = A z (float32, float64 result), the two pipelines joined by
 // one fused x pass.  With bd (bd->nv > 0) the last pass also forms the
 // Arnoldi inner products dots_out[q] = u_q . w, q < bd->nv (device).
+// spec_ready: the x spectra of v are already in the spectral buffer
+// (run_xfwd_upd with PRO_COPY3), so the apply's x-forward pass is skipped.
 hipError_t run_apply_matvec(const Ctx& c, const SymArgs& sym_ap, const SymArgs& sym_mv, const NodalArgs& na,
                             const double* v, const float* m32, float* z, double* w, hipStream_t st,
-                            const BasisDots* bd = nullptr, double* dots_out = nullptr);
+                            const BasisDots* bd = nullptr, double* dots_out = nullptr, bool spec_ready = false);
 // The same with a float32 w (the flexible cycle's operator output: the
 // float32 matvec's values, read exactly by the Arnoldi pass).
 hipError_t run_apply_matvec(const Ctx& c, const SymArgs& sym_ap, const SymArgs& sym_mv, const NodalArgs& na,
                             const double* v, const float* m32, float* z, float* w, hipStream_t st,
-                            const BasisDots* bd = nullptr, double* dots_out = nullptr);
+                            const BasisDots* bd = nullptr, double* dots_out = nullptr, bool spec_ready = false);
+
+// Delayed-CGS2 pass 2 of step ua.j fused into the x-forward pass of the next
+// operator (xfwd_upd.hip): k_xfwd_upd forms, stores and feeds u_new to the
+// prologue `pro` (PRO_COPY3: the precision form's float32 apply; PRO_SMINUS:
+// a fused M^{-1} A; PRO_M2T: the right-preconditioned adjoint), leaves the
+// operator's x spectra in the spectral buffer for a pipeline started with
+// PRO_NONE, and reduces [u_q . u_new (q <= j), u_new . u_new] into out.
+// T = float: float32 passes with a float32 w and float32 m; T = double:
+// float64 passes and w.  xfwd_upd_supported says whether to take it for this
+// grid, prologue and ua.j under the policy of llg_solver_opts::fuse_update
+// (-1 never, 0 large grids, 1 wherever an instantiation covers the grid).
+bool xfwd_upd_supported(const Ctx& c, int pro, bool f32, int j, int policy);
+hipError_t run_xfwd_upd(const Ctx& c, int pro, const NodalArgs& na, const UpdFirst& ua, const float* w,
+                        const float* m32, double* out, hipStream_t st);
+hipError_t run_xfwd_upd(const Ctx& c, int pro, const NodalArgs& na, const UpdFirst& ua, const double* w,
+                        const double* m, double* out, hipStream_t st);
 
 // Lower-order field pipeline (field.hip, float64): forward DFTs of three
 // planes, the 3x3 multiplier of FieldArgs, inverse DFTs, then the x-inverse

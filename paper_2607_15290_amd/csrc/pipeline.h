@@ -84,6 +84,8 @@ struct NodalArgs {
 };
 
 enum ProMode : int {
+  PRO_NONE = -1,   // no x-forward pass: the spectral buffer already holds the
+                   // filtered fields' x spectra (left by k_xfwd_upd)
   PRO_COPY3 = 0,   // u = in[0..2]
   PRO_SMINUS = 1,  // u = m x v + m r - lambda v  (first half of the fused op)
   PRO_M2T = 2,     // u = ((lambda I + S~) p)_v / (lambda^2 + |m|^2)
@@ -154,6 +156,25 @@ struct BasisDots {
   int nv = 0;
   double* partial = nullptr;
   double* out = nullptr;  // when set, the reduced products go here instead of the caller's default
+};
+
+// Delayed-CGS2 pass 2 of Arnoldi step j carried by the first x pass of the
+// operator of step j + 1 (k_xfwd_upd): with basis directions u_0 at u0 and
+// u_q at U1 + (q - 1) ld, the pass forms
+//   u_new = (w - sum_{q <= j} gamma_q u_q) * inv_beta
+// node by node, stores it at unew (the next basis direction), feeds it to
+// the operator's prologue, and leaves the block partials of u_q . u_new
+// (q <= j) and u_new . u_new at partial[q * gridDim.x + blockIdx.x],
+// q = 0 .. j + 1.
+struct UpdFirst {
+  const double* u0 = nullptr;
+  const double* U1 = nullptr;
+  long long ld = 0;
+  int j = 0;
+  const double* gamma = nullptr;  // j + 1 coefficients (device)
+  double inv_beta = 0;
+  double* unew = nullptr;         // must not alias w or a basis column 0..j
+  double* partial = nullptr;
 };
 
 }  // namespace llg

@@ -21,10 +21,10 @@ template hipError_t run_pipeline<float, double, double>(const Ctx&, int, int, co
 template <typename TW>
 static hipError_t apply_matvec_t(const Ctx& c, const SymArgs& sym_ap, const SymArgs& sym_mv, const NodalArgs& na,
                                  const double* v, const float* m32, float* z, TW* w, hipStream_t st,
-                                 const BasisDots* bd, double* dots_out) {
+                                 const BasisDots* bd, double* dots_out, bool spec_ready) {
   switch (c.geom.nh) {
 #define LLG_CASE(n) \
-  case n: return run_apply_matvec_nh<n, TW>(c, sym_ap, sym_mv, na, v, m32, z, w, bd, dots_out, st);
+  case n: return run_apply_matvec_nh<n, TW>(c, sym_ap, sym_mv, na, v, m32, z, w, bd, dots_out, spec_ready, st);
     LLG_FOR_NH(LLG_CASE)
 #undef LLG_CASE
     default: return hipErrorInvalidValue;
@@ -32,12 +32,12 @@ static hipError_t apply_matvec_t(const Ctx& c, const SymArgs& sym_ap, const SymA
 }
 hipError_t run_apply_matvec(const Ctx& c, const SymArgs& sym_ap, const SymArgs& sym_mv, const NodalArgs& na,
                             const double* v, const float* m32, float* z, double* w, hipStream_t st,
-                            const BasisDots* bd, double* dots_out) {
-  return apply_matvec_t(c, sym_ap, sym_mv, na, v, m32, z, w, st, bd, dots_out);
+                            const BasisDots* bd, double* dots_out, bool spec_ready) {
+  return apply_matvec_t(c, sym_ap, sym_mv, na, v, m32, z, w, st, bd, dots_out, spec_ready);
 }
 hipError_t run_apply_matvec(const Ctx& c, const SymArgs& sym_ap, const SymArgs& sym_mv, const NodalArgs& na,
                             const double* v, const float* m32, float* z, float* w, hipStream_t st,
-                            const BasisDots* bd, double* dots_out) {
-  return apply_matvec_t(c, sym_ap, sym_mv, na, v, m32, z, w, st, bd, dots_out);
+                            const BasisDots* bd, double* dots_out, bool spec_ready) {
+  return apply_matvec_t(c, sym_ap, sym_mv, na, v, m32, z, w, st, bd, dots_out, spec_ready);
 }
 }  // namespace llg

@@ -78,6 +78,18 @@ __device__ __forceinline__ void store2(U* __restrict__ p, U a, U b) {
   st_s(p + 1, b);
 }
 
+// Pair access at a wave-uniform plane base plus a 32-bit per-lane byte
+// offset: the load takes the scalar-base address form, so a pass touching
+// many planes keeps one offset register instead of a 64-bit address per plane.
+template <typename U>
+__device__ __forceinline__ void load2_at(const U* __restrict__ base, unsigned boff, U& a, U& b) {
+  load2(reinterpret_cast<const U*>(reinterpret_cast<const char*>(base) + boff), a, b);
+}
+template <typename U>
+__device__ __forceinline__ void store2_at(U* __restrict__ base, unsigned boff, U a, U b) {
+  store2(reinterpret_cast<U*>(reinterpret_cast<char*>(base) + boff), a, b);
+}
+
 // ---------------------------------------------------------------------------
 // Nodal algebra (Sec. 3.1, eqs. (S) and (Lambda); Sec. 3.2, eq. "inverse S")
 // ---------------------------------------------------------------------------
@@ -490,6 +502,150 @@ __global__ __launch_bounds__(192) void k_xfwd(const TIn* __restrict__ in, const 
     }
   }
   __syncthreads();
+  x_r2c_store<T, NH>(lds, line0, nlines, spec, g, twx);
+}
+
+// ---------------------------------------------------------------------------
+// k_xfwd_upd: the x-forward pass of an Arnoldi step's operator that first
+// forms its own input, the next basis direction of delayed CGS2 (UpdFirst):
+// the separate update pass would write u_new and this pass read it straight
+// back.
+//   Phase 1, one (plane, node pair) per loop trip as in the update pass: the
+//   loads of w and of the j + 1 basis directions are issued together, u_new
+//   is stored, its inner products accumulated (the directions stay in
+//   registers between the two uses), and u_new is parked in LDS in the
+//   precision T of the passes (the prologue converts its input to T first).
+//   Phase 2: the prologue PRO on the parked values, into the DFT layout.
+// JB >= j bounds the columns held (the guards q <= j are uniform branches).
+// W: float (the precision form's float32 operator output, converted exactly)
+// or double.
+// ---------------------------------------------------------------------------
+template <typename T, typename W, int NH, int PRO, int JB>
+__global__ __launch_bounds__(192) void k_xfwd_upd(UpdFirst ua, const W* __restrict__ w, const T* __restrict__ m,
+                                                  cx<T>* __restrict__ spec, SpecGeom g, NodalArgs na,
+                                                  const cx<T>* __restrict__ twx) {
+  using C = XCfg<T, NH>;
+  constexpr bool NODAL = PRO != PRO_COPY3;  // the prologue needs all four planes and m
+  __shared__ cx<T> lds[3 * C::LX * C::SL];
+  __shared__ cx<T> lds_r[NODAL ? C::LX * NH : 1];  // plane 3 of u_new (nodal prologues)
+  __shared__ double dred[C::NT / 64][JB + 2];
+  const int tid = threadIdx.x;
+  const long long nlines = (long long)g.ny * g.nz;
+  const long long line0 = (long long)blockIdx.x * C::LX;
+  constexpr int NX = 2 * NH;
+  constexpr int NPAIR = C::LX * NH;
+  const int J = ua.j;
+  double gm[JB + 1];
+#pragma unroll
+  for (int q = 0; q <= JB; ++q) gm[q] = q <= J ? ua.gamma[q] : 0.0;
+  double acc[JB + 2];  // u_q . u_new (q <= j), then u_new . u_new
+#pragma unroll
+  for (int q = 0; q < JB + 2; ++q) acc[q] = 0.0;
+  const long long np = (long long)(line0 + C::LX <= nlines ? C::LX : nlines - line0) * NH;  // live pairs
+  // NB items per trip: all their loads are issued before any store (the
+  // stores could alias them as far as the compiler knows), which keeps
+  // NB (j + 2) loads of each wave in flight
+  constexpr int NB = JB <= 3 ? 4 : 2;
+  static_assert(JB <= 7, "more directions than a batch of items keeps in registers");
+  constexpr int NITEM = 4 * NPAIR;
+#pragma unroll 1
+  for (int t0 = tid; t0 < NITEM; t0 += NB * C::NT) {
+    long long k[NB];
+    int slot[NB];
+    bool live[NB];
+    double s0[NB], s1[NB], q0[NB][JB + 1], q1[NB][JB + 1];
+#pragma unroll
+    for (int b = 0; b < NB; ++b) {
+      const int tt = t0 + b * C::NT;
+      const int t = tt < NITEM ? tt : NITEM - 1;
+      const int f = t / NPAIR, e = t - f * NPAIR;
+      const int l = e / NH, xp = e - l * NH;
+      live[b] = tt < NITEM && e < np;
+      k[b] = f * g.ng + (e < np ? line0 + l : line0) * NX + 2 * xp;
+      // LDS destination: DFT slot of field f, or (plane 3) the parking row
+      slot[b] = tt >= NITEM ? -1 : (f < 3 ? (f * C::LX + l) * C::SL + xphys(xp) : -2 - e);
+      W w0, w1;
+      load2(w + k[b], w0, w1);
+      s0[b] = double(w0);
+      s1[b] = double(w1);
+#pragma unroll
+      for (int q = 0; q <= JB; ++q) {
+        if (q <= J) load2((q == 0 ? ua.u0 : ua.U1 + (q - 1) * ua.ld) + k[b], q0[b][q], q1[b][q]);
+      }
+    }
+#pragma unroll
+    for (int b = 0; b < NB; ++b) {
+#pragma unroll
+      for (int q = 0; q <= JB; ++q) {
+        if (q <= J) {
+          s0[b] = fma(-gm[q], q0[b][q], s0[b]);
+          s1[b] = fma(-gm[q], q1[b][q], s1[b]);
+        }
+      }
+      const double a0 = s0[b] * ua.inv_beta, a1 = s1[b] * ua.inv_beta;
+      if (live[b]) store2(ua.unew + k[b], a0, a1);
+      const double d0 = live[b] ? a0 : 0.0, d1 = live[b] ? a1 : 0.0;
+#pragma unroll
+      for (int q = 0; q <= JB; ++q) {
+        if (q <= J) acc[q] = fma(q0[b][q], d0, fma(q1[b][q], d1, acc[q]));
+      }
+      acc[JB + 1] = fma(d0, d0, fma(d1, d1, acc[JB + 1]));
+      const cx<T> v{T(d0), T(d1)};  // dead lines filter zeros
+      if (slot[b] >= 0) lds[slot[b]] = v;
+      else if constexpr (NODAL) {
+        if (slot[b] <= -2) lds_r[-2 - slot[b]] = v;
+      }
+    }
+  }
+  // block partials of the inner products (fixed order: deterministic)
+  const int lane = tid & 63, wv = tid >> 6;
+#pragma unroll
+  for (int q = 0; q < JB + 2; ++q) {
+    if (q <= J || q == JB + 1) {
+      double s = acc[q];
+#pragma unroll
+      for (int off = 32; off > 0; off >>= 1) s += __shfl_xor(s, off, 64);
+      if (lane == 0) dred[wv][q] = s;
+    }
+  }
+  __syncthreads();
+  if (tid <= J + 1) {
+    const int src = tid <= J ? tid : JB + 1;
+    double s = dred[0][src];
+#pragma unroll
+    for (int k = 1; k < C::NT / 64; ++k) s += dred[k][src];
+    ua.partial[(long long)tid * gridDim.x + blockIdx.x] = s;
+  }
+  if constexpr (NODAL) {
+    // prologue in place: each node pair's slots are read and rewritten by
+    // the one thread that handles the pair here
+    constexpr int ITERS = (NPAIR + C::NT - 1) / C::NT;
+#pragma unroll
+    for (int it = 0; it < ITERS; ++it) {
+      const int e = tid + it * C::NT;
+      if (e < NPAIR) {
+        const int l = e / NH, xp = e - l * NH;
+        const bool live = e < np;
+        const long long i = (live ? line0 + l : line0) * NX + 2 * xp;
+        ProRaw<T, T, PRO> raw;
+#pragma unroll
+        for (int f = 0; f < 3; ++f) load2(m + f * g.ng + i, raw.m[f][0], raw.m[f][1]);
+#pragma unroll
+        for (int f = 0; f < 3; ++f) {
+          const cx<T> v = lds[(f * C::LX + l) * C::SL + xphys(xp)];
+          raw.v[f][0] = v.x;
+          raw.v[f][1] = v.y;
+        }
+        raw.v[3][0] = lds_r[e].x;
+        raw.v[3][1] = lds_r[e].y;
+        cx<T> u[3];
+        prologue_compute<T, T, PRO>(raw, na, u);
+#pragma unroll
+        for (int f = 0; f < 3; ++f) lds[(f * C::LX + l) * C::SL + xphys(xp)] = live ? u[f] : cx<T>{T(0), T(0)};
+      }
+    }
+    __syncthreads();
+  }
   x_r2c_store<T, NH>(lds, line0, nlines, spec, g, twx);
 }
 

@@ -15,6 +15,7 @@ namespace llg {
 // vectors, and float32 apply / fused M^{-1} A between float64 Krylov vectors.
 template <typename T, typename TIn, typename TOut>
 constexpr bool has_pro(int pro) {
+  if (pro == PRO_NONE) return true;
   if constexpr (std::is_same<T, TIn>::value && std::is_same<T, TOut>::value) return true;
   else if constexpr (std::is_same<TIn, double>::value) return pro == PRO_COPY3 || pro == PRO_SMINUS;
   else return pro == PRO_COPY3;
@@ -115,6 +116,7 @@ hipError_t run_nh(const Ctx& c, int pro, int epi, const SymArgs& sym, const Noda
     case PRO_COPY3: launch_xfwd<T, TIn, TOut, NH, PRO_COPY3>(c, na, io, st); break;
     case PRO_SMINUS: launch_xfwd<T, TIn, TOut, NH, PRO_SMINUS>(c, na, io, st); break;
     case PRO_M2T: launch_xfwd<T, TIn, TOut, NH, PRO_M2T>(c, na, io, st); break;
+    case PRO_NONE: break;  // x spectra already in place (k_xfwd_upd)
     default: return hipErrorInvalidValue;
   }
   cx<T>* spec = reinterpret_cast<cx<T>*>(c.spec);
@@ -175,15 +177,16 @@ hipError_t run_axes(const Ctx& c, const SymArgs& sym, hipStream_t st) {
 // float64 result; the junction of the two pipelines is the fused k_xmid pass.
 // The matvec's output w is float64 (a Krylov vector) or float32 (the Arnoldi
 // operator output of the precision form, whose float32 values convert to
-// float64 exactly when the Arnoldi pass reads them).
+// float64 exactly when the Arnoldi pass reads them).  spec_ready: the apply's
+// x-forward pass already ran (k_xfwd_upd with PRO_COPY3).
 template <int NH, typename TW>
 hipError_t run_apply_matvec_nh(const Ctx& c, const SymArgs& sym_ap, const SymArgs& sym_mv, const NodalArgs& na,
                                const double* v, const float* m32, float* z, TW* w, const BasisDots* bd,
-                               double* dots_out, hipStream_t st) {
+                               double* dots_out, bool spec_ready, hipStream_t st) {
   using C = XCfg<float, NH>;
   PipeIO<float, double, float> io_ap{v, m32, z, c.ng, nullptr, nullptr};
   PipeIO<float, float, TW> io_mv{z, m32, w, c.ng, nullptr, nullptr};
-  launch_xfwd<float, double, float, NH, PRO_COPY3>(c, na, io_ap, st);
+  if (!spec_ready) launch_xfwd<float, double, float, NH, PRO_COPY3>(c, na, io_ap, st);
   hipError_t e;
   if ((e = run_axes<float>(c, sym_ap, st)) != hipSuccess) return e;
   {

@@ -49,7 +49,7 @@ static const char* kNames[KK_COUNT] = {"xfwd",      "axis_fwd",          "axis_f
                                        "xinv",      "cgs_dots",          "cgs_update_dots",   "cgs_update_norm",
                                        "reduce",    "scale",             "axpby",             "lincomb",
                                        "convert",   "dot2",              "nodal",             "field3",
-                                       "xmid",      "xinv_dots"};
+                                       "xmid",      "xinv_dots",         "xfwd_upd"};
 
 const char* kernel_kind_name(int k) { return (k >= 0 && k < KK_COUNT) ? kNames[k] : "?"; }
 

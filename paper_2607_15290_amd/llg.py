@@ -72,12 +72,14 @@ class Params:
 ORTH = {"dcgs2": 0, "cgs2": 1, 0: 0, 1: 1}
 PRECOND = {"fft_hss": 0, "symmetric": 1, "none": 2, 0: 0, 1: 1, 2: 2}
 PICARD_NORM = {"midpoint": 0, "velocity": 1, 0: 0, 1: 1}
+FUSE_UPDATE = {"auto": 0, "always": 1, "never": -1, 0: 0, 1: 1, -1: -1}
 
 
 def _opts(restart, maxiter, rtol, prec, inner_rtol, max_outer, use_x0, orth="dcgs2", precond="fft_hss",
-          picard_norm="midpoint", transpose=False):
+          picard_norm="midpoint", transpose=False, fuse_update="auto"):
     o = L.LLGSolverOpts()
     o.transpose = int(bool(transpose))
+    o.fuse_update = FUSE_UPDATE[fuse_update]
     o.orth = ORTH[orth]
     o.precond = PRECOND[precond]
     o.picard_norm = PICARD_NORM[picard_norm]
@@ -249,13 +251,16 @@ def llg_precond_op_f32(ctx, params, m, x, side=0, z=None, y=None, basis=None):
 
 
 def gmres_solve(ctx, params, m, b, x=None, use_x0=False, restart=30, rtol=1e-10, maxiter=3000, prec="fp64",
-                inner_rtol=1e-5, max_outer=20, check=True, orth="dcgs2", precond="fft_hss", transpose=False):
+                inner_rtol=1e-5, max_outer=20, check=True, orth="dcgs2", precond="fft_hss", transpose=False,
+                fuse_update="auto"):
     """Solve A(m) x = b (or A(m)^T x = b with transpose); returns (x, stats).
+    fuse_update: "auto", "always" or "never" (llg_solver_opts::fuse_update).
     See gmres_solve in include/llg.h."""
     if x is None:
         x = ctx.new(4)
         use_x0 = False
-    o = _opts(restart, maxiter, rtol, prec, inner_rtol, max_outer, use_x0, orth, precond, transpose=transpose)
+    o = _opts(restart, maxiter, rtol, prec, inner_rtol, max_outer, use_x0, orth, precond, transpose=transpose,
+              fuse_update=fuse_update)
     st = L.LLGSolverStats()
     work = ctx.workspace(restart, prec)
     pr = params.c_struct(ctx)
@@ -270,14 +275,15 @@ def gmres_solve(ctx, params, m, b, x=None, use_x0=False, restart=30, rtol=1e-10,
 
 
 def gmres_solve_noalloc(ctx, params, m, b, x=None, use_x0=False, restart=30, rtol=1e-10, maxiter=3000,
-                        prec="fp64", inner_rtol=1e-5, max_outer=20, check=True, orth="dcgs2", precond="fft_hss"):
+                        prec="fp64", inner_rtol=1e-5, max_outer=20, check=True, orth="dcgs2", precond="fft_hss",
+                        fuse_update="auto"):
     """gmres_solve on the library's static workspace (no caller workspace,
     no device allocation in the call); returns (x, stats).  See
     gmres_solve_noalloc in include/llg.h."""
     if x is None:
         x = ctx.new(4)
         use_x0 = False
-    o = _opts(restart, maxiter, rtol, prec, inner_rtol, max_outer, use_x0, orth, precond)
+    o = _opts(restart, maxiter, rtol, prec, inner_rtol, max_outer, use_x0, orth, precond, fuse_update=fuse_update)
     st = L.LLGSolverStats()
     pr = params.c_struct(ctx)
     s = ctx.lib.gmres_solve_noalloc(ctx.handle, ctypes.byref(pr), ctx.check(m, 3, name="m"),
@@ -291,9 +297,9 @@ def gmres_solve_noalloc(ctx, params, m, b, x=None, use_x0=False, restart=30, rto
 
 
 def llg_step_euler(ctx, params, m, v_out=None, lam_out=None, restart=30, rtol=1e-10, maxiter=3000, prec="fp64",
-                   inner_rtol=1e-5, max_outer=20, check=True, orth="dcgs2"):
+                   inner_rtol=1e-5, max_outer=20, check=True, orth="dcgs2", fuse_update="auto"):
     """One projected Euler step; m is updated in place.  Returns stats."""
-    o = _opts(restart, maxiter, rtol, prec, inner_rtol, max_outer, 0, orth)
+    o = _opts(restart, maxiter, rtol, prec, inner_rtol, max_outer, 0, orth, fuse_update=fuse_update)
     st = L.LLGStepStats()
     work = ctx.workspace(restart, prec)
     pr = params.c_struct(ctx)
@@ -310,11 +316,12 @@ def llg_step_euler(ctx, params, m, v_out=None, lam_out=None, restart=30, rtol=1e
 
 def llg_step_midpoint(ctx, params, m, v_half=None, lam=None, picard_tol=1e-10, picard_max=50, restart=30,
                       rtol=1e-10, maxiter=3000, prec="fp64", inner_rtol=1e-5, max_outer=20, check=True,
-                      orth="dcgs2", picard_norm="midpoint"):
+                      orth="dcgs2", picard_norm="midpoint", fuse_update="auto"):
     """One midpoint step; m, v_half, lam updated in place.  picard_norm:
     "midpoint" (change of the frozen midpoint, default) or "velocity".
     Returns stats."""
-    o = _opts(restart, maxiter, rtol, prec, inner_rtol, max_outer, 1, orth, picard_norm=picard_norm)
+    o = _opts(restart, maxiter, rtol, prec, inner_rtol, max_outer, 1, orth, picard_norm=picard_norm,
+              fuse_update=fuse_update)
     st = L.LLGStepStats()
     work = ctx.workspace(restart, prec)
     pr = params.c_struct(ctx)
@@ -331,11 +338,11 @@ def llg_step_midpoint(ctx, params, m, v_half=None, lam=None, picard_tol=1e-10, p
 
 
 def llg_step_midpoint_adjoint(ctx, params, m_n, v, lam, gbar, hbar_field=None, hbar_uniform=None, restart=30,
-                              rtol=1e-12, maxiter=3000, check=True, orth="dcgs2"):
+                              rtol=1e-12, maxiter=3000, check=True, orth="dcgs2", fuse_update="auto"):
     """Back-propagate gbar (in/out) through one converged midpoint step.
     hbar_field (tensor, +=) and hbar_uniform (list of 3 floats, +=) are
     accumulated.  Returns (hbar_uniform, stats)."""
-    o = _opts(restart, maxiter, rtol, "fp64", 1e-5, 1, 0, orth)
+    o = _opts(restart, maxiter, rtol, "fp64", 1e-5, 1, 0, orth, fuse_update=fuse_update)
     st = L.LLGSolverStats()
     work = ctx.workspace(restart, "fp64")
     hu = (ctypes.c_double * 3)(*(hbar_uniform if hbar_uniform is not None else (0.0, 0.0, 0.0)))

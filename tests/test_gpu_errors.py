@@ -105,6 +105,13 @@ def test_argument_errors():
                                 ctypes.byref(o), None, work.data_ptr(), work.numel(), None)
         assert s == 1, r
     o.restart = 30
+    # fuse_update outside {-1, 0, 1}
+    for f in (2, -2):
+        o.fuse_update = f
+        s = ctx.lib.gmres_solve(ctx.handle, ctypes.byref(pr), md.data_ptr(), bd.data_ptr(), x.data_ptr(),
+                                ctypes.byref(o), None, work.data_ptr(), work.numel(), None)
+        assert s == 1 and "fuse_update" in _last_error(ctx), f
+    o.fuse_update = 0
     # a workspace one byte short
     need = ctx.lib.llg_workspace_bytes(ctx.handle, 30, 0)
     small = torch.empty(need - 1, dtype=torch.uint8, device="cuda:0")
