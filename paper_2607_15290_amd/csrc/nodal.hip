@@ -49,18 +49,37 @@ __device__ __forceinline__ void bstore(double (&acc)[NV], double* __restrict__ p
   }
 }
 
-#define GRID_LOOP(e, n) \
-  for (long long e = (long long)blockIdx.x * blockDim.x + threadIdx.x; e < (n); e += (long long)gridDim.x * blockDim.x)
+// Node-pair loop: thread-strided over pairs (i, i + 1), i even (n_x is even,
+// so every plane holds whole pairs); every plane access is one 16-byte
+// non-temporal load or store.
+#define PAIR_LOOP(i, ng)                                                                 \
+  for (long long i = 2 * ((long long)blockIdx.x * blockDim.x + threadIdx.x); i < (ng); \
+       i += 2 * (long long)gridDim.x * blockDim.x)
+
+struct Pr {
+  double v[2];
+  __device__ double operator[](int h) const { return v[h]; }
+};
+__device__ __forceinline__ Pr ldp(const double* __restrict__ p) {
+  return Pr{{__builtin_nontemporal_load(p), __builtin_nontemporal_load(p + 1)}};
+}
+__device__ __forceinline__ void stp(double* __restrict__ p, double a, double b) {
+  __builtin_nontemporal_store(a, p);
+  __builtin_nontemporal_store(b, p + 1);
+}
 
 __global__ __launch_bounds__(kRedThreads) void k_m_check(const double* __restrict__ m, long long ng,
                                                         double* __restrict__ partial) {
   double mn[1] = {INFINITY};
   double bad[1] = {0.0};
-  GRID_LOOP(i, ng) {
-    const double a = m[i], b = m[ng + i], c = m[2 * ng + i];
-    const double n2 = a * a + b * b + c * c;
-    if (!isfinite(n2)) bad[0] = 1.0;
-    mn[0] = fmin(mn[0], n2);
+  PAIR_LOOP(i, ng) {
+    const Pr a = ldp(m + i), b = ldp(m + ng + i), c = ldp(m + 2 * ng + i);
+#pragma unroll
+    for (int h = 0; h < 2; ++h) {
+      const double n2 = a[h] * a[h] + b[h] * b[h] + c[h] * c[h];
+      if (!isfinite(n2)) bad[0] = 1.0;
+      mn[0] = fmin(mn[0], n2);
+    }
   }
   bstore<1, 2>(mn, partial);
   __syncthreads();
@@ -70,23 +89,39 @@ __global__ __launch_bounds__(kRedThreads) void k_m_check(const double* __restric
 __global__ __launch_bounds__(kRedThreads) void k_euler_update(double* __restrict__ m, const double* __restrict__ v,
                                                              double k, long long ng, double* __restrict__ partial) {
   double mx[1] = {0.0};
-  GRID_LOOP(i, ng) {
-    double a = m[i] + k * v[i], b = m[ng + i] + k * v[ng + i], c = m[2 * ng + i] + k * v[2 * ng + i];
-    const double s = 1.0 / sqrt(a * a + b * b + c * c);
-    a *= s;
-    b *= s;
-    c *= s;
-    m[i] = a;
-    m[ng + i] = b;
-    m[2 * ng + i] = c;
-    mx[0] = fmax(mx[0], fabs(sqrt(a * a + b * b + c * c) - 1.0));
+  PAIR_LOOP(i, ng) {
+    Pr mc[3], vc[3];
+#pragma unroll
+    for (int f = 0; f < 3; ++f) {
+      mc[f] = ldp(m + f * ng + i);
+      vc[f] = ldp(v + f * ng + i);
+    }
+    double o[3][2];
+#pragma unroll
+    for (int h = 0; h < 2; ++h) {
+      double a = mc[0][h] + k * vc[0][h], b = mc[1][h] + k * vc[1][h], c = mc[2][h] + k * vc[2][h];
+      const double s = 1.0 / sqrt(a * a + b * b + c * c);
+      a *= s;
+      b *= s;
+      c *= s;
+      o[0][h] = a;
+      o[1][h] = b;
+      o[2][h] = c;
+      mx[0] = fmax(mx[0], fabs(sqrt(a * a + b * b + c * c) - 1.0));
+    }
+#pragma unroll
+    for (int f = 0; f < 3; ++f) stp(m + f * ng + i, o[f][0], o[f][1]);
   }
   bstore<1, 1>(mx, partial);
 }
 
+// out = m + a v over n values (n even)
 __global__ void k_axpy3(const double* __restrict__ m, double a, const double* __restrict__ v,
                         double* __restrict__ out, long long n) {
-  GRID_LOOP(i, n) out[i] = m[i] + a * v[i];
+  PAIR_LOOP(i, n) {
+    const Pr x = ldp(m + i), y = ldp(v + i);
+    stp(out + i, x[0] + a * y[0], x[1] + a * y[1]);
+  }
 }
 
 // Picard bookkeeping of the midpoint step, one pass over 3 planes:
@@ -98,38 +133,60 @@ __global__ __launch_bounds__(kRedThreads) void k_picard_update(const double* __r
                                                               float* __restrict__ mh32, double* __restrict__ r,
                                                               double a, long long ng, double* __restrict__ partial) {
   double acc[5] = {0, 0, 0, 0, 0};
-  GRID_LOOP(i, ng) {
-    double mm = 0, dm[3], vv[3];
+  PAIR_LOOP(i, ng) {
+    Pr xv[3], vo[3], mz[3];
 #pragma unroll
     for (int f = 0; f < 3; ++f) {
-      const long long j = f * ng + i;
-      const double vi = x[j], d = vi - vold[j], mi = m0[j] + a * vi;
-      acc[0] += d * d;
-      acc[1] += vi * vi;
-      mm += mi * mi;
-      vold[j] = vi;
-      mh[j] = mi;
-      if (mh32) mh32[j] = float(mi);
-      dm[f] = a * d;
-      vv[f] = vi;
+      xv[f] = ldp(x + f * ng + i);
+      vo[f] = ldp(vold + f * ng + i);
+      mz[f] = ldp(m0 + f * ng + i);
     }
-    acc[2] += mm;
-    acc[3] += mm <= 1e-300 ? 1.0 : 0.0;
+    double mm[2] = {0, 0}, dm[3][2], mi[3][2];
+#pragma unroll
+    for (int f = 0; f < 3; ++f) {
+#pragma unroll
+      for (int h = 0; h < 2; ++h) {
+        const double vi = xv[f][h], d = vi - vo[f][h];
+        mi[f][h] = mz[f][h] + a * vi;
+        acc[0] += d * d;
+        acc[1] += vi * vi;
+        mm[h] += mi[f][h] * mi[f][h];
+        dm[f][h] = a * d;
+      }
+      stp(vold + f * ng + i, xv[f][0], xv[f][1]);
+      stp(mh + f * ng + i, mi[f][0], mi[f][1]);
+      if (mh32) {
+        __builtin_nontemporal_store(float(mi[f][0]), mh32 + f * ng + i);
+        __builtin_nontemporal_store(float(mi[f][1]), mh32 + f * ng + i + 1);
+      }
+    }
+#pragma unroll
+    for (int h = 0; h < 2; ++h) {
+      acc[2] += mm[h];
+      acc[3] += mm[h] <= 1e-300 ? 1.0 : 0.0;
+    }
     if (r) {
       // r -= (dm x v + dm lam, -dm . v), dm = m_hat^{p+1} - m_hat^p
-      const double lam = x[3 * ng + i];
-      const double c0 = dm[1] * vv[2] - dm[2] * vv[1];
-      const double c1 = dm[2] * vv[0] - dm[0] * vv[2];
-      const double c2 = dm[0] * vv[1] - dm[1] * vv[0];
-      const double r0 = r[i] - (c0 + dm[0] * lam);
-      const double r1 = r[ng + i] - (c1 + dm[1] * lam);
-      const double r2 = r[2 * ng + i] - (c2 + dm[2] * lam);
-      const double r3 = r[3 * ng + i] + (dm[0] * vv[0] + dm[1] * vv[1] + dm[2] * vv[2]);
-      r[i] = r0;
-      r[ng + i] = r1;
-      r[2 * ng + i] = r2;
-      r[3 * ng + i] = r3;
-      acc[4] += r0 * r0 + r1 * r1 + r2 * r2 + r3 * r3;
+      const Pr lam = ldp(x + 3 * ng + i);
+      Pr rc[4];
+#pragma unroll
+      for (int f = 0; f < 4; ++f) rc[f] = ldp(r + f * ng + i);
+      double ro[4][2];
+#pragma unroll
+      for (int h = 0; h < 2; ++h) {
+        const double v0 = xv[0][h], v1 = xv[1][h], v2 = xv[2][h];
+        const double d0 = dm[0][h], d1 = dm[1][h], d2 = dm[2][h];
+        const double c0 = d1 * v2 - d2 * v1;
+        const double c1 = d2 * v0 - d0 * v2;
+        const double c2 = d0 * v1 - d1 * v0;
+        ro[0][h] = rc[0][h] - (c0 + d0 * lam[h]);
+        ro[1][h] = rc[1][h] - (c1 + d1 * lam[h]);
+        ro[2][h] = rc[2][h] - (c2 + d2 * lam[h]);
+        ro[3][h] = rc[3][h] + (d0 * v0 + d1 * v1 + d2 * v2);
+        acc[4] += ro[0][h] * ro[0][h] + ro[1][h] * ro[1][h] + ro[2][h] * ro[2][h] + ro[3][h] * ro[3][h];
+      }
+#pragma unroll
+      for (int f = 0; f < 4; ++f) stp(r + f * ng + i, ro[f][0], ro[f][1]);
     }
   }
   bstore<5, 0>(acc, partial);
@@ -138,21 +195,26 @@ __global__ __launch_bounds__(kRedThreads) void k_picard_update(const double* __r
 __global__ __launch_bounds__(kRedThreads) void k_len_err(const double* __restrict__ m, long long ng,
                                                         double* __restrict__ partial) {
   double mx[1] = {0.0};
-  GRID_LOOP(i, ng) {
-    const double a = m[i], b = m[ng + i], c = m[2 * ng + i];
-    mx[0] = fmax(mx[0], fabs(sqrt(a * a + b * b + c * c) - 1.0));
+  PAIR_LOOP(i, ng) {
+    const Pr a = ldp(m + i), b = ldp(m + ng + i), c = ldp(m + 2 * ng + i);
+#pragma unroll
+    for (int h = 0; h < 2; ++h) mx[0] = fmax(mx[0], fabs(sqrt(a[h] * a[h] + b[h] * b[h] + c[h] * c[h]) - 1.0));
   }
   bstore<1, 1>(mx, partial);
 }
 
-__device__ __forceinline__ void field_at(const NodalArgs& na, long long ng, long long i, double (&h)[3]) {
-  h[0] = na.hu0;
-  h[1] = na.hu1;
-  h[2] = na.hu2;
-  if (na.hfield) {
-    h[0] += na.hfield[i];
-    h[1] += na.hfield[ng + i];
-    h[2] += na.hfield[2 * ng + i];
+// applied field at the node pair (i, i + 1): uniform part plus the optional spatial field
+__device__ __forceinline__ void field_pair(const NodalArgs& na, long long ng, long long i, double (&h)[3][2]) {
+  const double hu[3] = {na.hu0, na.hu1, na.hu2};
+#pragma unroll
+  for (int c = 0; c < 3; ++c) {
+    if (na.hfield) {
+      const Pr f = ldp(na.hfield + c * ng + i);
+      h[c][0] = hu[c] + f[0];
+      h[c][1] = hu[c] + f[1];
+    } else {
+      h[c][0] = h[c][1] = hu[c];
+    }
   }
 }
 
@@ -164,36 +226,51 @@ __global__ __launch_bounds__(kRedThreads) void k_midpoint_diag(NodalArgs na, dou
                                                               const double* __restrict__ lv, long long ng,
                                                               double* __restrict__ partial) {
   double acc[5] = {0, 0, 0, 0, 0};
-  GRID_LOOP(i, ng) {
-    double h[3];
-    field_at(na, ng, i, h);
-    double a[3], vv[3], l0[3], l1[3], m1[3], mh[3], lmh[3];
+  PAIR_LOOP(i, ng) {
+    double hp[3][2];
+    field_pair(na, ng, i, hp);
+    Pr am[3], vm[3], l0m[3], lvm[3];
+#pragma unroll
     for (int c = 0; c < 3; ++c) {
-      a[c] = m0[c * ng + i];
-      vv[c] = v[c * ng + i];
-      l0[c] = lm0[c * ng + i];
-      const double lvc = lv[c * ng + i];
-      m1[c] = a[c] + k * vv[c];
-      mh[c] = a[c] + 0.5 * k * vv[c];
-      l1[c] = l0[c] + k * lvc;
-      lmh[c] = l0[c] + 0.5 * k * lvc;
+      am[c] = ldp(m0 + c * ng + i);
+      vm[c] = ldp(v + c * ng + i);
+      l0m[c] = ldp(lm0 + c * ng + i);
+      lvm[c] = ldp(lv + c * ng + i);
     }
-    const double rr = r[i];
-    const double cr[3] = {mh[1] * vv[2] - mh[2] * vv[1], mh[2] * vv[0] - mh[0] * vv[2], mh[0] * vv[1] - mh[1] * vv[0]};
-    double e0 = 0, e1 = 0, v2 = 0, rho = 0, mv = 0;
-    for (int c = 0; c < 3; ++c) {
-      e0 += 0.5 * cexc * a[c] * l0[c] - a[c] * h[c];
-      e1 += 0.5 * cexc * m1[c] * l1[c] - m1[c] * h[c];
-      v2 += vv[c] * vv[c];
-      const double rv = alpha * vv[c] + cr[c] + na.chat * lmh[c] + mh[c] * rr - na.hs * h[c];
-      rho += rv * vv[c];
-      mv += vv[c] * mh[c];
+    const Pr rp = ldp(r + i);
+#pragma unroll
+    for (int q = 0; q < 2; ++q) {
+      double a[3], vv[3], l0[3], l1[3], m1[3], mh[3], lmh[3], h[3];
+#pragma unroll
+      for (int c = 0; c < 3; ++c) {
+        a[c] = am[c][q];
+        vv[c] = vm[c][q];
+        l0[c] = l0m[c][q];
+        h[c] = hp[c][q];
+        m1[c] = a[c] + k * vv[c];
+        mh[c] = a[c] + 0.5 * k * vv[c];
+        l1[c] = l0[c] + k * lvm[c][q];
+        lmh[c] = l0[c] + 0.5 * k * lvm[c][q];
+      }
+      const double rr = rp[q];
+      const double cr[3] = {mh[1] * vv[2] - mh[2] * vv[1], mh[2] * vv[0] - mh[0] * vv[2],
+                            mh[0] * vv[1] - mh[1] * vv[0]};
+      double e0 = 0, e1 = 0, v2 = 0, rho = 0, mv = 0;
+#pragma unroll
+      for (int c = 0; c < 3; ++c) {
+        e0 += 0.5 * cexc * a[c] * l0[c] - a[c] * h[c];
+        e1 += 0.5 * cexc * m1[c] * l1[c] - m1[c] * h[c];
+        v2 += vv[c] * vv[c];
+        const double rv = alpha * vv[c] + cr[c] + na.chat * lmh[c] + mh[c] * rr - na.hs * h[c];
+        rho += rv * vv[c];
+        mv += vv[c] * mh[c];
+      }
+      acc[0] += e0;
+      acc[1] += e1;
+      acc[2] += v2;
+      acc[3] += rho;
+      acc[4] += mv * rr;
     }
-    acc[0] += e0;
-    acc[1] += e1;
-    acc[2] += v2;
-    acc[3] += rho;
-    acc[4] += mv * rr;
   }
   bstore<5, 0>(acc, partial);
 }
@@ -207,19 +284,37 @@ __global__ __launch_bounds__(kRedThreads) void k_adjoint_finish(NodalArgs na, co
                                                                double* __restrict__ hbar, long long ng,
                                                                double* __restrict__ partial) {
   double acc[3] = {0, 0, 0};
-  GRID_LOOP(i, ng) {
-    double vv[3], mv[3];
+  PAIR_LOOP(i, ng) {
+    Pr vp[3], mp[3], lp[3], gp[3];
+#pragma unroll
     for (int c = 0; c < 3; ++c) {
-      vv[c] = v[c * ng + i];
-      mv[c] = mu[c * ng + i];
+      vp[c] = ldp(v + c * ng + i);
+      mp[c] = ldp(mu + c * ng + i);
+      lp[c] = ldp(lmu + c * ng + i);
+      gp[c] = ldp(gbar + c * ng + i);
     }
-    const double mr = mu[3 * ng + i], rr = r[i];
-    const double cr[3] = {vv[1] * mv[2] - vv[2] * mv[1], vv[2] * mv[0] - vv[0] * mv[2], vv[0] * mv[1] - vv[1] * mv[0]};
+    const Pr mrp = ldp(mu + 3 * ng + i), rp = ldp(r + i);
+    double go[3][2], hb[3][2];
+#pragma unroll
+    for (int q = 0; q < 2; ++q) {
+      const double vv[3] = {vp[0][q], vp[1][q], vp[2][q]}, mv[3] = {mp[0][q], mp[1][q], mp[2][q]};
+      const double mr = mrp[q], rr = rp[q];
+      const double cr[3] = {vv[1] * mv[2] - vv[2] * mv[1], vv[2] * mv[0] - vv[0] * mv[2],
+                            vv[0] * mv[1] - vv[1] * mv[0]};
+#pragma unroll
+      for (int c = 0; c < 3; ++c) {
+        go[c][q] = gp[c][q] - (cr[c] + na.chat * lp[c][q] + rr * mv[c] - vv[c] * mr);
+        hb[c][q] = na.hs * mv[c];
+        acc[c] += hb[c][q];
+      }
+    }
+#pragma unroll
     for (int c = 0; c < 3; ++c) {
-      gbar[c * ng + i] -= cr[c] + na.chat * lmu[c * ng + i] + rr * mv[c] - vv[c] * mr;
-      const double hb = na.hs * mv[c];
-      if (hbar) hbar[c * ng + i] += hb;
-      acc[c] += hb;
+      stp(gbar + c * ng + i, go[c][0], go[c][1]);
+      if (hbar) {
+        const Pr o = ldp(hbar + c * ng + i);
+        stp(hbar + c * ng + i, o[0] + hb[c][0], o[1] + hb[c][1]);
+      }
     }
   }
   bstore<3, 0>(acc, partial);
