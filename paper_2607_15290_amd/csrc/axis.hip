@@ -8,7 +8,7 @@ namespace llg {
 
 template <typename T, int N>
 static hipError_t axis_n(const Ctx& c, int axis, int mode, const SymArgs& sym, cx<T>* spec, hipStream_t st) {
-  constexpr int W = axis_w(N), TPL = N / plan_p(axis_plan_key(int(sizeof(T)), N));
+  constexpr int W = axis_w(int(sizeof(T)), N), TPL = N / plan_p(axis_plan_key(int(sizeof(T)), N));
   const unsigned gx = (unsigned)((c.geom.cs + W - 1) / W);
   const unsigned gy = (unsigned)(axis == 1 ? c.nz : c.ny);
   const cx<T>* tw;

@@ -867,16 +867,29 @@ __global__ __launch_bounds__(192) void k_xmid(PipeIO<float, double, float> io, c
 // k_axis: DFTs along y (axis 1) or z (axis 2).  MODE 0 forward, 1 inverse,
 // 2 forward -> multiplier -> inverse.
 // ---------------------------------------------------------------------------
-// spectral columns per axis block; mixed-radix lengths up to 24 run one thread per line
-__host__ __device__ constexpr int axis_w(int n) {
-  return n <= 16 ? 64 : (n >= 512 ? 4 : ((n & (n - 1)) != 0 && n <= 24 ? 64 : 16));
+// Spectral columns per axis block (elements of elem_bytes bytes); mixed-radix
+// lengths up to 24 run one thread per line.  At N = 512 the LDS of a block
+// (N (W + 1) elements) limits W: float32 takes LLG_AXIS_W512_F32 columns,
+// float64 LLG_AXIS_W512_F64 (8 each: 64- and 128-byte row segments).  At
+// 512^3, float32 ran 4.37 solves/s with 8 columns, 4.35 with 16 and 3.49
+// with 4; float64 3.09 with 8 against 2.93 with 4 (512^2: 822 against 803).
+#ifndef LLG_AXIS_W512_F32
+#define LLG_AXIS_W512_F32 8
+#endif
+#ifndef LLG_AXIS_W512_F64
+#define LLG_AXIS_W512_F64 8
+#endif
+__host__ __device__ constexpr int axis_w(int elem_bytes, int n) {
+  return n <= 16 ? 64
+                 : (n >= 512 ? (elem_bytes == 4 ? LLG_AXIS_W512_F32 : LLG_AXIS_W512_F64)
+                             : ((n & (n - 1)) != 0 && n <= 24 ? 64 : 16));
 }
 
 template <typename T, int N, int MODE>
-__global__ __launch_bounds__(axis_w(N) * (N / plan_p(axis_plan_key(int(sizeof(T)), N)))) void k_axis(
+__global__ __launch_bounds__(axis_w(int(sizeof(T)), N) * (N / plan_p(axis_plan_key(int(sizeof(T)), N)))) void k_axis(
     cx<T>* __restrict__ spec, SpecGeom g, int axis, SymArgs sym, const cx<T>* __restrict__ tw) {
   constexpr int KEY = axis_plan_key(int(sizeof(T)), N);
-  constexpr int P = plan_p(KEY), TPL = N / P, W = axis_w(N);
+  constexpr int P = plan_p(KEY), TPL = N / P, W = axis_w(int(sizeof(T)), N);
   __shared__ cx<T> lds[N * (W + 1)];
   const int c = threadIdx.x % W, t = threadIdx.x / W;
   const int col = blockIdx.x * W + c;

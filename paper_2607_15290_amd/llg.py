@@ -141,12 +141,18 @@ class Context:
             pass
 
     def workspace(self, restart=30, prec="fp64"):
+        """The Krylov workspace for (restart, prec), one at a time: switching
+        frees the previous one and hands torch's cached blocks back to the
+        device first, so that two workspaces of a large grid (hundreds of GB
+        each) never need to coexist in the cache."""
         key = (int(restart), _PREC[prec])
         if key not in self._work:
             nbytes = self.lib.llg_workspace_bytes(self.handle, key[0], key[1])
             if nbytes == 0:
                 raise ValueError("bad workspace request")
-            self._work.clear()
+            if self._work:
+                self._work.clear()
+                torch.cuda.empty_cache()
             self._work[key] = torch.empty(nbytes, dtype=torch.uint8, device=self.device)
         return self._work[key]
 

@@ -67,8 +67,11 @@ def test_apply_and_matvec_match_dense(shape, theta):
     ctx.close()
 
 
+# 512-point y and z lines (8, 512, 4), (8, 4, 512), (8, 512, 1): the axis passes at 512 take 8
+# spectral columns per block, and 15 columns leave the second block partly empty
 SHAPES = [(16, 16, 1), (32, 64, 1), (128, 32, 1), (512, 8, 1), (16, 32, 8), (64, 16, 32), (32, 32, 32),
-          (8, 128, 16), (256, 8, 4), (256, 256, 8), (256, 8, 256), (8, 256, 256)]
+          (8, 128, 16), (256, 8, 4), (256, 256, 8), (256, 8, 256), (8, 256, 256), (8, 512, 4), (8, 4, 512),
+          (8, 512, 1)]
 
 
 @pytest.mark.parametrize("shape", SHAPES)
@@ -91,7 +94,7 @@ def test_operators_match_fft_oracle(shape):
 
 
 F32_SHAPES = [(16, 16, 1), (64, 32, 1), (32, 16, 16), (64, 64, 64), (256, 256, 8), (256, 8, 256), (8, 256, 256),
-              (256, 24, 20)]
+              (256, 24, 20), (8, 512, 4), (8, 4, 512), (8, 512, 1)]
 
 
 @pytest.mark.parametrize("shape", F32_SHAPES)
