@@ -271,44 +271,76 @@ __global__ __launch_bounds__(kDcgsThreads) void k_dcgs_dots(const double2* __res
   dcgs_block_store<J + 1>(acc, partial);
 }
 
-// Projection coefficients of pass 2, one wavefront.  With p = U_{j+1}^T w
-// (pass 1, on the device) and Minv = T^{-1} (columns 0..j-1 in minv from the
-// earlier steps, column j in cf):
+// Projection coefficients of pass 2.  With p = U_{j+1}^T w (pass 1, on the
+// device) and Minv = T^{-1} (columns 0..j-1 in minv from the earlier steps,
+// column j in cf):
 //   b = Q_j^T w = Minv_j^T p_{<j},   e_j = q_j.w = (p_j - a.b) / beta_j,
 //   Q_{j+1} [b; e_j] = U_{j+1} gamma,   gamma = Minv_{j+1} [b; e_j].
-// Also stores column j of Minv for the later steps.
-__global__ __launch_bounds__(64) void k_dcgs_coef(DcgsCoef cf, const double* __restrict__ p,
-                                                  double* __restrict__ minv, double* __restrict__ gamma) {
-  const int l = threadIdx.x, j = cf.j;
-  auto mi = [&](int r, int col) { return col == j ? cf.minv[r] : minv[col * kDcgsMaxCols + r]; };
-  double b = 0.0;
-  if (l < j)
-    for (int k = 0; k <= l; ++k) b = fma(mi(k, l), p[k], b);
-  const double ab = wave_sum(l < j ? cf.a[l] * b : 0.0);
-  const double e = (p[j] - ab) * cf.inv_beta;
+// The coefficient step inside a block: columns 0..j of Minv (column j from
+// cf) and p are staged in LDS with coalesced loads by the whole block, then
+// the first wavefront runs the two short triangular products from LDS (from
+// global memory each term of those loops would wait out a cache latency).
+// gs (LDS) receives gamma; with store, the block keeps column j of Minv for
+// the later steps.  Every thread of the block calls it.
+__device__ __forceinline__ void dcgs_coef_block(const DcgsCoef& cf, const double* __restrict__ p,
+                                                double* __restrict__ minv, bool store, double* gs) {
+  __shared__ double ms[kDcgsMaxCols * kDcgsMaxCols];  // column-major, columns 0..j
+  __shared__ double ps[kDcgsMaxCols];
   __shared__ double v[64];
-  v[l] = l < j ? b : (l == j ? e : 0.0);
+  const int l = threadIdx.x, j = cf.j;
+  for (int t = l; t < (j + 1) * kDcgsMaxCols; t += blockDim.x)
+    ms[t] = t < j * kDcgsMaxCols ? minv[t] : cf.minv[t - j * kDcgsMaxCols];
+  if (l <= j) ps[l] = p[l];
+  __syncthreads();
+  if (l < 64) {
+    double b = 0.0;
+    if (l < j)
+      for (int k = 0; k <= l; ++k) b = fma(ms[l * kDcgsMaxCols + k], ps[k], b);
+    const double ab = wave_sum(l < j ? cf.a[l] * b : 0.0);
+    const double e = (ps[j] - ab) * cf.inv_beta;
+    v[l] = l < j ? b : (l == j ? e : 0.0);
+  }
   __syncthreads();
   if (l <= j) {
     double g = 0.0;
-    for (int k = l; k <= j; ++k) g = fma(mi(l, k), v[k], g);
-    gamma[l] = g;
-    minv[j * kDcgsMaxCols + l] = cf.minv[l];
+    for (int k = l; k <= j; ++k) g = fma(ms[k * kDcgsMaxCols + l], v[k], g);
+    gs[l] = g;
+    if (store) minv[j * kDcgsMaxCols + l] = cf.minv[l];
   }
+  __syncthreads();
+}
+
+// Pass 2's coefficients as a kernel of their own (one block of one wavefront).
+__global__ __launch_bounds__(64) void k_dcgs_coef(DcgsCoef cf, const double* __restrict__ p,
+                                                  double* __restrict__ minv, double* __restrict__ gamma) {
+  __shared__ double gs[kDcgsMaxCols];
+  dcgs_coef_block(cf, p, minv, true, gs);
+  if (threadIdx.x <= cf.j) gamma[threadIdx.x] = gs[threadIdx.x];
 }
 
 // Pass 2: unew = (w - U gamma) / beta_j, and, for the next step,
-// out = [U_i.unew (i <= J), unew.unew], value-major partials.
-template <int J, typename W2>
+// out = [U_i.unew (i <= J), unew.unew], value-major partials.  With COEF the
+// pass forms gamma itself (dcgs_coef_block, from cf and the pass-1 products
+// p) instead of reading the coefficient kernel's output: on small grids that
+// saves a launch per step, where launches, not bytes, set the time.
+template <int J, typename W2, bool COEF>
 __global__ __launch_bounds__(kDcgsThreads) void k_dcgs_update(const double2* __restrict__ u0,
                                                             const double2* __restrict__ U1, long long ld2,
                                                             const double* __restrict__ gamma, double inv_beta,
                                                             const W2* __restrict__ w,
                                                             double2* __restrict__ unew, long long n2,
-                                                            double* __restrict__ partial) {
+                                                            double* __restrict__ partial, DcgsCoef cf,
+                                                            const double* __restrict__ p, double* __restrict__ minv) {
   double gm[J + 1];
+  if constexpr (COEF) {
+    __shared__ double gs[kDcgsMaxCols];
+    dcgs_coef_block(cf, p, minv, blockIdx.x == 0, gs);
 #pragma unroll
-  for (int i = 0; i <= J; ++i) gm[i] = gamma[i];
+    for (int i = 0; i <= J; ++i) gm[i] = gs[i];
+  } else {
+#pragma unroll
+    for (int i = 0; i <= J; ++i) gm[i] = gamma[i];
+  }
   double acc[J + 2];
 #pragma unroll
   for (int i = 0; i < J + 2; ++i) acc[i] = 0.0;
@@ -519,11 +551,19 @@ static void dd_t(const Ctx& c, const double* u0, const double* U1, long long ld,
 
 template <int J, typename TW>
 static void du_t(const Ctx& c, const double* u0, const double* U1, long long ld, const double* gamma,
-                 double inv_beta, const TW* w, double* unew, long long n, hipStream_t st) {
+                 const DcgsCoef& cf, const double* p, const TW* w, double* unew, long long n, hipStream_t st) {
   constexpr unsigned lds = std::is_same<TW, float>::value ? LLG_DCGS_UPDATE_LDS_F32W : LLG_DCGS_UPDATE_LDS;
-  hipLaunchKernelGGL((k_dcgs_update<J, pair_of<TW>>), dim3(red_blocks(n / 2)), dim3(kDcgsThreads), lds, st, reinterpret_cast<const double2*>(u0), reinterpret_cast<const double2*>(U1), ld / 2, gamma,
-                     inv_beta, reinterpret_cast<const pair_of<TW>*>(w), reinterpret_cast<double2*>(unew), n / 2,
-                     c.partial);
+  const dim3 grid(red_blocks(n / 2)), block(kDcgsThreads);
+  const double2* a0 = reinterpret_cast<const double2*>(u0);
+  const double2* a1 = reinterpret_cast<const double2*>(U1);
+  const pair_of<TW>* wp = reinterpret_cast<const pair_of<TW>*>(w);
+  double2* un = reinterpret_cast<double2*>(unew);
+  if (gamma)
+    hipLaunchKernelGGL((k_dcgs_update<J, pair_of<TW>, false>), grid, block, lds, st, a0, a1, ld / 2, gamma,
+                       cf.inv_beta, wp, un, n / 2, c.partial, cf, p, c.tri);
+  else
+    hipLaunchKernelGGL((k_dcgs_update<J, pair_of<TW>, true>), grid, block, lds, st, a0, a1, ld / 2, nullptr,
+                       cf.inv_beta, wp, un, n / 2, c.partial, cf, p, c.tri);
 }
 
 // Runtime J -> template instantiation J = 0..kDcgsMaxCols - 1.
@@ -580,13 +620,17 @@ template <typename TW>
 static hipError_t dcgs_update_t(const Ctx& c, const double* u0, const double* U1, long long ld, const DcgsCoef& cf,
                                 const double* p, const TW* w, double* unew, long long n, double* out,
                                 hipStream_t st) {
+  if (cf.j < 0 || cf.j >= kDcgsMaxCols) return hipErrorInvalidValue;
+  // small grids: the update pass forms gamma itself (one launch fewer)
   const double* gamma = nullptr;
-  hipError_t e = dcgs_coef(c, cf, p, &gamma, st);
-  if (e != hipSuccess) return e;
+  if (c.ng > kSpeculateMaxNodes) {
+    hipError_t e = dcgs_coef(c, cf, p, &gamma, st);
+    if (e != hipSuccess) return e;
+  }
   {
     // j + 1 directions read, w read, u_new written
     ProfScope ps(c.prof, st, KK_CGS_UPDATE_DOTS, double(n) * (8.0 * (cf.j + 2) + sizeof(TW)));
-    JDispatch<UpdF>::run(cf.j, c, u0, U1, ld, gamma, cf.inv_beta, w, unew, n, st);
+    JDispatch<UpdF>::run(cf.j, c, u0, U1, ld, gamma, cf, p, w, unew, n, st);
   }
   return reduce_partials_n(c, red_blocks(n / 2), cf.j + 2, out, st);
 }

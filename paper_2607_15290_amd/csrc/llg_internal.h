@@ -28,9 +28,11 @@ constexpr int kRedThreads = 256;
 constexpr int kMaxDots = 64;
 constexpr int kDcgsMaxCols = 32;  // delayed-CGS2 basis columns (restart <= 31)
 constexpr int kDotsSlots = 5;     // kMaxDots-sized slots of Ctx::dots (see Ctx)
-// Grids of at most this many nodes launch the next Arnoldi step's operator
-// before the host round trip of the current step (its work is short next to
-// the round trip, and it is discarded when the cycle ends).
+// Small grids, where an Arnoldi step's time is set by launches and round
+// trips rather than bytes: grids of at most this many nodes launch the next
+// step's operator before the host round trip of the current step (its work is
+// short next to the round trip, and it is discarded when the cycle ends), and
+// their update pass forms its own coefficients (one launch fewer per step).
 constexpr long long kSpeculateMaxNodes = 1 << 20;
 
 // Kernel kinds known to the event profiler.
