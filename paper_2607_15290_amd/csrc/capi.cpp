@@ -443,6 +443,14 @@ llg_status cycle_dcgs2(const Ctx& c, const ArnoldiOpT<TW>& op, bool op_dots, con
     out.k = 0;
     return LLG_OK;
   }
+  // Small grids whose updates never take the fused pass leave the operator's
+  // pass-1 block partials unreduced, in the upper half of the partial buffer
+  // (the update pass's own partials use the lower half), for the update pass
+  // to reduce: one launch fewer per step.
+  const bool speculate = c.ng <= kSpeculateMaxNodes;
+  const bool defer = speculate && op_dots && !(LLG_FUSE_UPDATE && fu && fu->ok(0));
+  double* const defer_part = c.partial + size_t(kRedBlocksMax) * kMaxDots / 2;
+  int defer_nb = 0;
   // Operator of step jj on u_jj into W, its pass-1 products into pslot.
   hipError_t op_err = hipSuccess;
   auto launch_op = [&](int jj, double* pslot, bool spec_ready) {
@@ -451,6 +459,10 @@ llg_status cycle_dcgs2(const Ctx& c, const ArnoldiOpT<TW>& op, bool op_dots, con
     if (op_dots) {
       BasisDots bq{u0, U1, n4, jj + 1, nullptr};
       bq.out = pslot;
+      if (defer) {
+        bq.defer = defer_part;
+        bq.defer_nb = &defer_nb;
+      }
       e = op(jj, ujj, W, &bq, spec_ready);
     } else {
       e = op(jj, ujj, W, nullptr, spec_ready);
@@ -458,7 +470,6 @@ llg_status cycle_dcgs2(const Ctx& c, const ArnoldiOpT<TW>& op, bool op_dots, con
     }
     if (e != hipSuccess && op_err == hipSuccess) op_err = e;
   };
-  const bool speculate = c.ng <= kSpeculateMaxNodes;
   bool ahead = false;  // step j's operator was launched during step j - 1
   bool ready = false;  // step j's first x pass ran with pass 2 of step j - 1
   for (int j = 0;; ++j) {
@@ -503,7 +514,14 @@ llg_status cycle_dcgs2(const Ctx& c, const ArnoldiOpT<TW>& op, bool op_dots, con
       CHK(dcgs_coef(c, cf, pslot, &ua.gamma, st));
       CHK(fu->run(ua, W, c.dots2));
     } else {
-      CHK(dcgs_update(c, u0, U1, n4, cf, pslot, W, U1 + size_t(j) * n4, n4, c.dots2, st));
+      DeferredDots dd;
+      if (defer && defer_nb > 0) {
+        dd.part = defer_part;
+        dd.nb = defer_nb;
+        dd.out = pslot;
+        dd.mirror = c.hmirror_dev + (pslot - c.dots);
+      }
+      CHK(dcgs_update(c, u0, U1, n4, cf, pslot, W, U1 + size_t(j) * n4, n4, c.dots2, st, &dd));
     }
     // one round trip: pass-1 dots p and the pass-2 dots of u_{j+1}, which their
     // reductions also wrote into the mapped host mirror.  On small grids the

@@ -26,14 +26,28 @@ hipError_t dcgs_dots(const Ctx& c, const double* u0, const double* U1, long long
                      long long n, double* out, hipStream_t st);
 hipError_t dcgs_dots(const Ctx& c, const double* u0, const double* U1, long long ld, int j, const float* w,
                      long long n, double* out, hipStream_t st);
+// Pass-1 products left unreduced by the operator's last pass (small grids,
+// BasisDots::defer): nb block partials per value at part, value-major.  The
+// update pass reduces them (the same fixed order in every block), uses them,
+// and stores the reduced values at out (device) and mirror (host-mapped).
+struct DeferredDots {
+  const double* part = nullptr;
+  int nb = 0;
+  double* out = nullptr;
+  double* mirror = nullptr;
+};
+
 // Pass 2 (p = pass-1 output on the device): with gamma = T_{j+1}^{-1} [b; e_j],
 // b = T_j^{-T} p_{<j}, e_j = (p_j - a.b) / beta_j (computed on the device),
 //   unew = (w - U gamma) / beta_j,   out = [U_i.unew (i <= j), unew.unew].
 // unew must not alias w or a basis column 0..j.
+// With dp (dp->nb > 0) p is not read: the pass-1 products come from dp.
 hipError_t dcgs_update(const Ctx& c, const double* u0, const double* U1, long long ld, const DcgsCoef& cf,
-                       const double* p, const double* w, double* unew, long long n, double* out, hipStream_t st);
+                       const double* p, const double* w, double* unew, long long n, double* out, hipStream_t st,
+                       const DeferredDots* dp = nullptr);
 hipError_t dcgs_update(const Ctx& c, const double* u0, const double* U1, long long ld, const DcgsCoef& cf,
-                       const double* p, const float* w, double* unew, long long n, double* out, hipStream_t st);
+                       const double* p, const float* w, double* unew, long long n, double* out, hipStream_t st,
+                       const DeferredDots* dp = nullptr);
 
 // The coefficient step of pass 2 alone (k_dcgs_coef): gamma (device, j + 1
 // values) for a pass 2 run elsewhere (k_xfwd_upd).

@@ -330,11 +330,30 @@ __global__ __launch_bounds__(kDcgsThreads) void k_dcgs_update(const double2* __r
                                                             const W2* __restrict__ w,
                                                             double2* __restrict__ unew, long long n2,
                                                             double* __restrict__ partial, DcgsCoef cf,
-                                                            const double* __restrict__ p, double* __restrict__ minv) {
+                                                            const double* __restrict__ p, double* __restrict__ minv,
+                                                            DeferredDots dp) {
   double gm[J + 1];
   if constexpr (COEF) {
     __shared__ double gs[kDcgsMaxCols];
-    dcgs_coef_block(cf, p, minv, blockIdx.x == 0, gs);
+    __shared__ double pr[kDcgsMaxCols];
+    const double* pp = p;
+    if (dp.nb > 0) {
+      // reduce the deferred pass-1 partials: value q by wavefront q mod 8
+      const int lane = threadIdx.x & 63, wv = threadIdx.x >> 6;
+      for (int q = wv; q <= cf.j; q += kDcgsThreads / 64) {
+        double t = 0.0;
+        for (int b = lane; b < dp.nb; b += 64) t += dp.part[(long long)q * dp.nb + b];
+        t = wave_sum(t);
+        if (lane == 0) pr[q] = t;
+      }
+      __syncthreads();
+      if (blockIdx.x == 0 && threadIdx.x <= cf.j) {
+        dp.out[threadIdx.x] = pr[threadIdx.x];
+        dp.mirror[threadIdx.x] = pr[threadIdx.x];
+      }
+      pp = pr;
+    }
+    dcgs_coef_block(cf, pp, minv, blockIdx.x == 0, gs);
 #pragma unroll
     for (int i = 0; i <= J; ++i) gm[i] = gs[i];
   } else {
@@ -551,7 +570,8 @@ static void dd_t(const Ctx& c, const double* u0, const double* U1, long long ld,
 
 template <int J, typename TW>
 static void du_t(const Ctx& c, const double* u0, const double* U1, long long ld, const double* gamma,
-                 const DcgsCoef& cf, const double* p, const TW* w, double* unew, long long n, hipStream_t st) {
+                 const DcgsCoef& cf, const double* p, const DeferredDots& dp, const TW* w, double* unew, long long n,
+                 hipStream_t st) {
   constexpr unsigned lds = std::is_same<TW, float>::value ? LLG_DCGS_UPDATE_LDS_F32W : LLG_DCGS_UPDATE_LDS;
   const dim3 grid(red_blocks(n / 2)), block(kDcgsThreads);
   const double2* a0 = reinterpret_cast<const double2*>(u0);
@@ -560,10 +580,10 @@ static void du_t(const Ctx& c, const double* u0, const double* U1, long long ld,
   double2* un = reinterpret_cast<double2*>(unew);
   if (gamma)
     hipLaunchKernelGGL((k_dcgs_update<J, pair_of<TW>, false>), grid, block, lds, st, a0, a1, ld / 2, gamma,
-                       cf.inv_beta, wp, un, n / 2, c.partial, cf, p, c.tri);
+                       cf.inv_beta, wp, un, n / 2, c.partial, cf, p, c.tri, dp);
   else
     hipLaunchKernelGGL((k_dcgs_update<J, pair_of<TW>, true>), grid, block, lds, st, a0, a1, ld / 2, nullptr,
-                       cf.inv_beta, wp, un, n / 2, c.partial, cf, p, c.tri);
+                       cf.inv_beta, wp, un, n / 2, c.partial, cf, p, c.tri, dp);
 }
 
 // Runtime J -> template instantiation J = 0..kDcgsMaxCols - 1.
@@ -619,28 +639,33 @@ hipError_t dcgs_coef(const Ctx& c, const DcgsCoef& cf, const double* p, const do
 template <typename TW>
 static hipError_t dcgs_update_t(const Ctx& c, const double* u0, const double* U1, long long ld, const DcgsCoef& cf,
                                 const double* p, const TW* w, double* unew, long long n, double* out,
-                                hipStream_t st) {
+                                hipStream_t st, const DeferredDots* dpp) {
   if (cf.j < 0 || cf.j >= kDcgsMaxCols) return hipErrorInvalidValue;
-  // small grids: the update pass forms gamma itself (one launch fewer)
+  const DeferredDots dp = dpp ? *dpp : DeferredDots{};
+  if (dp.nb > 0 && (!dp.part || !dp.out || !dp.mirror)) return hipErrorInvalidValue;
+  // small grids (and deferred pass-1 products): the update pass forms gamma
+  // itself (one launch fewer)
   const double* gamma = nullptr;
-  if (c.ng > kSpeculateMaxNodes) {
+  if (c.ng > kSpeculateMaxNodes && dp.nb == 0) {
     hipError_t e = dcgs_coef(c, cf, p, &gamma, st);
     if (e != hipSuccess) return e;
   }
   {
     // j + 1 directions read, w read, u_new written
     ProfScope ps(c.prof, st, KK_CGS_UPDATE_DOTS, double(n) * (8.0 * (cf.j + 2) + sizeof(TW)));
-    JDispatch<UpdF>::run(cf.j, c, u0, U1, ld, gamma, cf, p, w, unew, n, st);
+    JDispatch<UpdF>::run(cf.j, c, u0, U1, ld, gamma, cf, p, dp, w, unew, n, st);
   }
   return reduce_partials_n(c, red_blocks(n / 2), cf.j + 2, out, st);
 }
 hipError_t dcgs_update(const Ctx& c, const double* u0, const double* U1, long long ld, const DcgsCoef& cf,
-                       const double* p, const double* w, double* unew, long long n, double* out, hipStream_t st) {
-  return dcgs_update_t(c, u0, U1, ld, cf, p, w, unew, n, out, st);
+                       const double* p, const double* w, double* unew, long long n, double* out, hipStream_t st,
+                       const DeferredDots* dp) {
+  return dcgs_update_t(c, u0, U1, ld, cf, p, w, unew, n, out, st, dp);
 }
 hipError_t dcgs_update(const Ctx& c, const double* u0, const double* U1, long long ld, const DcgsCoef& cf,
-                       const double* p, const float* w, double* unew, long long n, double* out, hipStream_t st) {
-  return dcgs_update_t(c, u0, U1, ld, cf, p, w, unew, n, out, st);
+                       const double* p, const float* w, double* unew, long long n, double* out, hipStream_t st,
+                       const DeferredDots* dp) {
+  return dcgs_update_t(c, u0, U1, ld, cf, p, w, unew, n, out, st, dp);
 }
 
 hipError_t scale_invnorm(const Ctx& c, double* y, const double* x, const double* nrm2, long long n, hipStream_t st) {

@@ -156,7 +156,16 @@ struct BasisDots {
   int nv = 0;
   double* partial = nullptr;
   double* out = nullptr;  // when set, the reduced products go here instead of the caller's default
+  // Deferred reduction (small grids): when defer is set and the pass has at
+  // most kDeferMaxBlocks blocks, it leaves its block partials at defer
+  // (value-major) instead of reducing them and stores its block count at
+  // *defer_nb; otherwise it reduces as usual (products at out) and stores 0.
+  // The Arnoldi update pass reduces deferred partials.
+  double* defer = nullptr;
+  int* defer_nb = nullptr;
 };
+// Largest block count of a pass whose products are left for deferred reduction.
+constexpr int kDeferMaxBlocks = 64;
 
 // Delayed-CGS2 pass 2 of Arnoldi step j carried by the first x pass of the
 // operator of step j + 1 (k_xfwd_upd): with basis directions u_0 at u0 and

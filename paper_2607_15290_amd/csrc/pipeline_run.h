@@ -83,6 +83,7 @@ hipError_t launch_xinv_dots(const Ctx& c, const NodalArgs& na, const PipeIO<T, T
   if (bd.nv < 1 || bd.nv > kBasisDotsMax || io.rhs) return hipErrorInvalidValue;
   const long long lines = (long long)c.ny * c.nz;
   const unsigned grid = (unsigned)((lines + C::LX - 1) / C::LX);
+  if (bd.defer_nb) *bd.defer_nb = 0;
   if (grid > (unsigned)kRedBlocksMax) {
     // more blocks than partial rows (the largest grids in float64): plain
     // pass, then the separate inner-product pass over the output
@@ -93,8 +94,12 @@ hipError_t launch_xinv_dots(const Ctx& c, const NodalArgs& na, const PipeIO<T, T
   }
   const cx<T>* tw;
   if constexpr (std::is_same<T, double>::value) tw = c.tw_d[0]; else tw = c.tw_f[0];
+  // defer only over few blocks: every block of the update pass sums all of
+  // them (at 64 blocks one launch fewer per step gained 4%; at 256 the sums
+  // cost more than the launch)
+  const bool defer = bd.defer && grid <= unsigned(kDeferMaxBlocks);
   BasisDots kd = bd;
-  kd.partial = c.partial;
+  kd.partial = defer ? bd.defer : c.partial;
   {
     const double node_b = xinv_node_bytes<T, TIn, TOut, EPI>(na, io) + 4.0 * 8 * bd.nv;
     ProfScope ps(c.prof, st, KK_XINV_DOTS, double(c.ng) * node_b + double(c.geom.cs) * lines * 2 * sizeof(T));
@@ -102,6 +107,10 @@ hipError_t launch_xinv_dots(const Ctx& c, const NodalArgs& na, const PipeIO<T, T
                        reinterpret_cast<const cx<T>*>(c.spec), c.geom, na, tw, kd);
     hipError_t e = hipGetLastError();
     if (e != hipSuccess) return e;
+  }
+  if (defer) {
+    *bd.defer_nb = int(grid);
+    return hipSuccess;
   }
   return reduce_partials_n(c, int(grid), bd.nv, dots_out, st);
 }
