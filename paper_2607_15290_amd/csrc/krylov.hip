@@ -216,6 +216,8 @@ __global__ __launch_bounds__(kRedThreads) void k_update_norm(const double* __res
 // elements' loads per thread, whose extra streams in flight lower the DRAM
 // efficiency).
 constexpr int kDcgsThreads = 512;
+// The update pass of vectors of at most this many 16-byte pairs runs as one block.
+constexpr long long kDcgsSingleMaxN2 = 4 * kDcgsThreads;
 // Unused dynamic LDS of the update pass caps the blocks per CU.  With a
 // float64 operator output w it caps the pass at two 512-thread blocks per CU
 // (16 waves): fewer concurrent vector streams keep the DRAM pages of the
@@ -230,8 +232,11 @@ constexpr int kDcgsThreads = 512;
 #define LLG_DCGS_UPDATE_LDS_F32W 40960
 #endif
 
+// With mirror (single-block launches only) the block's sums are the final
+// values and are also written to the host-mapped mirror.
 template <int NV>
-__device__ __forceinline__ void dcgs_block_store(const double (&acc)[NV], double* __restrict__ partial) {
+__device__ __forceinline__ void dcgs_block_store(const double (&acc)[NV], double* __restrict__ partial,
+                                                 double* __restrict__ mirror = nullptr) {
   __shared__ double sm[kDcgsThreads / 64][NV];
   const int lane = threadIdx.x & 63, wv = threadIdx.x >> 6;
 #pragma unroll
@@ -245,6 +250,7 @@ __device__ __forceinline__ void dcgs_block_store(const double (&acc)[NV], double
 #pragma unroll
     for (int k = 1; k < kDcgsThreads / 64; ++k) t += sm[k][threadIdx.x];
     partial[(long long)threadIdx.x * gridDim.x + blockIdx.x] = t;
+    if (mirror) mirror[threadIdx.x] = t;
   }
 }
 
@@ -331,7 +337,7 @@ __global__ __launch_bounds__(kDcgsThreads) void k_dcgs_update(const double2* __r
                                                             double2* __restrict__ unew, long long n2,
                                                             double* __restrict__ partial, DcgsCoef cf,
                                                             const double* __restrict__ p, double* __restrict__ minv,
-                                                            DeferredDots dp) {
+                                                            DeferredDots dp, double* __restrict__ mirror) {
   double gm[J + 1];
   if constexpr (COEF) {
     __shared__ double gs[kDcgsMaxCols];
@@ -381,7 +387,7 @@ __global__ __launch_bounds__(kDcgsThreads) void k_dcgs_update(const double2* __r
     for (int i = 0; i <= J; ++i) acc[i] = fma(q[i].x, un.x, fma(q[i].y, un.y, acc[i]));
     acc[J + 1] = fma(un.x, un.x, fma(un.y, un.y, acc[J + 1]));
   }
-  dcgs_block_store<J + 2>(acc, partial);
+  dcgs_block_store<J + 2>(acc, partial, mirror);
 }
 
 // ---- simple vector kernels -------------------------------------------------
@@ -571,19 +577,19 @@ static void dd_t(const Ctx& c, const double* u0, const double* U1, long long ld,
 template <int J, typename TW>
 static void du_t(const Ctx& c, const double* u0, const double* U1, long long ld, const double* gamma,
                  const DcgsCoef& cf, const double* p, const DeferredDots& dp, const TW* w, double* unew, long long n,
-                 hipStream_t st) {
+                 double* part, double* mirror, hipStream_t st) {
   constexpr unsigned lds = std::is_same<TW, float>::value ? LLG_DCGS_UPDATE_LDS_F32W : LLG_DCGS_UPDATE_LDS;
-  const dim3 grid(red_blocks(n / 2)), block(kDcgsThreads);
+  const dim3 grid(mirror ? 1 : red_blocks(n / 2)), block(kDcgsThreads);
   const double2* a0 = reinterpret_cast<const double2*>(u0);
   const double2* a1 = reinterpret_cast<const double2*>(U1);
   const pair_of<TW>* wp = reinterpret_cast<const pair_of<TW>*>(w);
   double2* un = reinterpret_cast<double2*>(unew);
   if (gamma)
     hipLaunchKernelGGL((k_dcgs_update<J, pair_of<TW>, false>), grid, block, lds, st, a0, a1, ld / 2, gamma,
-                       cf.inv_beta, wp, un, n / 2, c.partial, cf, p, c.tri, dp);
+                       cf.inv_beta, wp, un, n / 2, part, cf, p, c.tri, dp, mirror);
   else
     hipLaunchKernelGGL((k_dcgs_update<J, pair_of<TW>, true>), grid, block, lds, st, a0, a1, ld / 2, nullptr,
-                       cf.inv_beta, wp, un, n / 2, c.partial, cf, p, c.tri, dp);
+                       cf.inv_beta, wp, un, n / 2, part, cf, p, c.tri, dp, mirror);
 }
 
 // Runtime J -> template instantiation J = 0..kDcgsMaxCols - 1.
@@ -650,11 +656,17 @@ static hipError_t dcgs_update_t(const Ctx& c, const double* u0, const double* U1
     hipError_t e = dcgs_coef(c, cf, p, &gamma, st);
     if (e != hipSuccess) return e;
   }
+  // Vectors of at most kDcgsSingleMaxN2 pairs: one block (grid-strided)
+  // whose sums are the final products, written to out and, for a mirrored
+  // slot, to its host mirror: no reduction launch.
+  const bool single = n / 2 <= kDcgsSingleMaxN2 && out >= c.dots && out < c.dots + kDotsSlots * kMaxDots;
   {
     // j + 1 directions read, w read, u_new written
     ProfScope ps(c.prof, st, KK_CGS_UPDATE_DOTS, double(n) * (8.0 * (cf.j + 2) + sizeof(TW)));
-    JDispatch<UpdF>::run(cf.j, c, u0, U1, ld, gamma, cf, p, dp, w, unew, n, st);
+    JDispatch<UpdF>::run(cf.j, c, u0, U1, ld, gamma, cf, p, dp, w, unew, n, single ? out : c.partial,
+                         single ? c.hmirror_dev + (out - c.dots) : nullptr, st);
   }
+  if (single) return hipGetLastError();
   return reduce_partials_n(c, red_blocks(n / 2), cf.j + 2, out, st);
 }
 hipError_t dcgs_update(const Ctx& c, const double* u0, const double* U1, long long ld, const DcgsCoef& cf,
