@@ -520,6 +520,11 @@ __global__ __launch_bounds__(192) void k_xfwd(const TIn* __restrict__ in, const 
 // W: float (the precision form's float32 operator output, converted exactly)
 // or double.
 // ---------------------------------------------------------------------------
+// Items per trip of k_xfwd_upd with at most 4 directions (2 with up to 8).
+// At 256^3 4 is fastest: 2, 3 and 6 made the pass 0.5-0.8% slower.
+#ifndef LLG_UPD_NB_SMALL
+#define LLG_UPD_NB_SMALL 4
+#endif
 template <typename T, typename W, int NH, int PRO, int JB>
 __global__ __launch_bounds__(192) void k_xfwd_upd(UpdFirst ua, const W* __restrict__ w, const T* __restrict__ m,
                                                   cx<T>* __restrict__ spec, SpecGeom g, NodalArgs na,
@@ -545,7 +550,7 @@ __global__ __launch_bounds__(192) void k_xfwd_upd(UpdFirst ua, const W* __restri
   // NB items per trip: all their loads are issued before any store (the
   // stores could alias them as far as the compiler knows), which keeps
   // NB (j + 2) loads of each wave in flight
-  constexpr int NB = JB <= 3 ? 4 : 2;
+  constexpr int NB = JB <= 3 ? LLG_UPD_NB_SMALL : 2;
   static_assert(JB <= 7, "more directions than a batch of items keeps in registers");
   constexpr int NITEM = 4 * NPAIR;
 #pragma unroll 1
