@@ -49,6 +49,11 @@ __device__ __forceinline__ int xphys(int pos) { return pos + (pos >> 4); }
 #ifndef LLG_XBATCH_F64
 #define LLG_XBATCH_F64 3
 #endif
+// the same for the precision form's junction pass k_xmid (256^3: 191 us with
+// 6, 200 with 3, 204 with 4)
+#ifndef LLG_XMID_BATCH
+#define LLG_XMID_BATCH LLG_XBATCH_F32
+#endif
 template <typename U>
 __device__ __forceinline__ U ld_s(const U* p) {
 #if LLG_PIPE_NT
@@ -822,7 +827,7 @@ __global__ __launch_bounds__(192) void k_xmid(PipeIO<float, double, float> io, c
 
   constexpr int NPAIR = C::LX * NH;
   constexpr int ITERS = (NPAIR + C::NT - 1) / C::NT;
-  constexpr int BATCH = LLG_XBATCH_F32;
+  constexpr int BATCH = LLG_XMID_BATCH;
 #pragma unroll
   for (int it0 = 0; it0 < ITERS; it0 += BATCH) {
     EpiRaw<T, double, T, EPI_APPLY> raw[BATCH];
@@ -884,10 +889,16 @@ __global__ __launch_bounds__(192) void k_xmid(PipeIO<float, double, float> io, c
 #ifndef LLG_AXIS_W512_F64
 #define LLG_AXIS_W512_F64 8
 #endif
+// float32 passes along 256-point lines: 16 columns (8 made them 30% slower,
+// 32 made the fused pass 35% slower)
+#ifndef LLG_AXIS_W256_F32
+#define LLG_AXIS_W256_F32 16
+#endif
 __host__ __device__ constexpr int axis_w(int elem_bytes, int n) {
   return n <= 16 ? 64
                  : (n >= 512 ? (elem_bytes == 4 ? LLG_AXIS_W512_F32 : LLG_AXIS_W512_F64)
-                             : ((n & (n - 1)) != 0 && n <= 24 ? 64 : 16));
+                             : (n == 256 && elem_bytes == 4 ? LLG_AXIS_W256_F32
+                                                             : ((n & (n - 1)) != 0 && n <= 24 ? 64 : 16)));
 }
 
 template <typename T, int N, int MODE>
