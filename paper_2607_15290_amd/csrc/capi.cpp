@@ -524,7 +524,8 @@ llg_status cycle_dcgs2(const Ctx& c, const ArnoldiOpT<TW>& op, bool op_dots, con
       CHK(dcgs_update(c, u0, U1, n4, cf, pslot, W, U1 + size_t(j) * n4, n4, c.dots2, st, &dd));
     }
     // one round trip: pass-1 dots p and the pass-2 dots of u_{j+1}, which their
-    // reductions also wrote into the mapped host mirror.  On small grids the
+    // reductions (on small grids the update pass itself) also wrote into the
+    // mapped host mirror.  On small grids the
     // next step's operator (on u_{j+1}, which no host decision changes) is
     // queued first, and the host waits only for this step's passes; when the
     // cycle then ends, that work is discarded.
