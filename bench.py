@@ -160,17 +160,50 @@ def dominant_kind(prof):
     return max(cands.items(), key=lambda kv: kv[1]["total_ms"])[0]
 
 
-def roofline_of(prof, footprint_bytes, traffic_kernel=None):
+_COPY_GBS = None
+
+
+def copy_ceiling():
+    """A reference streaming rate for context: torch's device copy of 1 GiB
+    (read + write bytes over the median of 10 timed copies after one
+    warm-up), measured once per run.  It is not the fastest copy this GPU
+    can run (a hand-written copy with non-temporal hints reaches more)."""
+    global _COPY_GBS
+    if _COPY_GBS is None:
+        import torch
+        a = torch.ones(1 << 27, dtype=torch.float64, device="cuda:0")
+        b = torch.empty_like(a)
+        b.copy_(a)
+        ts = []
+        for _ in range(10):
+            e0, e1 = torch.cuda.Event(enable_timing=True), torch.cuda.Event(enable_timing=True)
+            e0.record()
+            b.copy_(a)
+            e1.record()
+            e1.synchronize()
+            ts.append(e0.elapsed_time(e1) * 1e-3)
+        ts.sort()
+        _COPY_GBS = 2 * a.numel() * 8 / ts[len(ts) // 2] / 1e9
+        del a, b
+    return _COPY_GBS
+
+
+def roofline_of(prof, footprint_bytes, grid, traffic_kernel=None):
     dom_name = dominant_kind(prof)
     dom = prof[dom_name]
     achieved = dom["bytes"] / (dom["total_ms"] * 1e-3) / 1e9
     bpl = dom["bytes"] / dom["launches"]
-    traffic = measured_traffic(dom_name, bpl) if traffic_kernel is None or traffic_kernel == dom_name else None
+    traffic = (measured_traffic(dom_name, bpl, grid)
+               if traffic_kernel is None or traffic_kernel == dom_name else None)
     r = dict(bound="hbm", achieved=round(achieved, 1), peak=HBM_PEAK_GBS, unit="GB/s",
              frac=round(achieved / HBM_PEAK_GBS, 4),
              traffic=round(traffic) if traffic is not None else None, traffic_unit="HBM bytes per launch",
              kernel=dom_name, avg_launch_us=round(1e3 * dom["total_ms"] / dom["launches"], 2),
              launches=dom["launches"], bytes_per_launch=round(bpl))
+    # context, not the peak: the same kernel against torch's device copy
+    cgbs = copy_ceiling()
+    r["torch_copy_GBs"] = round(cgbs, 1)
+    r["frac_of_torch_copy"] = round(achieved / cgbs, 4)
     if footprint_bytes < INFINITY_CACHE_BYTES:
         r["note"] = (f"working set {footprint_bytes / 2**20:.3g} MiB fits the 256 MiB Infinity Cache: the rate "
                      f"is cache/latency bound, not an HBM figure; quote applies/s and solves/s")
@@ -183,18 +216,21 @@ def kernel_table(prof_all):
             for k, v in sorted(prof_all.items(), key=lambda kv: -kv[1]["total_ms"])}
 
 
-def measured_traffic(kernel_kind, bytes_per_launch):
+def measured_traffic(kernel_kind, bytes_per_launch, grid):
     """HBM bytes per launch of ``kernel_kind`` from the committed hardware-counter
     summary (profiles/traffic_3d256_midpoint.md), scaled to this run's
     algorithmic bytes per launch; None when the summary has no entry for the
-    kernel or the kernel source changed since the counters were taken."""
+    kernel on this grid (a ratio measured on one grid says nothing about
+    another, least of all one whose working set stays in the Infinity Cache)
+    or the kernel source changed since the counters were taken."""
     import hashlib
     path = os.path.join(ROOT, "profiles", "traffic_3d256_midpoint.md")
     if not os.path.exists(path):
         return None
     for line in open(path):
         parts = line.split()
-        if len(parts) == 5 and parts[0] == "bench-traffic:" and parts[1] == kernel_kind:
+        if (len(parts) == 6 and parts[0] == "bench-traffic:" and parts[1] == kernel_kind
+                and parts[5] == "x".join(str(int(v)) for v in grid)):
             src = os.path.join(ROOT, "paper_2607_15290_amd", "csrc", parts[3])
             if not os.path.exists(src):
                 return None
@@ -501,6 +537,10 @@ def footprint(spec, prec):
     return ng * 4 * 8 * 4
 
 
+def grid_of(spec):
+    return (spec["nx"], spec["ny"], spec["nz"])
+
+
 def run_headline(args, P, W, torch):
     steps = args.steps or 5
     log("generating workload 4 (3D midpoint)")
@@ -569,7 +609,7 @@ def run_headline(args, P, W, torch):
         "paper_protocol": {"fp32_ir": pp32, "fp64": pp64},
         "precond_comparison": comparison,
         "ops": ops,
-        "roofline": roofline_of(prof, footprint(spec, "fp32_ir")),
+        "roofline": roofline_of(prof, footprint(spec, "fp32_ir"), grid_of(spec)),
         "kernels": kernel_table(prof_all),
     })
     if not args.no_cpu_baseline:
@@ -623,7 +663,8 @@ def run_solver_workload(args, P, W, torch, wid):
     line.update({p: s for p, s in summ.items()})
     if "fp64" in summ and head != "fp64":
         line["fp32_ir_over_fp64"] = summ[head]["solves_per_s"] / summ["fp64"]["solves_per_s"]
-    line.update({"paper_protocol": pp, "ops": ops, "roofline": roofline_of(prof, footprint(spec, head)),
+    line.update({"paper_protocol": pp, "ops": ops,
+                 "roofline": roofline_of(prof, footprint(spec, head), grid_of(spec)),
                  "kernels": kernel_table(prof_all)})
     if not args.no_cpu_baseline:
         log("CPU oracle baseline (first system at full size)")
@@ -711,7 +752,8 @@ def run_adjoint_workload(args, P, W, torch):
                          "adjoint_rtol": 1e-10, "ckpt_every": spec["ckpt_every"], "parallelism": "1 GPU"})
     line.update({"forward_s": times["fwd"], "backward_s": times["bwd"], "loss": loss, "adjoint_step": adj,
                  "grad_norms": {"m0": gm, "h_field": ghf, "h_uniform": ghu}, "ops": ops,
-                 "roofline": roofline_of(prof, footprint(spec, "fp64")), "kernels": kernel_table(prof_all)})
+                 "roofline": roofline_of(prof, footprint(spec, "fp64"), grid_of(spec)),
+                 "kernels": kernel_table(prof_all)})
     if not args.no_cpu_baseline:
         log("CPU oracle baseline (one forward and one adjoint step at full size)")
         line["cpu_baseline"] = cpu_adjoint_baseline(spec, args.cpu_protocol)

@@ -73,3 +73,20 @@ def test_profiled_passes_time_and_profile_only_the_k_steps(no_device):
 def test_more_than_one_gpu_is_refused():
     p = subprocess.run([sys.executable, "bench.py", "--gpus", "2"], capture_output=True, text=True, timeout=120)
     assert p.returncode != 0 and "one GPU" in (p.stdout + p.stderr)
+
+
+def test_counter_traffic_is_reported_only_on_its_own_grid(monkeypatch):
+    """The committed counter ratio belongs to the grid it was measured on: the
+    roofline carries a traffic figure there and None on any other grid."""
+    prof = {"xfwd_upd": dict(launches=2, total_ms=1.0, bytes=2e9),
+            "axis_fwd": dict(launches=4, total_ms=0.5, bytes=1e9)}
+    big = 256 ** 3 * 128
+    assert bench.measured_traffic("xfwd_upd", 1e9, (256, 256, 256)) is not None
+    for grid in ((128, 128, 128), (256, 256, 1), (512, 512, 512)):
+        assert bench.measured_traffic("xfwd_upd", 1e9, grid) is None, grid
+    assert bench.measured_traffic("no_such_kind", 1e9, (256, 256, 256)) is None
+    monkeypatch.setattr(bench, "_COPY_GBS", 5000.0)  # the context copy needs a GPU
+    r = bench.roofline_of(prof, big, (256, 256, 256))
+    assert r["kernel"] == "xfwd_upd" and r["traffic"] is not None
+    assert abs(r["traffic"] / r["bytes_per_launch"] - 1.0) < 0.05
+    assert bench.roofline_of(prof, big, (128, 128, 128))["traffic"] is None
