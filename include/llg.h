@@ -146,8 +146,8 @@ typedef struct {
 
 /* Create a context for an nx x ny x nz grid (nz = 1: 2-D) with spacing h in
  * every direction (cell lengths n h; Sec. 2.3) on device `device`.
- * Grid sizes: ny and nz (or nz = 1) in [4, 512] and nx / 2 in [2, 256], each
- * of the form 2^a, 3 * 2^a or 5 * 2^a (nx even).  Allocates the twiddle
+ * Grid sizes: ny and nz (or nz = 1) even, in [4, 512], and nx / 2 in [2, 256],
+ * each of the form 2^a, 3 * 2^a or 5 * 2^a (nx even).  Allocates the twiddle
  * tables, the spectral scratch (about 48 N_g bytes) and reduction buffers.
  * Errors: LLG_EARG (null out, unsupported n, bad h), LLG_ENOMEM, LLG_EHIP. */
 llg_status llg_ctx_create(llg_ctx** out, int nx, int ny, int nz, double h, int device);

@@ -1074,7 +1074,7 @@ llg_status llg_ctx_create_cell(llg_ctx** out, int nx, int ny, int nz, double lx,
   if (nx % 2 != 0 || !nh_supported(nx / 2) || !axis_supported(ny) || !(nz == 1 || axis_supported(nz)))
     return fail(LLG_EARG,
                 "unsupported grid: nx must be 2 n with n in {2..256} of the form 2^a, 3*2^a or 5*2^a; ny and "
-                "nz (or nz = 1) in [4, 512] of the form 2^a, 3*2^a or 5*2^a");
+                "nz (or nz = 1) even, in [4, 512], of the form 2^a, 3*2^a or 5*2^a");
   if (!is_fin(lx) || lx <= 0 || !is_fin(ly) || ly <= 0 || !is_fin(lz) || lz <= 0)
     return fail(LLG_EARG, "cell lengths must be finite and > 0");
   if (device < 0) return fail(LLG_EARG, "device must be >= 0");

@@ -29,6 +29,10 @@ CASES = [
     (24, 10, 6, 13.3),   # half-length 12 (radices 4, 3), 60 lines
     (40, 6, 4, 13.3),    # half-length 20 (radices 4, 5), 24 lines
     (64, 64, 1, 400.0),  # stiff: full cycles, fused and separate updates mixed
+    # 256-point x lines, the instantiations of the 256^3 runs (half-length
+    # 128: 8 lines per float32 block, 4 per float64 block)
+    (256, 6, 6, 13.3),   # 36 lines (radix 3 along y and z): the last float32 block half dead
+    (256, 10, 1, 400.0),  # stiff, 10 lines: full cycles; the last block of either precision partly dead
 ]
 
 
@@ -70,22 +74,13 @@ def test_fused_update_solves_match_oracle(nx, ny, nz, mult):
     ctx.close()
 
 
-@pytest.mark.parametrize("n", [32, 48])
-def test_fused_update_adjoint_matches_oracle(n):
-    """The right-preconditioned adjoint solve (prologue M2^{-T}) with the
-    fused update, against the oracle's right-preconditioned adjoint."""
-    announce(f"fused update adjoint {n}^2")
-    spec = W.make(5, n=n)
-    kw = dict(alpha=spec["alpha"], cexc=1.0, dt=spec["dt"], theta=0.5, shift=spec["shift"])
-    g = Grid(n, n, 1, h=spec["h"])
-    op = OP(h_uniform=spec["h_uniform"], **kw)
-    m_n = spec["m0"]
+def _adjoint_case(g, op, prm, ctx, m_n):
+    """One adjoint step solved with the fused update forced on and off,
+    against the oracle's right-preconditioned adjoint."""
     m1, v, r, _ = steppers.midpoint_step(g, op, m_n, rtol=1e-14, picard_tol=1e-13, picard_max=100)
     gbar = np.zeros_like(m1)
     gbar[2] = 2 * m1[2]
     gb_ref, hf_ref, _, _, info = adjoint.step_adjoint(g, op, m_n, v, r, gbar, rtol=1e-12, side="right")
-    ctx = P.Context(n, n, 1, spec["h"], 0)
-    prm = P.Params(h_uniform=spec["h_uniform"], **kw)
     iters = {}
     for fuse in ("always", "never"):
         gb = dev(gbar)
@@ -98,4 +93,27 @@ def test_fused_update_adjoint_matches_oracle(n):
         assert_elem(host(hbf), hf_ref, 1e-9, f"hbar_field ({fuse})")
     print(f"  adjoint iters fused {iters['always']} unfused {iters['never']} oracle {info['iters']}", flush=True)
     assert abs(iters["always"] - info["iters"]) <= 1 and abs(iters["always"] - iters["never"]) <= 1
+
+
+@pytest.mark.parametrize("n", [32, 48])
+def test_fused_update_adjoint_matches_oracle(n):
+    """The right-preconditioned adjoint solve (prologue M2^{-T}) with the
+    fused update, against the oracle's right-preconditioned adjoint."""
+    announce(f"fused update adjoint {n}^2")
+    spec = W.make(5, n=n)
+    kw = dict(alpha=spec["alpha"], cexc=1.0, dt=spec["dt"], theta=0.5, shift=spec["shift"])
+    g = Grid(n, n, 1, h=spec["h"])
+    op = OP(h_uniform=spec["h_uniform"], **kw)
+    ctx = P.Context(n, n, 1, spec["h"], 0)
+    _adjoint_case(g, op, P.Params(h_uniform=spec["h_uniform"], **kw), ctx, spec["m0"])
+    ctx.close()
+
+
+def test_fused_update_adjoint_256_point_lines():
+    """The adjoint's float64 fused pass on 256-point x lines (4 lines per
+    block): 10 lines, so the last block is half dead."""
+    announce("fused update adjoint 256x10")
+    g, prm, op, m, _ = _system(256, 10, 1, 13.3)
+    ctx = P.Context(256, 10, 1, 1.0 / 256, 0)
+    _adjoint_case(g, op, prm, ctx, m)
     ctx.close()
