@@ -7,9 +7,11 @@ the right-preconditioned adjoint's one pipeline -- is run with the fused
 update on small grids chosen for their x-pass blocks: a block covering more
 lines than the grid has (a ragged, partly dead block), mixed-radix lines, and
 a stiff system whose cycles run to 30 columns (steps past the eighth switch
-to the separate update pass within the cycle).  Solutions are compared
-element-wise with the oracle's solvers, iteration counts with the oracle's
-and with the unfused path's."""
+to the separate update pass within the cycle); 256-point x lines (the
+instantiations of the 256^3 runs); and one 3D grid above 2^20 nodes, where
+no operator is launched ahead of the host's decision on the cycle.
+Solutions are compared element-wise with the oracle's solvers, iteration
+counts with the oracle's and with the unfused path's."""
 
 import numpy as np
 import pytest
@@ -33,6 +35,10 @@ CASES = [
     # 128: 8 lines per float32 block, 4 per float64 block)
     (256, 6, 6, 13.3),   # 36 lines (radix 3 along y and z): the last float32 block half dead
     (256, 10, 1, 400.0),  # stiff, 10 lines: full cycles; the last block of either precision partly dead
+    # above 2^20 nodes, where the next operator is not launched ahead of the
+    # host's decision: the cycle waits for each step (1.3M nodes; the
+    # oracle's three solves take up to a minute)
+    pytest.param(256, 80, 64, 13.3, marks=pytest.mark.timeout(600)),
 ]
 
 
