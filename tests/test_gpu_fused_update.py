@@ -35,6 +35,8 @@ CASES = [
     # 128: 8 lines per float32 block, 4 per float64 block)
     (256, 6, 6, 13.3),   # 36 lines (radix 3 along y and z): the last float32 block half dead
     (256, 10, 1, 400.0),  # stiff, 10 lines: full cycles; the last block of either precision partly dead
+    (512, 10, 1, 13.3),  # 512-point x lines (the 512^3 capacity run's instantiations): 4 lines per
+                         # float32 block, the last one half dead
     # above 2^20 nodes, where the next operator is not launched ahead of the
     # host's decision: the cycle waits for each step (1.3M nodes; the
     # oracle's three solves take up to a minute)
@@ -115,11 +117,12 @@ def test_fused_update_adjoint_matches_oracle(n):
     ctx.close()
 
 
-def test_fused_update_adjoint_256_point_lines():
-    """The adjoint's float64 fused pass on 256-point x lines (4 lines per
-    block): 10 lines, so the last block is half dead."""
-    announce("fused update adjoint 256x10")
-    g, prm, op, m, _ = _system(256, 10, 1, 13.3)
-    ctx = P.Context(256, 10, 1, 1.0 / 256, 0)
+@pytest.mark.parametrize("nx", [256, 512])
+def test_fused_update_adjoint_long_lines(nx):
+    """The adjoint's float64 fused pass on 256- and 512-point x lines (4 and
+    2 lines per block): 10 lines, so at 256 the last block is half dead."""
+    announce(f"fused update adjoint {nx}x10")
+    g, prm, op, m, _ = _system(nx, 10, 1, 13.3)
+    ctx = P.Context(nx, 10, 1, 1.0 / nx, 0)
     _adjoint_case(g, op, prm, ctx, m)
     ctx.close()
