@@ -3,8 +3,9 @@ FFT-HSS apply (plain and transposed) and the fused preconditioned operators
 M^{-1} A, in float64 and float32, against the FP64 oracle -- the dense
 assembled matrices on tiny grids and the FFT tier on grids that span several
 tiles with ragged column tiles, including 256-point lines along x, y and z
-(the line lengths of the 256^3 workload's kernels).  Every comparison is
-element-wise: max |gpu - ref| <= tol * max |ref|."""
+(the line lengths of the 256^3 workload's kernels) and 512-point lines along
+x, y and z (the 512^3 capacity run's).  Every comparison is element-wise:
+max |gpu - ref| <= tol * max |ref|."""
 
 import math
 
@@ -94,7 +95,7 @@ def test_operators_match_fft_oracle(shape):
 
 
 F32_SHAPES = [(16, 16, 1), (64, 32, 1), (32, 16, 16), (64, 64, 64), (256, 256, 8), (256, 8, 256), (8, 256, 256),
-              (256, 24, 20), (8, 512, 4), (8, 4, 512), (8, 512, 1)]
+              (256, 24, 20), (8, 512, 4), (8, 4, 512), (8, 512, 1), (512, 8, 4), (512, 10, 1)]
 
 
 @pytest.mark.parametrize("shape", F32_SHAPES)
@@ -124,7 +125,8 @@ def _workload_params(nx, ny, nz):
     return dict(alpha=0.02, cexc=1.0, dt=dt, theta=0.5, shift=0.5, h_uniform=(0.0, 0.0, 1.0))
 
 
-PRECOND_SHAPES = [(16, 16, 1), (32, 16, 16), (48, 40, 24), (256, 256, 8), (256, 8, 256), (256, 256, 1)]
+PRECOND_SHAPES = [(16, 16, 1), (32, 16, 16), (48, 40, 24), (256, 256, 8), (256, 8, 256), (256, 256, 1),
+                  (512, 8, 4), (512, 10, 1)]
 
 
 @pytest.mark.parametrize("shape", PRECOND_SHAPES)
