@@ -908,8 +908,24 @@ __global__ __launch_bounds__(axis_w(int(sizeof(T)), N) * (N / plan_p(axis_plan_k
   constexpr int P = plan_p(KEY), TPL = N / P, W = axis_w(int(sizeof(T)), N);
   __shared__ cx<T> lds[N * (W + 1)];
   const int c = threadIdx.x % W, t = threadIdx.x / W;
-  const int col = blockIdx.x * W + c;
-  const int outer = blockIdx.y;
+  // Row segments shorter than a 128-byte cache line (float32 at N = 512: 8
+  // columns, 64 bytes) share each line with the next column group.  Blocks
+  // are dispatched to the 8 XCDs (each with its own L2) round-robin by linear
+  // id, so neighbouring groups would each fetch the whole line; renumbered so
+  // that every XCD runs one contiguous range of groups, the second half of a
+  // line is an L2 hit.  The renumbering is a bijection of the grid.
+  int col, outer;
+  if constexpr (W * sizeof(cx<T>) < 128) {
+    constexpr unsigned kXcd = 8;
+    const unsigned nb = gridDim.x * gridDim.y, lin = blockIdx.x + gridDim.x * blockIdx.y;
+    const unsigned xcd = lin % kXcd, k = lin / kXcd, per = nb / kXcd, rem = nb % kXcd;
+    const unsigned logical = xcd < rem ? xcd * (per + 1) + k : rem * (per + 1) + (xcd - rem) * per + k;
+    col = (logical % gridDim.x) * W + c;
+    outer = logical / gridDim.x;
+  } else {
+    col = blockIdx.x * W + c;
+    outer = blockIdx.y;
+  }
   long long sp, so;
   if (axis == 1) {
     sp = g.rs;

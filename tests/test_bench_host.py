@@ -2,6 +2,7 @@
 before the clock and the profiler start, exactly K steps are timed and
 counted, and a request for more than one GPU is refused."""
 
+import hashlib
 import subprocess
 import sys
 import time
@@ -75,18 +76,28 @@ def test_more_than_one_gpu_is_refused():
     assert p.returncode != 0 and "one GPU" in (p.stdout + p.stderr)
 
 
-def test_counter_traffic_is_reported_only_on_its_own_grid(monkeypatch):
-    """The committed counter ratio belongs to the grid it was measured on: the
-    roofline carries a traffic figure there and None on any other grid."""
-    prof = {"xfwd_upd": dict(launches=2, total_ms=1.0, bytes=2e9),
-            "axis_fwd": dict(launches=4, total_ms=0.5, bytes=1e9)}
-    big = 256 ** 3 * 128
-    assert bench.measured_traffic("xfwd_upd", 1e9, (256, 256, 256)) is not None
+def test_counter_traffic_is_reported_only_on_its_own_grid(monkeypatch, tmp_path):
+    """A committed counter ratio belongs to the grid and the kernel source it
+    was measured with: the roofline carries a traffic figure there and None on
+    any other grid or once the source has changed."""
+    src = tmp_path / "paper_2607_15290_amd" / "csrc"
+    src.mkdir(parents=True)
+    (src / "k.h").write_text("kernel source")
+    h = hashlib.sha256(b"kernel source").hexdigest()[:16]
+    (tmp_path / "profiles").mkdir()
+    (tmp_path / "profiles" / "traffic_3d256_midpoint.md").write_text(
+        f"bench-traffic: xfwd_upd 1.0028 k.h {h} 256x256x256\n")
+    monkeypatch.setattr(bench, "ROOT", str(tmp_path))
+    monkeypatch.setattr(bench, "_COPY_GBS", 5000.0)  # the context copy needs a GPU
+    assert bench.measured_traffic("xfwd_upd", 1e9, (256, 256, 256)) == pytest.approx(1.0028e9)
     for grid in ((128, 128, 128), (256, 256, 1), (512, 512, 512)):
         assert bench.measured_traffic("xfwd_upd", 1e9, grid) is None, grid
     assert bench.measured_traffic("no_such_kind", 1e9, (256, 256, 256)) is None
-    monkeypatch.setattr(bench, "_COPY_GBS", 5000.0)  # the context copy needs a GPU
+    prof = {"xfwd_upd": dict(launches=2, total_ms=1.0, bytes=2e9),
+            "axis_fwd": dict(launches=4, total_ms=0.5, bytes=1e9)}
+    big = 256 ** 3 * 128
     r = bench.roofline_of(prof, big, (256, 256, 256))
-    assert r["kernel"] == "xfwd_upd" and r["traffic"] is not None
-    assert abs(r["traffic"] / r["bytes_per_launch"] - 1.0) < 0.05
+    assert r["kernel"] == "xfwd_upd" and r["traffic"] == round(1.0028e9)
     assert bench.roofline_of(prof, big, (128, 128, 128))["traffic"] is None
+    (src / "k.h").write_text("kernel source, edited")
+    assert bench.measured_traffic("xfwd_upd", 1e9, (256, 256, 256)) is None
