@@ -908,14 +908,20 @@ __global__ __launch_bounds__(axis_w(int(sizeof(T)), N) * (N / plan_p(axis_plan_k
   constexpr int P = plan_p(KEY), TPL = N / P, W = axis_w(int(sizeof(T)), N);
   __shared__ cx<T> lds[N * (W + 1)];
   const int c = threadIdx.x % W, t = threadIdx.x / W;
-  // Row segments shorter than a 128-byte cache line (float32 at N = 512: 8
-  // columns, 64 bytes) share each line with the next column group.  Blocks
-  // are dispatched to the 8 XCDs (each with its own L2) round-robin by linear
-  // id, so neighbouring groups would each fetch the whole line; renumbered so
-  // that every XCD runs one contiguous range of groups, the second half of a
-  // line is an L2 hit.  The renumbering is a bijection of the grid.
+  // XCD-aware block numbering.  Blocks are dispatched to the 8 XCDs (each
+  // with its own L2) round-robin by linear id; renumbered, every XCD runs one
+  // contiguous range of (column group, outer) blocks instead.
+  //  * Along y the outer index is the z plane, so each XCD then streams its
+  //    own contiguous slab of the spectrum (256^3: y passes 4-5% faster in
+  //    float32, up to 14% in float64).
+  //  * Row segments shorter than a 128-byte line (float32 at N = 512: 8
+  //    columns, 64 bytes) share each line with the next column group, whose
+  //    half is then an L2 hit (512^3: all three passes 2-5% faster).
+  // Along z with whole-line segments it gains nothing (each block spans every
+  // z plane anyway), and those passes keep the plain numbering.  The
+  // renumbering is a bijection of the grid.
   int col, outer;
-  if constexpr (W * sizeof(cx<T>) < 128) {
+  if (W * sizeof(cx<T>) < 128 || axis == 1) {
     constexpr unsigned kXcd = 8;
     const unsigned nb = gridDim.x * gridDim.y, lin = blockIdx.x + gridDim.x * blockIdx.y;
     const unsigned xcd = lin % kXcd, k = lin / kXcd, per = nb / kXcd, rem = nb % kXcd;
